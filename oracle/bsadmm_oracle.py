@@ -1,0 +1,391 @@
+"""FP64 CPU oracle for block-splitting ADMM over random Fourier features.
+
+TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import or run this module.  It is a plain, slow,
+obviously-correct restatement of what the paper (Sindhwani & Avron,
+"High-performance Kernel Machines with Implicit Distributed Optimization and
+Randomization") computes, in float64, and shares no code with the HIP path.
+
+Everything is float64.  Inputs arrive as float32 arrays (the canonical inputs)
+and are upcast exactly, so only arithmetic differs from the GPU path.
+
+Readings of the paper taken here (each is listed with its reason in the
+design notes of the repository):
+
+* Feature map: z(x) = sqrt(2/s) cos(W^T x + b), W ~ N(0, 1/sigma^2),
+  b ~ U[0, 2 pi) (section "Randomized Kernel Maps"; the printed 1/sqrt(s)
+  scaling would estimate k/2, not k).  Column block j of Z is the column
+  slice of one s-feature map, which equals the block construction of that
+  section when the blocks are drawn independently.
+* Split rule: block i of n items is [floor(i n / R), floor((i+1) n / R)).
+* Loss weight: ADMM is run on n F(W) = sum_r V + n lambda r(W), i.e. the loss
+  prox has weight tau = 1/rho and the regulariser prox weight
+  kappa = n lambda / rho.  This is the paper's literal update (loss scaled by
+  1/n inside l_i, prox of l_i/rho) with rho replaced by rho/n; scaled duals
+  and the minimiser are unchanged.  ``rho_convention="literal"`` gives the
+  printed scaling.
+* Algorithm 1, step 17 gets the term Z_ij^T nu_i that the graph-projection
+  equation for W_ij contains (otherwise nu never reaches W).
+* The dual updates of mu and mu' use the freshly averaged W-bar, as in the
+  block-splitting update equations (Algorithm 1 places them before the
+  average; ``variant="literal_g1"`` reproduces that order as a diagnostic).
+* The returned model is W-bar; predictions are Z(X_test) W-bar.
+* Multiclass hinge is one-vs-all: sum_k max(0, 1 - y_k o_k), y in {-1, +1}.
+* Squared loss is ||y - o||^2 without a 1/2 and r(W) = ||W||_F^2.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg as sla
+
+__all__ = [
+    "partition", "rff", "rff_block", "gaussian_kernel",
+    "prox_squared", "prox_hinge", "prox_l2", "prox_loss", "loss_sum",
+    "objective", "ridge_closed_form", "ridge_push_through",
+    "graph_projection", "Problem", "weights", "admm", "admm_reference",
+    "paper_memory_floats", "predict",
+]
+
+
+# ---------------------------------------------------------------------------
+# Partition (section on block splitting: X, Y split into R row blocks, W into
+# C row blocks; the paper leaves uneven splits open)
+# ---------------------------------------------------------------------------
+
+def partition(n: int, parts: int):
+    """Contiguous blocks [floor(i n / parts), floor((i+1) n / parts))."""
+    return [(i * n // parts, (i + 1) * n // parts) for i in range(parts)]
+
+
+# ---------------------------------------------------------------------------
+# Random Fourier features (section "Randomized Kernel Maps")
+# ---------------------------------------------------------------------------
+
+def rff(X, W, b, s=None):
+    """Z = sqrt(2/s) cos(X W + b) in float64; X n x d, W d x s, b length s."""
+    X = np.asarray(X, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    s = W.shape[1] if s is None else s
+    return math.sqrt(2.0 / s) * np.cos(X @ W + b[None, :])
+
+
+def rff_block(X, W, b, rows, cols, s):
+    """The transform T[X_i, j]: rows (r0, r1) of X, feature columns (c0, c1)."""
+    r0, r1 = rows
+    c0, c1 = cols
+    return rff(X[r0:r1], W[:, c0:c1], b[c0:c1], s)
+
+
+def gaussian_kernel(X1, X2, sigma):
+    """k(x, x') = exp(-||x - x'||^2 / (2 sigma^2)) in float64."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    X2 = np.asarray(X2, dtype=np.float64)
+    d2 = (X1 * X1).sum(1)[:, None] + (X2 * X2).sum(1)[None, :] - 2.0 * X1 @ X2.T
+    return np.exp(-np.maximum(d2, 0.0) / (2.0 * sigma * sigma))
+
+
+# ---------------------------------------------------------------------------
+# Proximal operators (definition of prox; closed forms for the modular losses)
+# prox_{t f}(v) = argmin_o 1/2 ||o - v||^2 + t f(o)
+# ---------------------------------------------------------------------------
+
+def prox_squared(v, y, tau):
+    """f(o) = ||y - o||^2:  o = (v + 2 tau y) / (1 + 2 tau)."""
+    return (v + 2.0 * tau * y) / (1.0 + 2.0 * tau)
+
+
+def prox_hinge(v, y, tau):
+    """f(o) = max(0, 1 - y o), y in {-1, +1}, elementwise.
+
+    If the margin y v is at least 1 the point is untouched; if it is below
+    1 - tau the full step tau y is taken; in between o lands on y (margin 1).
+    """
+    u = y * v
+    return v + y * np.clip(1.0 - u, 0.0, tau)
+
+
+def prox_l2(v, kappa):
+    """f(W) = ||W||_F^2:  w = v / (1 + 2 kappa)."""
+    return v / (1.0 + 2.0 * kappa)
+
+
+def prox_loss(kind, v, y, tau):
+    if kind == "squared":
+        return prox_squared(v, y, tau)
+    if kind in ("hinge", "mc_hinge"):
+        return prox_hinge(v, y, tau)
+    raise ValueError(kind)
+
+
+def loss_sum(kind, Y, O):
+    """sum over rows (and outputs) of V(y_r, o_r)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    if kind == "squared":
+        return float(((Y - O) ** 2).sum())
+    if kind in ("hinge", "mc_hinge"):
+        return float(np.maximum(0.0, 1.0 - Y * O).sum())
+    raise ValueError(kind)
+
+
+def objective(kind, Z, Y, Wmodel, lam):
+    """F(W) = (1/n) sum_r V(y_r, W^T z_r) + lam ||W||_F^2 (linearised problem)."""
+    n = Z.shape[0]
+    return loss_sum(kind, Y, Z @ Wmodel) / n + lam * float((Wmodel * Wmodel).sum())
+
+
+# ---------------------------------------------------------------------------
+# Closed-form ridge on the feature matrix (squared loss, l2 regulariser):
+# gradient of (1/n)||Z W - Y||^2 + lam ||W||^2 vanishes at
+# (Z^T Z + n lam I) W = Z^T Y.
+# ---------------------------------------------------------------------------
+
+def ridge_closed_form(Z, Y, lam):
+    n, s = Z.shape
+    G = Z.T @ Z + n * lam * np.eye(s)
+    return sla.cho_solve(sla.cho_factor(G, lower=True), Z.T @ np.asarray(Y, np.float64))
+
+
+def ridge_push_through(Z, Y, lam):
+    """Same minimiser through the n x n system: W = Z^T (Z Z^T + n lam I)^{-1} Y."""
+    n = Z.shape[0]
+    K = Z @ Z.T + n * lam * np.eye(n)
+    alpha = sla.cho_solve(sla.cho_factor(K, lower=True), np.asarray(Y, np.float64))
+    return Z.T @ alpha
+
+
+# ---------------------------------------------------------------------------
+# Graph projection (definition of the graph projection operator over
+# matrices): argmin 1/2||V - c||^2 + 1/2||U - e||^2 s.t. V = A U, solved by
+# U = (A^T A + I)^{-1} (e + A^T c), V = A U.
+# ---------------------------------------------------------------------------
+
+def graph_projection(A, c, e, factor=None):
+    """Returns (U, V) for the projection of (c, e) onto {V = A U}."""
+    if factor is None:
+        factor = sla.cho_factor(A.T @ A + np.eye(A.shape[1]), lower=True)
+    U = sla.cho_solve(factor, e + A.T @ c)
+    return U, A @ U
+
+
+# ---------------------------------------------------------------------------
+# Problem description and prox weights
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Problem:
+    X: np.ndarray          # n x d (float32 canonical input)
+    Y: np.ndarray          # n x m
+    W: np.ndarray          # d x s feature-map directions
+    b: np.ndarray          # s feature-map offsets
+    R: int
+    C: int
+    lam: float
+    rho: float
+    loss: str              # squared | hinge | mc_hinge
+    rho_convention: str = "per_example"
+
+    @property
+    def n(self):
+        return self.X.shape[0]
+
+    @property
+    def s(self):
+        return self.W.shape[1]
+
+    @property
+    def m(self):
+        return self.Y.shape[1]
+
+
+def weights(p: Problem):
+    """(tau, kappa): weights of the loss prox and the regulariser prox."""
+    if p.rho_convention == "per_example":
+        return 1.0 / p.rho, p.n * p.lam / p.rho
+    if p.rho_convention == "literal":
+        return 1.0 / (p.n * p.rho), p.lam / p.rho
+    raise ValueError(p.rho_convention)
+
+
+def _blocks(p: Problem):
+    return partition(p.n, p.R), partition(p.s, p.C)
+
+
+def _zero_state(p: Problem):
+    n, s, m, R = p.n, p.s, p.m, p.R
+    z = lambda *sh: np.zeros(sh, dtype=np.float64)
+    return {
+        "O": z(n, m), "Obar": z(n, m), "nu": z(n, m), "Dbar": z(n, m),
+        "Wc": z(s, m), "Wbar": z(s, m), "mu": z(s, m),
+        "Wp": z(R, s, m), "mup": z(R, s, m), "U": z(R, s, m),
+    }
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 (BlockADMM), memory-efficient reorganised form
+# ---------------------------------------------------------------------------
+
+class _BlockCache:
+    """Per-block feature matrices and Cholesky factors of I + Z_ij^T Z_ij.
+
+    The factor is built the first time a block is visited (the cache set up
+    in the first iteration).  With ``regenerate`` the block Z_ij is rebuilt
+    from X on every visit, as the method prescribes; otherwise it is kept.
+    """
+
+    def __init__(self, p: Problem, regenerate: bool):
+        self.p = p
+        self.rows, self.cols = _blocks(p)
+        self.regenerate = regenerate
+        self.Z = {}
+        self.factor = {}
+
+    def Zblock(self, i, j):
+        if not self.regenerate and (i, j) in self.Z:
+            return self.Z[(i, j)]
+        Z = rff_block(self.p.X, self.p.W, self.p.b, self.rows[i], self.cols[j], self.p.s)
+        if not self.regenerate:
+            self.Z[(i, j)] = Z
+        return Z
+
+    def chol(self, i, j, Z):
+        if (i, j) not in self.factor:
+            self.factor[(i, j)] = sla.cho_factor(Z.T @ Z + np.eye(Z.shape[1]), lower=True)
+        return self.factor[(i, j)]
+
+
+def admm(p: Problem, iters: int, state=None, variant: str = "fixed",
+         regenerate: bool = False, cache: _BlockCache | None = None, callback=None):
+    """Run ``iters`` iterations of the reorganised block-splitting ADMM.
+
+    Returns (state, cache).  ``state`` holds O, Obar, nu, Dbar (n x m), the
+    regulariser-prox output Wc, the consensus W-bar, mu (s x m) and the
+    per-row-block W' (local models), mu' and U (R x s x m).
+    """
+    tau, kappa = weights(p)
+    st = _zero_state(p) if state is None else {k: v.copy() for k, v in state.items()}
+    cache = cache or _BlockCache(p, regenerate)
+    rows, cols = cache.rows, cache.cols
+    C, R = p.C, p.R
+    Y = np.asarray(p.Y, dtype=np.float64)
+    for it in range(iters):
+        # step 4: loss prox on the row state
+        O = prox_loss(p.loss, st["Obar"] - st["nu"], Y, tau)
+        # step 6: regulariser prox on the consensus model
+        Wc = prox_l2(st["Wbar"] - st["mu"], kappa)
+        # steps 11-12
+        Delta = O.copy()
+        Obar = (C / (C + 1.0)) * O
+        Wp = np.empty_like(st["Wp"])
+        U = np.empty_like(st["U"])
+        for i, (r0, r1) in enumerate(rows):
+            Dbar_i = st["Dbar"][r0:r1]
+            nu_i = st["nu"][r0:r1]
+            for j, (c0, c1) in enumerate(cols):
+                Z = cache.Zblock(i, j)                       # step 15
+                L = cache.chol(i, j, Z)                      # step 16
+                A = Z.T @ (Dbar_i / (C + 1.0) + nu_i)        # step 17 (+ Z^T nu)
+                rhs = st["Wbar"][c0:c1] - st["mup"][i, c0:c1] + st["U"][i, c0:c1] + A
+                Wp[i, c0:c1] = sla.cho_solve(L, rhs)         # step 18
+                Op = Z @ Wp[i, c0:c1]                        # step 19
+                Delta[r0:r1] -= Op                           # step 20
+                U[i, c0:c1] = Z.T @ Op                       # step 21
+                Obar[r0:r1] += Op / (C + 1.0)                # step 22
+        # step 25
+        Dbar = Delta
+        # steps 27-29: consensus average over the R local models
+        Wbar_new = (Wc + Wp.sum(axis=0)) / (R + 1.0)
+        if variant == "fixed":
+            mu = st["mu"] + Wc - Wbar_new
+            mup = st["mup"] + Wp - Wbar_new[None]
+        elif variant == "literal_g1":
+            mu = st["mu"] + Wc - st["Wbar"]
+            mup = st["mup"] + Wp - st["Wbar"][None]
+        else:
+            raise ValueError(variant)
+        # step 33
+        nu = st["nu"] + O - Obar
+        st = {"O": O, "Obar": Obar, "nu": nu, "Dbar": Dbar, "Wc": Wc, "Wbar": Wbar_new,
+              "mu": mu, "Wp": Wp, "mup": mup, "U": U}
+        if callback is not None:
+            callback(it + 1, st)
+    return st, cache
+
+
+# ---------------------------------------------------------------------------
+# The printed block-splitting update equations (Parikh-Boyd form with
+# nu_ij = -nu_i and W-bar_ij = W-bar_j eliminated): it keeps every O_ij and
+# O-bar_ij.  Written independently of ``admm`` to cross-check it.
+# ---------------------------------------------------------------------------
+
+def admm_reference(p: Problem, iters: int, callback=None):
+    tau, kappa = weights(p)
+    rows, cols = _blocks(p)
+    R, C, m = p.R, p.C, p.m
+    Y = np.asarray(p.Y, dtype=np.float64)
+    Zb = {(i, j): rff_block(p.X, p.W, p.b, rows[i], cols[j], p.s)
+          for i in range(R) for j in range(C)}
+    Qf = {k: sla.cho_factor(Z.T @ Z + np.eye(Z.shape[1]), lower=True) for k, Z in Zb.items()}
+    ni = [r1 - r0 for r0, r1 in rows]
+    sj = [c1 - c0 for c0, c1 in cols]
+    Oi = [np.zeros((ni[i], m)) for i in range(R)]
+    Obar_i = [np.zeros((ni[i], m)) for i in range(R)]
+    nu = [np.zeros((ni[i], m)) for i in range(R)]
+    Oij = {(i, j): np.zeros((ni[i], m)) for i in range(R) for j in range(C)}
+    Obar_ij = {(i, j): np.zeros((ni[i], m)) for i in range(R) for j in range(C)}
+    Wj = [np.zeros((sj[j], m)) for j in range(C)]
+    Wbar = [np.zeros((sj[j], m)) for j in range(C)]
+    mu = [np.zeros((sj[j], m)) for j in range(C)]
+    Wij = {(i, j): np.zeros((sj[j], m)) for i in range(R) for j in range(C)}
+    mu_ij = {(i, j): np.zeros((sj[j], m)) for i in range(R) for j in range(C)}
+    for it in range(iters):
+        Oi = [prox_loss(p.loss, Obar_i[i] - nu[i], Y[rows[i][0]:rows[i][1]], tau)
+              for i in range(R)]
+        Wj = [prox_l2(Wbar[j] - mu[j], kappa) for j in range(C)]
+        newW, newO = {}, {}
+        for (i, j), Z in Zb.items():
+            Wn, On = graph_projection(Z, Obar_ij[(i, j)] + nu[i], Wbar[j] - mu_ij[(i, j)],
+                                      factor=Qf[(i, j)])
+            newW[(i, j)], newO[(i, j)] = Wn, On
+        Wij, Oij = newW, newO
+        Wbar = [(Wj[j] + sum(Wij[(i, j)] for i in range(R))) / (R + 1.0) for j in range(C)]
+        for i in range(R):
+            gap = Oi[i] - sum(Oij[(i, j)] for j in range(C))
+            for j in range(C):
+                Obar_ij[(i, j)] = Oij[(i, j)] + gap / (C + 1.0)
+            Obar_i[i] = sum(Obar_ij[(i, j)] for j in range(C))
+        mu = [mu[j] + Wj[j] - Wbar[j] for j in range(C)]
+        mu_ij = {(i, j): mu_ij[(i, j)] + Wij[(i, j)] - Wbar[j] for (i, j) in Wij}
+        nu = [nu[i] + Oi[i] - Obar_i[i] for i in range(R)]
+        if callback is not None:
+            callback(it + 1, {
+                "O": np.concatenate(Oi), "Obar": np.concatenate(Obar_i),
+                "nu": np.concatenate(nu), "Wc": np.concatenate(Wj),
+                "Wbar": np.concatenate(Wbar), "mu": np.concatenate(mu),
+                "Wp": np.stack([np.concatenate([Wij[(i, j)] for j in range(C)])
+                                for i in range(R)]),
+                "mup": np.stack([np.concatenate([mu_ij[(i, j)] for j in range(C)])
+                                 for i in range(R)]),
+            })
+    return {"Wbar": np.concatenate(Wbar), "O": np.concatenate(Oi),
+            "Obar": np.concatenate(Obar_i), "nu": np.concatenate(nu)}
+
+
+def predict(Xt, W, b, Wbar, s=None):
+    """Scores Z(Xt) W-bar (n_t x m); the class is the lowest-index argmax."""
+    return rff(Xt, W, b, s) @ Wbar
+
+
+# ---------------------------------------------------------------------------
+# Memory model of the paper (paragraph "Memory Requirements", eq. mem):
+# floating point numbers per node.
+# ---------------------------------------------------------------------------
+
+def paper_memory_floats(n, s, C, d, m, N, R, t):
+    return (4 * n * m / N + 5 * s * m * R / N + n * d / N + n * m / N
+            + t * n * s / (C * N) + t * s * m * R / (C * N) + n * m * t / N
+            + n * m / N + s * s * R / (C * N))
