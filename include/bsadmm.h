@@ -1,0 +1,249 @@
+/*
+ * bsadmm.h -- C ABI of the MI355X block-splitting ADMM solver over random
+ * Fourier features.
+ *
+ * The method is the one of Sindhwani & Avron, "High-performance Kernel
+ * Machines with Implicit Distributed Optimization and Randomization"
+ * (arXiv 1409.0940): the regularised risk problem (eq. basicproblem) is
+ * linearised with random Fourier features (eq. problem_linear, section
+ * "Randomized Kernel Maps") and solved with the block-splitting ADMM of
+ * Algorithm 1 (BlockADMM) over an R x C grid of blocks of the feature matrix
+ * Z, which is regenerated from X instead of being kept between iterations.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status (bsadmm_status).  Nothing throws
+ *   across the ABI.  On a non-OK status a message is available from
+ *   bsadmm_last_error() (thread-local, valid until the next call on the
+ *   same thread).  BSADMM_EINVAL leaves every output and handle untouched.
+ * - Pointers named "device" are HIP device pointers on the current device;
+ *   pointers named "host" are ordinary host memory.  All matrices are dense
+ *   row-major with the leading dimension equal to the column count.
+ * - "stream" is a hipStream_t passed as void*; NULL means the default stream.
+ *   Work is enqueued on it asynchronously unless a function says it
+ *   synchronises.
+ * - The caller owns every buffer it passes.  The library owns every buffer
+ *   it allocates and releases all of them in bsadmm_destroy.
+ * - Block split rule (the paper leaves uneven splits open): row block i of
+ *   n rows is [floor(i n / R), floor((i+1) n / R)), feature block j of s
+ *   features is [floor(j s / C), floor((j+1) s / C)).
+ */
+#ifndef BSADMM_H
+#define BSADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define BSADMM_API __attribute__((visibility("default")))
+#else
+#define BSADMM_API
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef enum {
+  BSADMM_OK = 0,
+  BSADMM_EINVAL = 1,     /* invalid argument (sizes, enums, pointers, values)   */
+  BSADMM_ENOMEM = 2,     /* footprint above hbm_budget_bytes, or hipMalloc failed */
+  BSADMM_EDEVICE = 3,    /* a HIP runtime call or kernel launch failed           */
+  BSADMM_ENOTPD = 4,     /* a Cholesky pivot of I + Z_ij^T Z_ij was not positive */
+  BSADMM_ENONFINITE = 5, /* NaN or Inf in X, Y, W or b                           */
+  BSADMM_ESTATE = 6,     /* handle poisoned by an earlier EDEVICE / ENOTPD       */
+  BSADMM_ENOTIMPL = 7    /* combination not implemented                          */
+} bsadmm_status;
+
+/* ------------------------------------------------------------- precision */
+/* Arithmetic of the feature regeneration and of the Z products.  The ADMM
+ * state, the Cholesky factorisation and the cached inverse are always FP64.
+ *   FP64: phase X W + b, cos and products in FP64 (FP64 MFMA).
+ *   FP32: FP32 MFMA with FP32 accumulation, phase and cos in FP32.
+ *   BF16: X, W, Z and the product right-hand sides rounded to BF16 (round to
+ *         nearest even), FP32 accumulation; b is added to the FP32 phase.   */
+enum { BSADMM_FP64 = 0, BSADMM_FP32 = 1, BSADMM_BF16 = 2 };
+
+/* ------------------------------------------------------------------ loss */
+/* V(y, o) of eq. basicproblem, entering only through its prox (paragraph
+ * "Modularity").
+ *   SQUARED : ||y - o||^2 (no 1/2), any m.
+ *   HINGE   : max(0, 1 - y o), m = 1, y in {-1, +1}.
+ *   MC_HINGE: one-vs-all sum_k max(0, 1 - y_k o_k), y in {-1, +1}^m.      */
+enum { BSADMM_SQUARED = 0, BSADMM_HINGE = 1, BSADMM_MC_HINGE = 2 };
+
+/* ----------------------------------------------------------- regulariser */
+/* r(W) = ||W||_F^2, separable over feature blocks (l2 case of the block
+ * reformulation, eq. prob2).                                               */
+enum { BSADMM_L2 = 0 };
+
+/* ------------------------------------------------------------ Z handling */
+/* STORE: each iteration regenerates the blocks Z_ij of a group of row
+ *        blocks once into a library workspace and both products of the
+ *        iteration read them (the paper keeps Z_ij for the products of one
+ *        block visit, steps 15-21); nothing of Z survives the iteration.
+ * AUTO : STORE with the largest row-block groups that fit the budget.      */
+enum { BSADMM_Z_AUTO = 0, BSADMM_Z_STORE = 1 };
+
+/* -------------------------------------------------------------- problem */
+/* Problem of eq. problem_linear with Z = sqrt(2/s) cos(X W + b):
+ *   minimise (1/n) sum_r V(y_r, W_model^T z(x_r)) + lambda ||W_model||_F^2.
+ * The ADMM penalty rho applies to n times that objective (the loss prox has
+ * weight 1/rho and the regulariser prox weight n lambda / rho); this is the
+ * paper's update with its rho replaced by rho / n, and has the same
+ * minimiser.                                                              */
+typedef struct bsadmm_problem {
+  int64_t n;        /* examples (rows of X, Y), >= R                        */
+  int64_t d;        /* input dimension, >= 1                                */
+  int64_t m;        /* outputs / classes (columns of Y), 1 <= m <= 1024     */
+  int64_t s;        /* random features, >= C                                */
+  int32_t R;        /* row blocks, >= 1                                     */
+  int32_t C;        /* feature (column) blocks, >= 1                        */
+  int32_t loss;     /* BSADMM_SQUARED | BSADMM_HINGE | BSADMM_MC_HINGE      */
+  int32_t reg;      /* BSADMM_L2                                            */
+  int32_t precision;/* BSADMM_FP64 | BSADMM_FP32 | BSADMM_BF16              */
+  int32_t z_mode;   /* BSADMM_Z_AUTO | BSADMM_Z_STORE                       */
+  double lambda;    /* >= 0                                                 */
+  double rho;       /* > 0                                                  */
+  double sigma;     /* kernel bandwidth the caller drew W with; > 0; used
+                       only for validation and reporting                    */
+  const float* X;   /* device, n x d, caller-owned, must outlive the handle */
+  const float* Y;   /* device, n x m, caller-owned, must outlive the handle */
+  const float* W;   /* device, d x s feature directions (N(0, 1/sigma^2)),
+                       caller-owned; copied at setup                        */
+  const float* b;   /* device, s feature offsets (U[0, 2 pi)); copied       */
+  void* stream;     /* hipStream_t for every call on the handle             */
+  size_t hbm_budget_bytes;  /* 0 = no limit; else setup fails with ENOMEM
+                               when the footprint exceeds it                */
+  size_t workspace_bytes;   /* cap on the Z workspace; 0 = automatic        */
+} bsadmm_problem;
+
+/* Phases timed with HIP events on the handle's stream (bsadmm_stats). */
+enum {
+  BSADMM_PH_REGEN = 0,   /* feature regeneration Z = sqrt(2/s) cos(XW + b)  */
+  BSADMM_PH_ZTR = 1,     /* A_ij = Z_ij^T (Delta-bar_i/(C+1) + nu_i)        */
+  BSADMM_PH_SOLVE = 2,   /* W'_ij = (I + Z_ij^T Z_ij)^{-1} rhs_ij, U update */
+  BSADMM_PH_ZW = 3,      /* sum_j Z_ij W'_ij                                */
+  BSADMM_PH_ROW = 4,     /* loss prox, exchange and nu updates              */
+  BSADMM_PH_COL = 5,     /* regulariser prox, consensus and mu updates      */
+  BSADMM_PH_COUNT = 8
+};
+
+typedef struct bsadmm_stats {
+  int64_t iters_done;       /* total iterations run on the handle          */
+  int32_t timed;            /* in: nonzero asks for per-phase timing        */
+  int32_t launches;         /* out: launches of the regeneration kernel in
+                               the call (one per row-block group per
+                               iteration)                                  */
+  double phase_ms[BSADMM_PH_COUNT];  /* out: summed over the call          */
+  double iterate_ms;        /* out: whole call, HIP events                 */
+} bsadmm_stats;
+
+typedef struct bsadmm_handle bsadmm_handle;
+
+/* ----------------------------------------------------------------------
+ * rff_map -- the transform T of Algorithm 1, step 15, for the random
+ * Fourier feature map of section "Randomized Kernel Maps":
+ *   Z[r][f] = sqrt(2/s) * cos(sum_k X[r][k] W[k][f] + b[f]).
+ * X: device n x d float32.  W: device d x s float32.  b: device s float32.
+ * Z_out: device n x s of double (FP64), float (FP32) or bf16 bits stored
+ * as uint16 (BF16).  n may be 0 (no work).  Allocates and frees a small
+ * operand staging buffer; synchronises the stream before returning.
+ * Errors: EINVAL (null pointers with n > 0, d < 1, s < 1, bad precision),
+ * ENOMEM, EDEVICE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int rff_map(const float* X, int64_t n, int64_t d, const float* W, const float* b,
+            int64_t s, int32_t precision, void* Z_out, void* stream);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_validate -- host-only argument checks of a problem (no HIP call,
+ * no device access): n >= R >= 1, s >= C >= 1, d >= 1, 1 <= m <= 1024,
+ * m == 1 for HINGE, lambda >= 0, rho > 0, sigma > 0, known enums, non-null
+ * X, Y, W, b, and 16-byte alignment of X, Y, W, b.  Returns OK or EINVAL.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_validate(const bsadmm_problem* p);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_footprint -- device bytes bsadmm_setup will allocate for p
+ * (operand copies, factor cache R*C*S^2 doubles with S = s_j rounded up to
+ * 64, ADMM state, Z workspace, partial sums).  Host-only; validates p
+ * first.  The paper's own per-node model is eq. mem of paragraph "Memory
+ * Requirements"; this is its device counterpart.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_footprint(const bsadmm_problem* p, size_t* bytes);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_setup -- validate, allocate, copy W and b into the operand
+ * layout, set the ADMM state of Algorithm 1, step 2 to zero and build the
+ * cache of eq. cache: for every block, Q_ij = (I + Z_ij^T Z_ij)^{-1} in
+ * FP64 through a Cholesky factorisation (the paper builds it in the first
+ * iteration, step 16).  Synchronises the stream.
+ * Errors: EINVAL, ENONFINITE (NaN/Inf in X, Y, W or b), ENOMEM, EDEVICE,
+ * ENOTPD.  On error *out is NULL and nothing stays allocated.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_setup(const bsadmm_problem* p, bsadmm_handle** out);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_iterate -- run `iters` (>= 0) iterations of Algorithm 1 with the
+ * graph-projection right-hand side of eq. gpWij (it includes Z_ij^T nu_i)
+ * and the dual updates of mu, mu' made with the new consensus W-bar, as in
+ * the block-splitting update equations.  Enqueued on the handle's stream;
+ * if st != NULL the call synchronises and fills st.
+ * Errors: EINVAL (iters < 0, null handle), ESTATE, EDEVICE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_iterate(bsadmm_handle* h, int32_t iters, bsadmm_stats* st);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_predict -- scores of the consensus model: out = Z(Xt) W-bar
+ * (prediction f(x) = W^T z(x) of the linearised hypothesis space).
+ * Xt: device nt x d float32.  out: device nt x m float32.  Uses the
+ * handle's precision for the feature map.  nt may be 0.  Synchronises.
+ * Errors: EINVAL, ESTATE, ENOMEM, EDEVICE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, void* stream);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_get_coef -- copy the consensus model W-bar (s x m, FP64) into a
+ * caller-owned device buffer.  Synchronises.  Errors: EINVAL, ESTATE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_get_coef(const bsadmm_handle* h, double* Wbar);
+
+/* State arrays of the iteration (names of Algorithm 1; sizes in doubles). */
+enum {
+  BSADMM_ST_O = 0,     /* n x m   loss-prox output O                        */
+  BSADMM_ST_OBAR = 1,  /* n x m   O-bar                                     */
+  BSADMM_ST_NU = 2,    /* n x m   nu                                        */
+  BSADMM_ST_DBAR = 3,  /* n x m   Delta-bar                                 */
+  BSADMM_ST_WC = 4,    /* s x m   regulariser-prox output W                 */
+  BSADMM_ST_WBAR = 5,  /* s x m   consensus W-bar                           */
+  BSADMM_ST_MU = 6,    /* s x m   mu                                        */
+  BSADMM_ST_WP = 7,    /* R x s x m local models W'                         */
+  BSADMM_ST_MUP = 8,   /* R x s x m mu'                                     */
+  BSADMM_ST_U = 9,     /* R x s x m U = Z_ij^T Z_ij W'_ij                   */
+  BSADMM_ST_COUNT = 10
+};
+
+/* ----------------------------------------------------------------------
+ * bsadmm_state_size -- number of doubles of state array `which`.
+ * bsadmm_export_state / bsadmm_import_state -- copy one state array to /
+ * from a caller-owned device buffer (checkpoint and resume: exporting all
+ * BSADMM_ST_COUNT arrays and the iteration count and importing them into a
+ * handle set up from the same inputs continues the run exactly).  Both
+ * synchronise.  Errors: EINVAL (bad `which`, null pointer), ESTATE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_state_size(const bsadmm_handle* h, int32_t which, int64_t* count);
+BSADMM_API int bsadmm_export_state(const bsadmm_handle* h, int32_t which, double* dst);
+BSADMM_API int bsadmm_import_state(bsadmm_handle* h, int32_t which, const double* src);
+
+/* bsadmm_destroy -- free everything the handle owns.  NULL is allowed. */
+BSADMM_API int bsadmm_destroy(bsadmm_handle* h);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+BSADMM_API const char* bsadmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSADMM_H */

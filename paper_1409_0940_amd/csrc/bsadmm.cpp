@@ -1,0 +1,643 @@
+// libbsadmm host library: the C ABI of include/bsadmm.h.
+//
+// A handle owns, in HBM: operand copies of X and W (k padded, in the
+// arithmetic precision), the cached inverses Q_ij (FP64), the FP64 ADMM
+// state of Algorithm 1 and a workspace for the blocks Z_ij of one group of
+// row blocks.  One iteration enqueues, on the handle's stream:
+//   row_pre, col_pre                      steps 4, 6 (+ operand of step 17)
+//   per row-block group:
+//     regen (one launch per column block) step 15
+//     ztr partial + reduce_rhs            step 17 and the rhs of step 18
+//     solve                               step 18 (+ U, step 21)
+//     zw                                  step 19 (sums of steps 20, 22)
+//   row_post, col_post                    steps 25, 27-29, 33
+#include "bsadmm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(BSADMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Sizes and layout derived from a problem; computed on the host only.
+struct Plan {
+  int prec = 0;
+  int64_t n = 0, d = 0, m = 0, s = 0, mp = 0, Kp = 0, spad = 0, S = 0;
+  int R = 1, C = 1;
+  std::vector<int64_t> rstart, cstart, coff, sj;
+  std::vector<std::pair<int, int>> groups;  // row-block ranges [i0, i1)
+  int64_t ws_rows = 0;
+  int64_t split_rows = 2048, nsplit_max = 1;
+  int fac_batch = 1;
+  size_t op = 4, accb = 4;
+  // byte counts
+  size_t b_xp = 0, b_wt = 0, b_bias = 0, b_q = 0, b_ws = 0, b_row = 0, b_rop = 0, b_col = 0,
+         b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0;
+  size_t total() const {
+    return b_xp + b_wt + b_bias + b_q + b_ws + 5 * b_row + b_rop + 3 * b_col + 4 * b_colR + b_wop +
+           b_part + b_small + b_fac_tmp;
+  }
+};
+
+int validate(const bsadmm_problem* p) {
+  if (!p) return fail(BSADMM_EINVAL, "problem is NULL");
+  if (p->R < 1 || p->C < 1) return fail(BSADMM_EINVAL, "R and C must be >= 1");
+  if (p->n < p->R) return fail(BSADMM_EINVAL, "need n >= R");
+  if (p->s < p->C) return fail(BSADMM_EINVAL, "need s >= C");
+  if (p->d < 1) return fail(BSADMM_EINVAL, "need d >= 1");
+  if (p->m < 1 || p->m > 1024) return fail(BSADMM_EINVAL, "need 1 <= m <= 1024");
+  if (p->loss != BSADMM_SQUARED && p->loss != BSADMM_HINGE && p->loss != BSADMM_MC_HINGE)
+    return fail(BSADMM_EINVAL, "unknown loss");
+  if (p->loss == BSADMM_HINGE && p->m != 1) return fail(BSADMM_EINVAL, "HINGE needs m == 1");
+  if (p->reg != BSADMM_L2) return fail(BSADMM_EINVAL, "unknown regulariser");
+  if (p->precision != BSADMM_FP64 && p->precision != BSADMM_FP32 && p->precision != BSADMM_BF16)
+    return fail(BSADMM_EINVAL, "unknown precision");
+  if (p->z_mode != BSADMM_Z_AUTO && p->z_mode != BSADMM_Z_STORE)
+    return fail(BSADMM_EINVAL, "unknown z_mode");
+  if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(BSADMM_EINVAL, "need lambda >= 0");
+  if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return fail(BSADMM_EINVAL, "need rho > 0");
+  if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) return fail(BSADMM_EINVAL, "need sigma > 0");
+  if (!p->X || !p->Y || !p->W || !p->b) return fail(BSADMM_EINVAL, "X, Y, W, b must be non-NULL");
+  const void* ptrs[4] = {p->X, p->Y, p->W, p->b};
+  for (const void* q : ptrs)
+    if (reinterpret_cast<uintptr_t>(q) % 16 != 0)
+      return fail(BSADMM_EINVAL, "X, Y, W, b must be 16-byte aligned");
+  return BSADMM_OK;
+}
+
+int make_plan(const bsadmm_problem* p, Plan& L) {
+  int rc = validate(p);
+  if (rc) return rc;
+  L.prec = p->precision;
+  L.n = p->n; L.d = p->d; L.m = p->m; L.s = p->s; L.R = p->R; L.C = p->C;
+  L.mp = rup(L.m, 16);
+  L.op = bs::op_bytes(L.prec);
+  L.accb = (L.prec == BSADMM_FP64) ? 8 : 4;
+  L.Kp = bs::padded_k(L.prec, L.d);
+  L.rstart.resize(L.R + 1);
+  for (int i = 0; i <= L.R; ++i) L.rstart[i] = (int64_t)i * L.n / L.R;
+  L.cstart.resize(L.C + 1);
+  for (int j = 0; j <= L.C; ++j) L.cstart[j] = (int64_t)j * L.s / L.C;
+  L.coff.resize(L.C);
+  L.sj.resize(L.C);
+  int64_t off = 0, smax = 0;
+  for (int j = 0; j < L.C; ++j) {
+    L.sj[j] = L.cstart[j + 1] - L.cstart[j];
+    L.coff[j] = off;
+    off += rup(L.sj[j], 64);
+    smax = std::max(smax, L.sj[j]);
+  }
+  L.spad = off;
+  L.S = rup(smax, 64);
+  // Row-block groups for the Z workspace.
+  size_t cap = p->workspace_bytes ? p->workspace_bytes : (size_t)32 << 30;
+  const size_t row_bytes = (size_t)L.spad * L.op;
+  L.groups.clear();
+  int i = 0;
+  L.ws_rows = 0;
+  while (i < L.R) {
+    int i1 = i + 1;
+    while (i1 < L.R && (size_t)(L.rstart[i1 + 1] - L.rstart[i]) * row_bytes <= cap) ++i1;
+    L.groups.push_back({i, i1});
+    L.ws_rows = std::max(L.ws_rows, L.rstart[i1] - L.rstart[i]);
+    i = i1;
+  }
+  int64_t nmax = 0;
+  for (int r = 0; r < L.R; ++r) nmax = std::max(nmax, L.rstart[r + 1] - L.rstart[r]);
+  L.split_rows = std::max<int64_t>(2048, rup((nmax + 63) / 64, 4));
+  L.nsplit_max = (nmax + L.split_rows - 1) / L.split_rows;
+  const size_t slot = (size_t)L.S * L.S * 8;
+  const size_t fac_cap = (size_t)4 << 30;
+  L.fac_batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.R * L.C, fac_cap / slot));
+  L.b_xp = (size_t)L.n * L.Kp * L.op;
+  L.b_wt = (size_t)L.s * L.Kp * L.op;
+  L.b_bias = (size_t)L.s * (L.prec == BSADMM_FP64 ? 8 : 4);
+  L.b_q = (size_t)L.R * L.C * slot;
+  L.b_ws = (size_t)L.ws_rows * row_bytes;
+  L.b_row = (size_t)L.n * L.mp * 8;
+  L.b_rop = (size_t)L.n * L.mp * L.op;
+  L.b_col = (size_t)L.spad * L.mp * 8;
+  L.b_colR = (size_t)L.R * L.spad * L.mp * 8;
+  L.b_wop = (size_t)L.R * L.spad * L.mp * L.op;
+  L.b_part = (size_t)L.R * L.nsplit_max * L.spad * L.mp * L.accb;
+  L.b_small = 256 + 2 * (size_t)L.C * 8;
+  L.b_fac_tmp = (size_t)L.fac_batch * (slot + (size_t)L.S * 64 * 8);
+  return BSADMM_OK;
+}
+
+}  // namespace
+
+struct bsadmm_handle {
+  Plan L;
+  bsadmm_problem p{};
+  hipStream_t st = nullptr;
+  double tau = 0, kappa = 0, scale = 0;
+  std::vector<void*> allocs;
+  void *Xp = nullptr, *Wt = nullptr, *bias = nullptr, *Z = nullptr, *Rop = nullptr,
+       *Wop = nullptr, *part = nullptr;
+  double *Q = nullptr, *O = nullptr, *Obar = nullptr, *nu = nullptr, *Dbar = nullptr,
+         *P = nullptr, *Wbar = nullptr, *mu = nullptr, *Wc = nullptr, *Wp = nullptr,
+         *mup = nullptr, *U = nullptr, *rhs = nullptr;
+  int64_t *d_coff = nullptr, *d_sj = nullptr;
+  int* dflag = nullptr;
+  int64_t iters = 0;
+  bool poisoned = false;
+  std::vector<hipEvent_t> evpool;
+
+  hipError_t alloc(void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipSuccess) allocs.push_back(*ptr);
+    return e;
+  }
+  ~bsadmm_handle() {
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    for (void* a : allocs) (void)hipFree(a);
+  }
+};
+
+namespace {
+
+#define HCHK(expr)                                        \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);     \
+  } while (0)
+
+// Feature regeneration of the rows of group g into the workspace.
+hipError_t regen_group(bsadmm_handle* h, int i0, int i1, const void* Xop) {
+  const Plan& L = h->L;
+  const int64_t r0 = L.rstart[i0], rows = L.rstart[i1] - r0;
+  for (int j = 0; j < L.C; ++j) {
+    hipError_t e = bs::regen(L.prec, (const char*)Xop + (size_t)r0 * L.Kp * L.op, rows,
+                             (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.sj[j],
+                             (const char*)h->bias + (size_t)L.cstart[j] * (L.prec == BSADMM_FP64 ? 8 : 4),
+                             L.Kp, h->scale, (char*)h->Z + (size_t)L.coff[j] * L.op, L.spad, h->st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+struct PhaseTimer {
+  bsadmm_handle* h;
+  bool on;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == h->evpool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      h->evpool.push_back(e);
+    }
+    return h->evpool[used++];
+  }
+  hipEvent_t start_ev = nullptr;
+  void begin() {
+    if (!on) return;
+    start_ev = get();
+    if (start_ev) (void)hipEventRecord(start_ev, h->st);
+  }
+  void end(int phase) {
+    if (!on || !start_ev) return;
+    hipEvent_t e = get();
+    if (!e) return;
+    (void)hipEventRecord(e, h->st);
+    marks.push_back({phase, {start_ev, e}});
+    start_ev = nullptr;
+  }
+};
+
+int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
+  const Plan& L = h->L;
+  PhaseTimer tm{h, st && st->timed != 0};
+  hipEvent_t all0 = nullptr, all1 = nullptr;
+  if (st) {
+    all0 = tm.get();
+    all1 = tm.get();
+    if (all0) HCHK(hipEventRecord(all0, h->st));
+  }
+  int launches = 0;
+  const double cfac = 1.0 / (double)(L.C + 1);
+  for (int it = 0; it < iters; ++it) {
+    tm.begin();
+    HCHK(bs::row_pre(L.prec, h->p.loss == BSADMM_SQUARED ? 0 : 1, h->tau, cfac, L.n, L.m, L.mp,
+                     h->p.Y, h->Obar, h->nu, h->Dbar, h->O, h->Rop, h->st));
+    tm.end(BSADMM_PH_ROW);
+    tm.begin();
+    HCHK(bs::col_pre(h->kappa, L.spad, L.m, L.mp, h->Wbar, h->mu, h->Wc, h->st));
+    tm.end(BSADMM_PH_COL);
+    for (const auto& g : L.groups) {
+      const int i0 = g.first, i1 = g.second;
+      const int64_t r0 = L.rstart[i0];
+      tm.begin();
+      HCHK(regen_group(h, i0, i1, h->Xp));
+      launches += L.C;
+      tm.end(BSADMM_PH_REGEN);
+      tm.begin();
+      for (int i = i0; i < i1; ++i) {
+        const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
+        HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.op,
+                             L.spad, ni, L.spad, (const char*)h->Rop + (size_t)ri * L.mp * L.op,
+                             L.mp, L.split_rows,
+                             (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.accb,
+                             h->st));
+      }
+      HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
+                          L.mp, h->Wbar, h->mup, h->U, h->rhs, h->st));
+      tm.end(BSADMM_PH_ZTR);
+      tm.begin();
+      HCHK(bs::solve(L.prec, h->Q, L.S, L.C, i0 * L.C, (i1 - i0) * L.C, h->d_coff, h->d_sj,
+                     L.spad, L.mp, h->rhs, h->Wp, h->U, h->Wop, h->st));
+      tm.end(BSADMM_PH_SOLVE);
+      tm.begin();
+      for (int i = i0; i < i1; ++i) {
+        const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
+        HCHK(bs::zw(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.op, L.spad, ni,
+                    L.spad, (const char*)h->Wop + (size_t)i * L.spad * L.mp * L.op, L.mp,
+                    h->P + (size_t)ri * L.mp, h->st));
+      }
+      tm.end(BSADMM_PH_ZW);
+    }
+    tm.begin();
+    HCHK(bs::row_post(L.n, L.m, L.mp, L.C, h->O, h->P, h->Obar, h->nu, h->Dbar, h->st));
+    tm.end(BSADMM_PH_ROW);
+    tm.begin();
+    HCHK(bs::col_post(L.R, L.spad, L.m, L.mp, h->Wc, h->Wp, h->Wbar, h->mu, h->mup, h->st));
+    tm.end(BSADMM_PH_COL);
+  }
+  h->iters += iters;
+  if (st) {
+    if (all1) HCHK(hipEventRecord(all1, h->st));
+    HCHK(hipStreamSynchronize(h->st));
+    for (int k = 0; k < BSADMM_PH_COUNT; ++k) st->phase_ms[k] = 0.0;
+    for (auto& mk : tm.marks) {
+      float ms = 0.f;
+      HCHK(hipEventElapsedTime(&ms, mk.second.first, mk.second.second));
+      st->phase_ms[mk.first] += ms;
+    }
+    float all = 0.f;
+    if (all0 && all1) HCHK(hipEventElapsedTime(&all, all0, all1));
+    st->iterate_ms = all;
+    st->launches = launches;
+    st->iters_done = h->iters;
+  }
+  return BSADMM_OK;
+}
+
+int do_setup(bsadmm_handle* h) {
+  Plan& L = h->L;
+  const bsadmm_problem& p = h->p;
+  h->st = (hipStream_t)p.stream;
+  h->scale = std::sqrt(2.0 / (double)L.s);
+  // n F(W) scaling of the penalty: loss prox weight 1/rho, regulariser n lambda / rho
+  h->tau = 1.0 / p.rho;
+  h->kappa = (double)L.n * p.lambda / p.rho;
+  void* tmp = nullptr;
+#define ALLOC(ptr, bytes)                                                         \
+  do {                                                                            \
+    hipError_t e_ = h->alloc((void**)&(ptr), (bytes));                            \
+    if (e_ != hipSuccess) return fail(BSADMM_ENOMEM, "hipMalloc failed for " #ptr); \
+  } while (0)
+  ALLOC(h->Xp, L.b_xp);
+  ALLOC(h->Wt, L.b_wt);
+  ALLOC(h->bias, L.b_bias);
+  ALLOC(h->Q, L.b_q);
+  ALLOC(h->Z, L.b_ws);
+  ALLOC(h->O, L.b_row);
+  ALLOC(h->Obar, L.b_row);
+  ALLOC(h->nu, L.b_row);
+  ALLOC(h->Dbar, L.b_row);
+  ALLOC(h->P, L.b_row);
+  ALLOC(h->Rop, L.b_rop);
+  ALLOC(h->Wbar, L.b_col);
+  ALLOC(h->mu, L.b_col);
+  ALLOC(h->Wc, L.b_col);
+  ALLOC(h->Wp, L.b_colR);
+  ALLOC(h->mup, L.b_colR);
+  ALLOC(h->U, L.b_colR);
+  ALLOC(h->rhs, L.b_colR);
+  ALLOC(h->Wop, L.b_wop);
+  ALLOC(h->part, L.b_part);
+  ALLOC(tmp, L.b_small);
+  h->dflag = (int*)tmp;
+  h->d_coff = (int64_t*)((char*)tmp + 256);
+  h->d_sj = h->d_coff + L.C;
+  hipStream_t st = h->st;
+  HCHK(hipMemcpyAsync(h->d_coff, L.coff.data(), L.C * 8, hipMemcpyHostToDevice, st));
+  HCHK(hipMemcpyAsync(h->d_sj, L.sj.data(), L.C * 8, hipMemcpyHostToDevice, st));
+  HCHK(hipMemsetAsync(h->dflag, 0, 256, st));
+  for (void* z : {(void*)h->O, (void*)h->Obar, (void*)h->nu, (void*)h->Dbar, (void*)h->P})
+    HCHK(hipMemsetAsync(z, 0, L.b_row, st));
+  HCHK(hipMemsetAsync(h->Rop, 0, L.b_rop, st));
+  for (void* z : {(void*)h->Wbar, (void*)h->mu, (void*)h->Wc})
+    HCHK(hipMemsetAsync(z, 0, L.b_col, st));
+  for (void* z : {(void*)h->Wp, (void*)h->mup, (void*)h->U, (void*)h->rhs})
+    HCHK(hipMemsetAsync(z, 0, L.b_colR, st));
+  HCHK(hipMemsetAsync(h->Wop, 0, L.b_wop, st));
+  HCHK(hipMemsetAsync(h->Z, 0, L.b_ws, st));
+  // operands and input checks
+  HCHK(bs::prep_rows(L.prec, p.X, L.n, L.d, L.Kp, h->Xp, h->dflag, st));
+  HCHK(bs::prep_w(L.prec, p.W, p.b, L.d, L.s, L.Kp, h->Wt, h->bias, h->dflag, st));
+  HCHK(bs::check_finite(p.Y, L.n * L.m, h->dflag, st));
+  int flag = 0;
+  HCHK(hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HCHK(hipStreamSynchronize(st));
+  if (flag & 1) return fail(BSADMM_ENONFINITE, "X, Y, W or b holds NaN or Inf");
+  if (p.loss != BSADMM_SQUARED) {
+    // hinge targets must be exactly +-1: checked on a host copy of Y
+    std::vector<float> y((size_t)L.n * L.m);
+    HCHK(hipMemcpyAsync(y.data(), p.Y, y.size() * 4, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    for (float v : y)
+      if (v != 1.0f && v != -1.0f) return fail(BSADMM_EINVAL, "hinge targets must be +1 or -1");
+  }
+  // Gram blocks and the FP64 inverse cache (eq. cache)
+  const size_t slot = (size_t)L.S * L.S;
+  for (const auto& g : L.groups) {
+    const int i0 = g.first, i1 = g.second;
+    const int64_t r0 = L.rstart[i0];
+    HCHK(regen_group(h, i0, i1, h->Xp));
+    for (int i = i0; i < i1; ++i)
+      for (int j = 0; j < L.C; ++j)
+        HCHK(bs::gram(L.prec, (const char*)h->Z + (size_t)(L.rstart[i] - r0) * L.spad * L.op,
+                      L.spad, L.rstart[i + 1] - L.rstart[i], L.coff[j], L.sj[j],
+                      h->Q + (size_t)(i * L.C + j) * slot, L.S, st));
+  }
+  std::vector<int64_t> sjb((size_t)L.R * L.C);
+  for (int i = 0; i < L.R; ++i)
+    for (int j = 0; j < L.C; ++j) sjb[(size_t)i * L.C + j] = L.sj[j];
+  HCHK(bs::identity_pad(h->Q, L.R * L.C, L.S, sjb.data(), st));
+  double* work = nullptr;
+  {
+    hipError_t e = hipMalloc((void**)&work, L.b_fac_tmp);
+    if (e != hipSuccess) return fail(BSADMM_ENOMEM, "hipMalloc failed for factor workspace");
+  }
+  double* dinv = work + (size_t)L.fac_batch * slot;
+  int rc = BSADMM_OK;
+  for (int b0 = 0; b0 < L.R * L.C && rc == BSADMM_OK; b0 += L.fac_batch) {
+    const int nb = std::min(L.fac_batch, L.R * L.C - b0);
+    hipError_t e = bs::spd_inverse(h->Q + (size_t)b0 * slot, nb, L.S, work, dinv, h->dflag, st);
+    if (e != hipSuccess) rc = hip_fail(e, "spd_inverse");
+  }
+  hipError_t e1 = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  (void)hipFree(work);
+  if (rc) return rc;
+  if (e1 != hipSuccess) return hip_fail(e1, "flag copy");
+  if (e2 != hipSuccess) return hip_fail(e2, "setup synchronize");
+  if (flag & 2) return fail(BSADMM_ENOTPD, "Cholesky pivot of I + Z^T Z not positive");
+  return BSADMM_OK;
+}
+
+// Which array, its rows and whether it is row-side (n), column-side (s) or
+// per-row-block column-side (R x s).
+struct StateRef {
+  double* ptr;
+  int kind;  // 0: n x m, 1: s x m, 2: R x s x m
+};
+
+StateRef state_ref(const bsadmm_handle* h, int which) {
+  switch (which) {
+    case BSADMM_ST_O: return {h->O, 0};
+    case BSADMM_ST_OBAR: return {h->Obar, 0};
+    case BSADMM_ST_NU: return {h->nu, 0};
+    case BSADMM_ST_DBAR: return {h->Dbar, 0};
+    case BSADMM_ST_WC: return {h->Wc, 1};
+    case BSADMM_ST_WBAR: return {h->Wbar, 1};
+    case BSADMM_ST_MU: return {h->mu, 1};
+    case BSADMM_ST_WP: return {h->Wp, 2};
+    case BSADMM_ST_MUP: return {h->mup, 2};
+    case BSADMM_ST_U: return {h->U, 2};
+    default: return {nullptr, -1};
+  }
+}
+
+int copy_state(const bsadmm_handle* h, int which, double* dense, bool to_dense) {
+  const Plan& L = h->L;
+  StateRef s = state_ref(h, which);
+  if (!s.ptr) return fail(BSADMM_EINVAL, "unknown state array");
+  hipStream_t st = h->st;
+  auto mv = [&](double* padded, int64_t rows, double* dn) -> hipError_t {
+    return to_dense ? bs::unpad(padded, rows, L.m, L.mp, dn, st)
+                    : bs::pad(dn, rows, L.m, L.mp, padded, st);
+  };
+  if (s.kind == 0) {
+    HCHK(mv(s.ptr, L.n, dense));
+  } else {
+    const int reps = s.kind == 1 ? 1 : L.R;
+    for (int i = 0; i < reps; ++i)
+      for (int j = 0; j < L.C; ++j)
+        HCHK(mv(s.ptr + ((size_t)i * L.spad + L.coff[j]) * L.mp, L.sj[j],
+                dense + ((size_t)i * L.s + L.cstart[j]) * L.m));
+  }
+  if (!to_dense && which == BSADMM_ST_WP) {
+    // keep the operand copy of W' in step with the imported state
+    HCHK(bs::to_op(L.prec, h->Wp, (int64_t)L.R * L.spad * L.mp, h->Wop, st));
+  }
+  HCHK(hipStreamSynchronize(st));
+  return BSADMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bsadmm_last_error(void) { return g_err.c_str(); }
+
+int bsadmm_validate(const bsadmm_problem* p) {
+  g_err.clear();
+  return validate(p);
+}
+
+int bsadmm_footprint(const bsadmm_problem* p, size_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(BSADMM_EINVAL, "bytes is NULL");
+  Plan L;
+  int rc = make_plan(p, L);
+  if (rc) return rc;
+  *bytes = L.total();
+  return BSADMM_OK;
+}
+
+int bsadmm_setup(const bsadmm_problem* p, bsadmm_handle** out) {
+  g_err.clear();
+  if (!out) return fail(BSADMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Plan L;
+  int rc = make_plan(p, L);
+  if (rc) return rc;
+  if (p->hbm_budget_bytes && L.total() > p->hbm_budget_bytes)
+    return fail(BSADMM_ENOMEM, "footprint " + std::to_string(L.total()) + " B exceeds budget " +
+                                   std::to_string(p->hbm_budget_bytes) + " B");
+  bsadmm_handle* h = new (std::nothrow) bsadmm_handle();
+  if (!h) return fail(BSADMM_ENOMEM, "host allocation failed");
+  h->L = L;
+  h->p = *p;
+  rc = do_setup(h);
+  if (rc) {
+    std::string msg = g_err;
+    (void)hipStreamSynchronize(h->st);
+    delete h;
+    g_err = msg;
+    return rc;
+  }
+  *out = h;
+  return BSADMM_OK;
+}
+
+int bsadmm_iterate(bsadmm_handle* h, int32_t iters, bsadmm_stats* st) {
+  g_err.clear();
+  if (!h) return fail(BSADMM_EINVAL, "handle is NULL");
+  if (iters < 0) return fail(BSADMM_EINVAL, "iters must be >= 0");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  int rc = run_iterations(h, iters, st);
+  if (rc == BSADMM_EDEVICE) h->poisoned = true;
+  return rc;
+}
+
+int bsadmm_get_coef(const bsadmm_handle* h, double* Wbar) {
+  g_err.clear();
+  if (!h || !Wbar) return fail(BSADMM_EINVAL, "NULL argument");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  return copy_state(h, BSADMM_ST_WBAR, Wbar, true);
+}
+
+int bsadmm_state_size(const bsadmm_handle* h, int32_t which, int64_t* count) {
+  g_err.clear();
+  if (!h || !count) return fail(BSADMM_EINVAL, "NULL argument");
+  StateRef s = state_ref(h, which);
+  if (!s.ptr) return fail(BSADMM_EINVAL, "unknown state array");
+  const Plan& L = h->L;
+  *count = s.kind == 0 ? L.n * L.m : (s.kind == 1 ? L.s * L.m : (int64_t)L.R * L.s * L.m);
+  return BSADMM_OK;
+}
+
+int bsadmm_export_state(const bsadmm_handle* h, int32_t which, double* dst) {
+  g_err.clear();
+  if (!h || !dst) return fail(BSADMM_EINVAL, "NULL argument");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  return copy_state(h, which, dst, true);
+}
+
+int bsadmm_import_state(bsadmm_handle* h, int32_t which, const double* src) {
+  g_err.clear();
+  if (!h || !src) return fail(BSADMM_EINVAL, "NULL argument");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  return copy_state(h, which, const_cast<double*>(src), false);
+}
+
+int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, void* stream) {
+  g_err.clear();
+  if (!h) return fail(BSADMM_EINVAL, "handle is NULL");
+  if (nt < 0) return fail(BSADMM_EINVAL, "nt must be >= 0");
+  if (nt > 0 && (!Xt || !out)) return fail(BSADMM_EINVAL, "Xt and out must be non-NULL");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  if (nt == 0) return BSADMM_OK;
+  const Plan& L = h->L;
+  hipStream_t st = stream ? (hipStream_t)stream : h->st;
+  if (st != h->st) {
+    // order after the handle's pending work
+    hipEvent_t e;
+    HCHK(hipEventCreate(&e));
+    HCHK(hipEventRecord(e, h->st));
+    HCHK(hipStreamWaitEvent(st, e, 0));
+    (void)hipEventDestroy(e);
+  }
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nt, L.ws_rows));
+  void *xop = nullptr, *wop = nullptr;
+  double* pbuf = nullptr;
+  auto cleanup = [&]() {
+    if (xop) (void)hipFree(xop);
+    if (wop) (void)hipFree(wop);
+    if (pbuf) (void)hipFree(pbuf);
+  };
+  if (hipMalloc(&xop, (size_t)chunk * L.Kp * L.op) != hipSuccess ||
+      hipMalloc(&wop, (size_t)L.spad * L.mp * L.op) != hipSuccess ||
+      hipMalloc((void**)&pbuf, (size_t)chunk * L.mp * 8) != hipSuccess) {
+    cleanup();
+    return fail(BSADMM_ENOMEM, "hipMalloc failed in predict");
+  }
+  hipError_t e = bs::to_op(L.prec, h->Wbar, L.spad * L.mp, wop, st);
+  for (int64_t r0 = 0; r0 < nt && e == hipSuccess; r0 += chunk) {
+    const int64_t rows = std::min(chunk, nt - r0);
+    e = bs::prep_rows(L.prec, Xt + r0 * L.d, rows, L.d, L.Kp, xop, nullptr, st);
+    for (int j = 0; j < L.C && e == hipSuccess; ++j)
+      e = bs::regen(L.prec, xop, rows, (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op,
+                    L.sj[j],
+                    (const char*)h->bias + (size_t)L.cstart[j] * (L.prec == BSADMM_FP64 ? 8 : 4),
+                    L.Kp, h->scale, (char*)h->Z + (size_t)L.coff[j] * L.op, L.spad, st);
+    if (e == hipSuccess) e = bs::zw(L.prec, h->Z, L.spad, rows, L.spad, wop, L.mp, pbuf, st);
+    if (e == hipSuccess) e = bs::scores_out(pbuf, rows, L.m, L.mp, out + r0 * L.m, st);
+  }
+  hipError_t e2 = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) return hip_fail(e, "predict");
+  if (e2 != hipSuccess) return hip_fail(e2, "predict synchronize");
+  if (st != h->st) HCHK(hipStreamSynchronize(h->st));
+  return BSADMM_OK;
+}
+
+int bsadmm_destroy(bsadmm_handle* h) {
+  g_err.clear();
+  if (!h) return BSADMM_OK;
+  (void)hipStreamSynchronize(h->st);
+  delete h;
+  return BSADMM_OK;
+}
+
+int rff_map(const float* X, int64_t n, int64_t d, const float* W, const float* b, int64_t s,
+            int32_t precision, void* Z_out, void* stream) {
+  g_err.clear();
+  if (precision != BSADMM_FP64 && precision != BSADMM_FP32 && precision != BSADMM_BF16)
+    return fail(BSADMM_EINVAL, "unknown precision");
+  if (n < 0 || d < 1 || s < 1) return fail(BSADMM_EINVAL, "need n >= 0, d >= 1, s >= 1");
+  if (n == 0) return BSADMM_OK;
+  if (!X || !W || !b || !Z_out) return fail(BSADMM_EINVAL, "NULL pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t Kp = bs::padded_k(precision, d);
+  const size_t op = bs::op_bytes(precision);
+  void *xop = nullptr, *wt = nullptr, *bias = nullptr;
+  auto cleanup = [&]() {
+    if (xop) (void)hipFree(xop);
+    if (wt) (void)hipFree(wt);
+    if (bias) (void)hipFree(bias);
+  };
+  if (hipMalloc(&xop, (size_t)n * Kp * op) != hipSuccess ||
+      hipMalloc(&wt, (size_t)s * Kp * op) != hipSuccess || hipMalloc(&bias, (size_t)s * 8) != hipSuccess) {
+    cleanup();
+    return fail(BSADMM_ENOMEM, "hipMalloc failed in rff_map");
+  }
+  hipError_t e = bs::prep_rows(precision, X, n, d, Kp, xop, nullptr, st);
+  if (e == hipSuccess) e = bs::prep_w(precision, W, b, d, s, Kp, wt, bias, nullptr, st);
+  if (e == hipSuccess) e = bs::regen(precision, xop, n, wt, s, bias, Kp, std::sqrt(2.0 / (double)s),
+                                     Z_out, s, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) return hip_fail(e, "rff_map");
+  if (e2 != hipSuccess) return hip_fail(e2, "rff_map synchronize");
+  return BSADMM_OK;
+}
+
+}  // extern "C"

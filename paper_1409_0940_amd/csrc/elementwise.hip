@@ -1,0 +1,201 @@
+// Elementwise steps of Algorithm 1 on the FP64 ADMM state.
+//
+// Row side (n x m, padded to mp columns; pad columns stay zero):
+//   row_pre  : O = prox_{tau V}(O-bar - nu)                        (step 4)
+//              R = Delta-bar / (C+1) + nu as product operand        (step 17)
+//   row_post : Delta-bar = O - sum_j O'_ij                         (steps 11, 20, 25)
+//              O-bar = C/(C+1) O + sum_j O'_ij / (C+1)             (steps 12, 22)
+//              nu += O - O-bar                                       (step 33)
+// Column side (padded feature index x mp):
+//   col_pre  : W = prox_{kappa r}(W-bar - mu)                        (step 6)
+//   col_post : W-bar = (W + sum_i W'_i) / (R+1), summed in order i   (steps 28-29)
+//              mu += W - W-bar, mu'_i += W'_i - W-bar (new W-bar, as in the
+//              block-splitting update equations)
+#include "common.h"
+#include "kernels.h"
+
+namespace bs {
+
+namespace {
+
+inline unsigned grid_for(int64_t count) {
+  int64_t g = (count + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (unsigned)g;
+}
+
+#define GRID_STRIDE(e, total)                                                   \
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (total); \
+       e += (int64_t)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ double prox_loss(int loss, double v, double y, double tau) {
+  if (loss == 0) return (v + 2.0 * tau * y) / (1.0 + 2.0 * tau);  // ||y - o||^2
+  // max(0, 1 - y o): move by y * clamp(1 - y v, 0, tau)
+  double g = 1.0 - y * v;
+  g = g < 0.0 ? 0.0 : (g > tau ? tau : g);
+  return v + y * g;
+}
+
+template <typename OP>
+__global__ void row_pre_kernel(int loss, double tau, double cfac, int64_t n, int64_t m, int64_t mp,
+                               const float* __restrict__ Y, const double* __restrict__ Obar,
+                               const double* __restrict__ nu, const double* __restrict__ Dbar,
+                               double* __restrict__ O, OP* __restrict__ Rop) {
+  GRID_STRIDE(e, n * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    const double nv = nu[o];
+    O[o] = prox_loss(loss, Obar[o] - nv, (double)Y[e], tau);
+    Rop[o] = cvt_from_double<OP>(Dbar[o] * cfac + nv);
+  }
+}
+
+__global__ void row_post_kernel(int64_t n, int64_t m, int64_t mp, double a, double bfac,
+                                const double* __restrict__ O, const double* __restrict__ P,
+                                double* __restrict__ Obar, double* __restrict__ nu,
+                                double* __restrict__ Dbar) {
+  GRID_STRIDE(e, n * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    const double ov = O[o], pv = P[o];
+    const double ob = a * ov + bfac * pv;
+    Dbar[o] = ov - pv;
+    Obar[o] = ob;
+    nu[o] = nu[o] + ov - ob;
+  }
+}
+
+__global__ void col_pre_kernel(double kappa, int64_t rows, int64_t m, int64_t mp,
+                               const double* __restrict__ Wbar, const double* __restrict__ mu,
+                               double* __restrict__ Wc) {
+  const double den = 1.0 / (1.0 + 2.0 * kappa);
+  GRID_STRIDE(e, rows * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    Wc[o] = (Wbar[o] - mu[o]) * den;
+  }
+}
+
+__global__ void col_post_kernel(int R, int64_t rows, int64_t m, int64_t mp,
+                                const double* __restrict__ Wc, const double* __restrict__ Wp,
+                                double* __restrict__ Wbar, double* __restrict__ mu,
+                                double* __restrict__ mup) {
+  const int64_t per = rows * mp;
+  const double inv = 1.0 / (double)(R + 1);
+  GRID_STRIDE(e, rows * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    const double wc = Wc[o];
+    double sum = wc;
+    for (int i = 0; i < R; ++i) sum += Wp[(int64_t)i * per + o];
+    const double wb = sum * inv;
+    Wbar[o] = wb;
+    mu[o] = mu[o] + wc - wb;
+    for (int i = 0; i < R; ++i) {
+      const int64_t oi = (int64_t)i * per + o;
+      mup[oi] = mup[oi] + Wp[oi] - wb;
+    }
+  }
+}
+
+__global__ void unpad_kernel(const double* __restrict__ src, int64_t rows, int64_t m, int64_t mp,
+                             double* __restrict__ dst) {
+  GRID_STRIDE(e, rows * m) {
+    const int64_t r = e / m, c = e - r * m;
+    dst[e] = src[r * mp + c];
+  }
+}
+
+__global__ void pad_kernel(const double* __restrict__ src, int64_t rows, int64_t m, int64_t mp,
+                           double* __restrict__ dst) {
+  GRID_STRIDE(e, rows * m) {
+    const int64_t r = e / m, c = e - r * m;
+    dst[r * mp + c] = src[e];
+  }
+}
+
+template <typename OP>
+__global__ void to_op_kernel(const double* __restrict__ src, int64_t count, OP* __restrict__ dst) {
+  GRID_STRIDE(e, count) dst[e] = cvt_from_double<OP>(src[e]);
+}
+
+__global__ void scores_kernel(const double* __restrict__ P, int64_t rows, int64_t m, int64_t mp,
+                              float* __restrict__ out) {
+  GRID_STRIDE(e, rows * m) {
+    const int64_t r = e / m, c = e - r * m;
+    out[e] = (float)P[r * mp + c];
+  }
+}
+
+}  // namespace
+
+hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int64_t m, int64_t mp,
+                   const float* Y, const double* Obar, const double* nu, const double* Dbar,
+                   double* O, void* Rop, hipStream_t st) {
+  unsigned g = grid_for(n * m);
+  if (prec == BS_PREC_F64)
+    row_pre_kernel<double><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
+                                               (double*)Rop);
+  else if (prec == BS_PREC_F32)
+    row_pre_kernel<float><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
+                                              (float*)Rop);
+  else
+    row_pre_kernel<uint16_t><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
+                                                 (uint16_t*)Rop);
+  return hipGetLastError();
+}
+
+hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, const double* P,
+                    double* Obar, double* nu, double* Dbar, hipStream_t st) {
+  const double a = (double)C / (double)(C + 1), bfac = 1.0 / (double)(C + 1);
+  row_post_kernel<<<grid_for(n * m), 256, 0, st>>>(n, m, mp, a, bfac, O, P, Obar, nu, Dbar);
+  return hipGetLastError();
+}
+
+hipError_t col_pre(double kappa, int64_t s, int64_t m, int64_t mp, const double* Wbar,
+                   const double* mu, double* Wc, hipStream_t st) {
+  col_pre_kernel<<<grid_for(s * m), 256, 0, st>>>(kappa, s, m, mp, Wbar, mu, Wc);
+  return hipGetLastError();
+}
+
+hipError_t col_post(int R, int64_t s, int64_t m, int64_t mp, const double* Wc, const double* Wp,
+                    double* Wbar, double* mu, double* mup, hipStream_t st) {
+  col_post_kernel<<<grid_for(s * m), 256, 0, st>>>(R, s, m, mp, Wc, Wp, Wbar, mu, mup);
+  return hipGetLastError();
+}
+
+hipError_t unpad(const double* src, int64_t rows, int64_t m, int64_t mp, double* dst,
+                 hipStream_t st) {
+  if (rows * m == 0) return hipSuccess;
+  unpad_kernel<<<grid_for(rows * m), 256, 0, st>>>(src, rows, m, mp, dst);
+  return hipGetLastError();
+}
+
+hipError_t pad(const double* src, int64_t rows, int64_t m, int64_t mp, double* dst,
+               hipStream_t st) {
+  if (rows * m == 0) return hipSuccess;
+  pad_kernel<<<grid_for(rows * m), 256, 0, st>>>(src, rows, m, mp, dst);
+  return hipGetLastError();
+}
+
+hipError_t to_op(int prec, const double* src, int64_t count, void* dst, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  unsigned g = grid_for(count);
+  if (prec == BS_PREC_F64)
+    to_op_kernel<double><<<g, 256, 0, st>>>(src, count, (double*)dst);
+  else if (prec == BS_PREC_F32)
+    to_op_kernel<float><<<g, 256, 0, st>>>(src, count, (float*)dst);
+  else
+    to_op_kernel<uint16_t><<<g, 256, 0, st>>>(src, count, (uint16_t*)dst);
+  return hipGetLastError();
+}
+
+hipError_t scores_out(const double* P, int64_t rows, int64_t m, int64_t mp, float* out,
+                      hipStream_t st) {
+  if (rows * m == 0) return hipSuccess;
+  scores_kernel<<<grid_for(rows * m), 256, 0, st>>>(P, rows, m, mp, out);
+  return hipGetLastError();
+}
+
+}  // namespace bs

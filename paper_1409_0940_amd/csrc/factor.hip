@@ -1,0 +1,363 @@
+// FP64 factor cache of eq. cache and the graph-projection solve of eq. gpWij.
+//
+// The paper caches either Q_ij = (Z_ij^T Z_ij + I)^{-1} or its Cholesky
+// factors.  Here the explicit inverse is cached: the per-iteration solve
+// W'_ij = Q_ij rhs_ij becomes one batched FP64 product with no sequential
+// triangular sweeps, and its cost (2 s_j^2 m flops, s_j^2 doubles streamed)
+// is the same as two triangular solves.  Setup, per matrix A = I + G:
+//   1. blocked right-looking Cholesky A = L L^T (64 x 64 tiles),
+//   2. X = L^{-1} by block forward substitution, column tiles in parallel,
+//   3. Q = X^T X, written as a full symmetric matrix.
+// Every 64 x 64 x 64 tile product runs on the FP64 16x16x4 MFMA.
+#include "common.h"
+#include "kernels.h"
+
+#include <algorithm>
+
+namespace bs {
+
+namespace {
+
+constexpr int NB = 64;
+constexpr int LDP = NB + 1;  // LDS row pitch (doubles)
+
+typedef double tile_t[NB][LDP];
+
+// Load a 64 x 64 tile (row-major, leading dimension ld) into LDS, optionally
+// transposed.  256 threads.
+__device__ __forceinline__ void load_tile(tile_t& dst, const double* __restrict__ src, int64_t ld,
+                                          bool transpose) {
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    int r = e >> 6, c = e & 63;
+    double v = src[r * ld + c];
+    if (transpose)
+      dst[c][r] = v;
+    else
+      dst[r][c] = v;
+  }
+}
+
+// acc += A B^T over k < 64, A and B in LDS as [row][k].  Wave w owns the
+// 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 MFMA tiles.
+__device__ __forceinline__ void tile_mma_nt(v4d (&acc)[2][2], const tile_t& A, const tile_t& B) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int fr = lane & 15, fg = lane >> 4;
+#pragma unroll 4
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    double a0 = A[wm * 32 + fr][k0 + fg];
+    double a1 = A[wm * 32 + 16 + fr][k0 + fg];
+    double b0 = B[wn * 32 + fr][k0 + fg];
+    double b1 = B[wn * 32 + 16 + fr][k0 + fg];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void zero_acc(v4d (&acc)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
+}
+
+// Visit the elements of the accumulator: f(row, col, value) in tile coords.
+template <typename F>
+__device__ __forceinline__ void for_acc(const v4d (&acc)[2][2], F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int fr = lane & 15, fg = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        f(wm * 32 + i * 16 + acc_row<double>(fg, r), wn * 32 + j * 16 + fr, acc[i][j][r]);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal tile kb: unblocked Cholesky in LDS, then the inverse of the
+// triangular factor.  One workgroup per matrix.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+potrf_diag_kernel(double* __restrict__ slots, int64_t S, int kb, double* __restrict__ dinv,
+                  int* __restrict__ flag) {
+  __shared__ tile_t L;
+  __shared__ tile_t Li;
+  double* A = slots + (int64_t)blockIdx.x * S * S + (int64_t)kb * NB * S + (int64_t)kb * NB;
+  const int tid = threadIdx.x;
+  load_tile(L, A, S, false);
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (tid == 0) {
+      double dj = L[j][j];
+      if (!(dj > 0.0)) {
+        atomicOr(flag, 2);
+        dj = 1.0;
+      }
+      L[j][j] = __builtin_sqrt(dj);
+    }
+    __syncthreads();
+    const double inv = 1.0 / L[j][j];
+    for (int i = j + 1 + tid; i < NB; i += 256) L[i][j] *= inv;
+    __syncthreads();
+    // trailing update of the lower triangle: L[i][k] -= L[i][j] L[k][j], j < k <= i
+    const int m = NB - 1 - j;
+    for (int e = tid; e < m * m; e += 256) {
+      int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) L[i][k] -= L[i][j] * L[k][j];
+    }
+    __syncthreads();
+  }
+  // Li = L^{-1}, one column per thread (forward substitution)
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = 0; i < c; ++i) Li[i][c] = 0.0;
+    Li[c][c] = 1.0 / L[c][c];
+    for (int i = c + 1; i < NB; ++i) {
+      double acc = 0.0;
+      for (int k = c; k < i; ++k) acc += L[i][k] * Li[k][c];
+      Li[i][c] = -acc / L[i][i];
+    }
+  }
+  __syncthreads();
+  double* D = dinv + (int64_t)blockIdx.x * S * NB + (int64_t)kb * NB * NB;
+  for (int e = tid; e < NB * NB; e += 256) {
+    int r = e >> 6, c = e & 63;
+    A[r * S + c] = (c <= r) ? L[r][c] : 0.0;
+    D[e] = Li[r][c];
+  }
+}
+
+// Panel: L[ib][kb] = A[ib][kb] Linv_kk^T for ib > kb.
+__global__ void __launch_bounds__(256)
+trsm_kernel(double* __restrict__ slots, int64_t S, int kb, const double* __restrict__ dinv) {
+  __shared__ tile_t At;
+  __shared__ tile_t Bt;
+  const int ib = kb + 1 + blockIdx.x;
+  double* base = slots + (int64_t)blockIdx.y * S * S;
+  double* T = base + (int64_t)ib * NB * S + (int64_t)kb * NB;
+  load_tile(At, T, S, false);
+  load_tile(Bt, dinv + (int64_t)blockIdx.y * S * NB + (int64_t)kb * NB * NB, NB, false);
+  __syncthreads();
+  v4d acc[2][2];
+  zero_acc(acc);
+  tile_mma_nt(acc, At, Bt);
+  for_acc(acc, [&](int r, int c, double v) { T[r * S + c] = v; });
+}
+
+// Trailing update: A[ib][jb] -= L[ib][kb] L[jb][kb]^T for kb < jb <= ib.
+__global__ void __launch_bounds__(256)
+syrk_kernel(double* __restrict__ slots, int64_t S, int kb) {
+  __shared__ tile_t At;
+  __shared__ tile_t Bt;
+  const int64_t t = blockIdx.x;
+  int64_t a = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= t) ++a;
+  while (a * (a + 1) / 2 > t) --a;
+  const int64_t b = t - a * (a + 1) / 2;
+  const int64_t ib = kb + 1 + a, jb = kb + 1 + b;
+  double* base = slots + (int64_t)blockIdx.y * S * S;
+  load_tile(At, base + ib * NB * S + (int64_t)kb * NB, S, false);
+  load_tile(Bt, base + jb * NB * S + (int64_t)kb * NB, S, false);
+  __syncthreads();
+  v4d acc[2][2];
+  zero_acc(acc);
+  tile_mma_nt(acc, At, Bt);
+  double* T = base + ib * NB * S + jb * NB;
+  for_acc(acc, [&](int r, int c, double v) { T[r * S + c] -= v; });
+}
+
+// Block row i of X = L^{-1}: X_ik = -Linv_ii sum_{j=k}^{i-1} L_ij X_jk for
+// k < i, and X_ii = Linv_ii.  Launch i covers k = 0..i.
+__global__ void __launch_bounds__(256)
+linv_row_kernel(const double* __restrict__ slots, int64_t S, int i,
+                const double* __restrict__ dinv, double* __restrict__ work) {
+  __shared__ tile_t At;
+  __shared__ tile_t Bt;
+  const int k = blockIdx.x;
+  const double* Lb = slots + (int64_t)blockIdx.y * S * S;
+  double* Xb = work + (int64_t)blockIdx.y * S * S;
+  const double* Dii = dinv + (int64_t)blockIdx.y * S * NB + (int64_t)i * NB * NB;
+  double* out = Xb + (int64_t)i * NB * S + (int64_t)k * NB;
+  if (k == i) {
+    for (int e = threadIdx.x; e < NB * NB; e += 256) out[(e >> 6) * S + (e & 63)] = Dii[e];
+    return;
+  }
+  v4d acc[2][2];
+  zero_acc(acc);
+  for (int j = k; j < i; ++j) {
+    load_tile(At, Lb + (int64_t)i * NB * S + (int64_t)j * NB, S, false);
+    load_tile(Bt, Xb + (int64_t)j * NB * S + (int64_t)k * NB, S, true);
+    __syncthreads();
+    tile_mma_nt(acc, At, Bt);
+    __syncthreads();
+  }
+  // Bt <- acc^T so that the second product reads it as [col][k]
+  for_acc(acc, [&](int r, int c, double v) { Bt[c][r] = v; });
+  load_tile(At, Dii, NB, false);
+  __syncthreads();
+  zero_acc(acc);
+  tile_mma_nt(acc, At, Bt);
+  for_acc(acc, [&](int r, int c, double v) { out[r * S + c] = -v; });
+}
+
+// Q_ab = sum_{c >= a} X_ca^T X_cb for a >= b; Q_ba = Q_ab^T.
+__global__ void __launch_bounds__(256)
+xtx_kernel(const double* __restrict__ work, int64_t S, double* __restrict__ slots) {
+  __shared__ tile_t At;
+  __shared__ tile_t Bt;
+  const int64_t t = blockIdx.x;
+  int64_t a = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= t) ++a;
+  while (a * (a + 1) / 2 > t) --a;
+  const int64_t b = t - a * (a + 1) / 2;
+  const int64_t nblk = S / NB;
+  const double* Xb = work + (int64_t)blockIdx.y * S * S;
+  double* Qb = slots + (int64_t)blockIdx.y * S * S;
+  v4d acc[2][2];
+  zero_acc(acc);
+  for (int64_t c = a; c < nblk; ++c) {
+    load_tile(At, Xb + c * NB * S + a * NB, S, true);
+    load_tile(Bt, Xb + c * NB * S + b * NB, S, true);
+    __syncthreads();
+    tile_mma_nt(acc, At, Bt);
+    __syncthreads();
+  }
+  // On a diagonal tile only the lower half is written (and mirrored), so each
+  // element has exactly one writer.
+  for_acc(acc, [&](int r, int cc, double v) {
+    if (a != b || r >= cc) {
+      Qb[(a * NB + r) * S + b * NB + cc] = v;
+      Qb[(b * NB + cc) * S + a * NB + r] = v;
+    }
+  });
+}
+
+// Identity in the pad rows / columns [sj, S) of each slot.
+__global__ void identity_pad_kernel(double* __restrict__ slot, int64_t S, int64_t sj) {
+  const int64_t total = S * S;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e / S, c = e - r * S;
+    if (r >= sj || c >= sj) slot[e] = (r == c) ? 1.0 : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Projection solve W'_b = Q_b rhs_b for block b = (i, j).  A wave owns 16
+// rows of W'_b and up to NTC column tiles; a lane loads 4 adjacent doubles of
+// a row of Q and the 4 matching rhs rows feed 4 MFMA instructions.
+// ---------------------------------------------------------------------------
+template <int P, int NTC>
+__global__ void __launch_bounds__(256)
+solve_kernel(const double* __restrict__ Q, int64_t S, int C, int b0, const int64_t* __restrict__ coff,
+             const int64_t* __restrict__ sjs, int64_t spad, int64_t mp,
+             const double* __restrict__ rhs, double* __restrict__ Wp, double* __restrict__ U,
+             typename Prec<P>::op_t* __restrict__ Wop) {
+  using op_t = typename Prec<P>::op_t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int b = b0 + (int)blockIdx.y;
+  const int i = b / C, j = b - i * C;
+  const int64_t sj = sjs[j];
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  if (row0 >= sj) return;
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const double* Qb = Q + (int64_t)b * S * S;
+  const int64_t base = ((int64_t)i * spad + coff[j]) * mp;
+  const double* rb = rhs + base;
+  const int64_t k16 = (sj + 15) / 16 * 16;  // Q pad columns are zero off the diagonal
+  const double* qrow = Qb + (row0 + fr) * S + 4 * fg;
+  v4d acc[NTC];
+#pragma unroll
+  for (int t = 0; t < NTC; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[t][r] = 0.0;
+  for (int64_t k0 = 0; k0 < k16; k0 += 16) {
+    Frag<BS_PREC_F64> a = load_frag<BS_PREC_F64>(qrow + k0);
+    const double* rk = rb + (k0 + 4 * fg) * mp + fr;
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const int nt = nc0 + t;
+      if (nt < ntiles) {
+        Frag<BS_PREC_F64> bb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb.v[q] = rk[q * mp + nt * 16];
+        mfma_step(acc[t], a, bb);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NTC; ++t) {
+    const int nt = nc0 + t;
+    if (nt >= ntiles) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + acc_row<double>(fg, r);
+      if (row < sj) {
+        const int64_t o = base + row * mp + nt * 16 + fr;
+        const double w = acc[t][r];
+        Wp[o] = w;
+        U[o] = rhs[o] - w;
+        Wop[o] = cvt_from_double<op_t>(w);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t identity_pad(double* slots, int batch, int64_t S, const int64_t* sj_host,
+                        hipStream_t st) {
+  for (int b = 0; b < batch; ++b) {
+    if (sj_host[b] >= S) continue;
+    unsigned g = (unsigned)std::min<int64_t>((S * S + 255) / 256, 16384);
+    identity_pad_kernel<<<g, 256, 0, st>>>(slots + (int64_t)b * S * S, S, sj_host[b]);
+  }
+  return hipGetLastError();
+}
+
+hipError_t spd_inverse(double* slots, int batch, int64_t S, double* work, double* dinv, int* flag,
+                       hipStream_t st) {
+  const int nblk = (int)(S / NB);
+  for (int kb = 0; kb < nblk; ++kb) {
+    potrf_diag_kernel<<<batch, 256, 0, st>>>(slots, S, kb, dinv, flag);
+    const int T = nblk - kb - 1;
+    if (T > 0) {
+      trsm_kernel<<<dim3(T, batch), 256, 0, st>>>(slots, S, kb, dinv);
+      syrk_kernel<<<dim3(T * (T + 1) / 2, batch), 256, 0, st>>>(slots, S, kb);
+    }
+  }
+  for (int i = 0; i < nblk; ++i)
+    linv_row_kernel<<<dim3(i + 1, batch), 256, 0, st>>>(slots, S, i, dinv, work);
+  xtx_kernel<<<dim3(nblk * (nblk + 1) / 2, batch), 256, 0, st>>>(work, S, slots);
+  return hipGetLastError();
+}
+
+hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, const int64_t* coff,
+                 const int64_t* sjs, int64_t spad, int64_t mp, const double* rhs, double* Wp,
+                 double* U, void* Wop, hipStream_t st) {
+  constexpr int NTC = 4;
+  const int ntiles = (int)(mp / 16);
+  if (nb <= 0) return hipSuccess;
+  dim3 g((unsigned)(S / 64), (unsigned)nb, (unsigned)((ntiles + NTC - 1) / NTC));
+  if (prec == BS_PREC_F64)
+    solve_kernel<BS_PREC_F64, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
+                                                      (double*)Wop);
+  else if (prec == BS_PREC_F32)
+    solve_kernel<BS_PREC_F32, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
+                                                      (float*)Wop);
+  else
+    solve_kernel<BS_PREC_BF16, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
+                                                       (uint16_t*)Wop);
+  return hipGetLastError();
+}
+
+}  // namespace bs

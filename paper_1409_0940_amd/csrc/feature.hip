@@ -1,0 +1,291 @@
+// Feature regeneration: the transform T[X_i, j] of Algorithm 1 (step 15)
+// for random Fourier features, Z = sqrt(2/s) cos(X W + b) (section
+// "Randomized Kernel Maps"; the transform is one GEMM followed by an
+// entrywise cosine).  One MFMA GEMM per launch with the phase offset and the
+// range-reduced cosine fused into its epilogue.
+#include "common.h"
+#include "kernels.h"
+
+namespace bs {
+
+namespace {
+
+constexpr int BM = 128;          // rows of Z per workgroup
+constexpr int BN = 128;          // features of Z per workgroup
+constexpr int KROW_BYTES = 128;  // bytes of k per LDS row and chunk
+constexpr int LDS_PITCH = KROW_BYTES + 16;
+constexpr int NTHREADS = 256;
+constexpr int GROUP_M = 8;
+
+template <int P> constexpr int bk_elems() { return KROW_BYTES / (int)sizeof(typename Prec<P>::op_t); }
+
+// ---------------------------------------------------------------------------
+// Operand preparation
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void prep_rows_kernel(const float* __restrict__ src, int64_t rows, int64_t d,
+                                 int64_t Kp, typename Prec<P>::op_t* __restrict__ dst,
+                                 int* __restrict__ flag) {
+  using op_t = typename Prec<P>::op_t;
+  int64_t total = rows * Kp;
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = e / Kp, k = e - r * Kp;
+    float v = (k < d) ? src[r * d + k] : 0.0f;
+    if (!__builtin_isfinite(v)) bad = 1;
+    dst[e] = cvt_from_float<op_t>(v);
+  }
+  if (bad && flag) atomicOr(flag, 1);
+}
+
+// W is d x s (ld = s); Wt is s x Kp.  32 x 32 tiles through LDS.
+template <int P>
+__global__ void prep_w_kernel(const float* __restrict__ W, int64_t d, int64_t s, int64_t Kp,
+                              typename Prec<P>::op_t* __restrict__ Wt, int* __restrict__ flag) {
+  using op_t = typename Prec<P>::op_t;
+  __shared__ float tile[32][33];
+  int64_t f0 = (int64_t)blockIdx.x * 32, k0 = (int64_t)blockIdx.y * 32;
+  int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: ty 0..7
+  int bad = 0;
+  for (int yy = ty; yy < 32; yy += 8) {
+    int64_t k = k0 + yy, f = f0 + tx;
+    float v = (k < d && f < s) ? W[k * s + f] : 0.0f;
+    if (!__builtin_isfinite(v)) bad = 1;
+    tile[yy][tx] = v;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    int64_t f = f0 + yy, k = k0 + tx;
+    if (f < s && k < Kp) Wt[f * Kp + k] = cvt_from_float<op_t>(tile[tx][yy]);
+  }
+  if (bad && flag) atomicOr(flag, 1);
+}
+
+template <typename B>
+__global__ void prep_bias_kernel(const float* __restrict__ b, int64_t s, B* __restrict__ out,
+                                 int* __restrict__ flag) {
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f < s) {
+    float v = b[f];
+    if (!__builtin_isfinite(v) && flag) atomicOr(flag, 1);
+    out[f] = (B)v;
+  }
+}
+
+__global__ void check_finite_kernel(const float* __restrict__ p, int64_t count, int* flag) {
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    if (!__builtin_isfinite(p[e])) bad = 1;
+  if (bad) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Regeneration GEMM.  Xp (rows x Kp) and Wt (cols x Kp) are both k-contiguous.
+// A 256-thread workgroup computes a 128 x 128 tile of Z; its 4 waves each own
+// a 64 x 64 quadrant made of 4 x 4 MFMA 16 x 16 tiles.  k advances in chunks
+// of 128 bytes staged through double-buffered LDS; the next chunk's global
+// loads are in flight while the current one feeds the MFMAs.
+// ---------------------------------------------------------------------------
+template <int P, typename ZT>
+__global__ void __launch_bounds__(NTHREADS, 2)
+regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t rows,
+             const typename Prec<P>::op_t* __restrict__ Wt, int64_t cols,
+             const typename Prec<P>::acc_t* __restrict__ bias, int64_t Kp,
+             typename Prec<P>::acc_t scale, ZT* __restrict__ Z, int64_t ldz) {
+  using op_t = typename Prec<P>::op_t;
+  using acc_t = typename Prec<P>::acc_t;
+  using accv = typename Prec<P>::accv;
+  constexpr int VEC = Prec<P>::VEC;
+  constexpr int KC = Prec<P>::KC;
+  constexpr int BK = bk_elems<P>();
+  constexpr int STEPS = BK / KC;  // fragment steps per chunk
+
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2][BM * LDS_PITCH];
+
+  const int tiles_m = (int)((rows + BM - 1) / BM);
+  const int tiles_n = (int)((cols + BN - 1) / BN);
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_group = GROUP_M * tiles_n;
+  const int g = t / per_group;
+  const int first_m = g * GROUP_M;
+  const int gsize = min(GROUP_M, tiles_m - first_m);
+  const int tm = first_m + (t % per_group) % gsize;
+  const int tn = (t % per_group) / gsize;
+  const int64_t row0 = (int64_t)tm * BM, col0 = (int64_t)tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // global -> register staging: 128 rows x 128 bytes per operand = 1024 x 16 B
+  const unsigned char* gA[4];
+  const unsigned char* gB[4];
+  int ldsoff[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int idx = tid + NTHREADS * i;
+    int r = idx >> 3, seg = idx & 7;
+    int64_t ra = min(row0 + r, rows - 1);
+    int64_t rb = min(col0 + r, cols - 1);
+    gA[i] = reinterpret_cast<const unsigned char*>(Xp + ra * Kp) + seg * 16;
+    gB[i] = reinterpret_cast<const unsigned char*>(Wt + rb * Kp) + seg * 16;
+    ldsoff[i] = r * LDS_PITCH + seg * 16;
+  }
+  const int64_t nchunks = Kp / BK;
+  uint4 ra[4], rb[4];
+  auto gload = [&](int64_t c) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ra[i] = *reinterpret_cast<const uint4*>(gA[i] + c * KROW_BYTES);
+      rb[i] = *reinterpret_cast<const uint4*>(gB[i] + c * KROW_BYTES);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[i]]) = ra[i];
+      *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[i]]) = rb[i];
+    }
+  };
+
+  accv acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int fr = lane & 15, fg = lane >> 4;
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const int buf = (int)(c & 1);
+    if (c + 1 < nchunks) gload(c + 1);
+#pragma unroll
+    for (int ks = 0; ks < STEPS; ++ks) {
+      Frag<P> fa[4], fb[4];
+      const int kbyte = (ks * KC + VEC * fg) * (int)sizeof(op_t);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        fa[i] = load_frag<P>(reinterpret_cast<const op_t*>(
+            &lds[buf][0][(wm * 64 + i * 16 + fr) * LDS_PITCH + kbyte]));
+        fb[i] = load_frag<P>(reinterpret_cast<const op_t*>(
+            &lds[buf][1][(wn * 64 + i * 16 + fr) * LDS_PITCH + kbyte]));
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mfma_step(acc[i][j], fa[i], fb[j]);
+    }
+    if (c + 1 < nchunks) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds D[acc_row(lane / 16, r)][lane % 16] of each 16 x 16 tile.
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t col = col0 + wn * 64 + j * 16 + fr;
+    const bool cok = col < cols;
+    const acc_t bcol = cok ? bias[col] : (acc_t)0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + wm * 64 + i * 16 + acc_row<acc_t>(fg, r);
+        if (cok && row < rows) {
+          acc_t th = acc[i][j][r] + bcol;
+          acc_t z;
+          if constexpr (P == BS_PREC_F64)
+            z = scale * cos(th);
+          else
+            z = scale * rff_cosf(th);
+          if constexpr (sizeof(ZT) == 2)
+            Z[row * ldz + col] = f32_to_bf16((float)z);
+          else
+            Z[row * ldz + col] = (ZT)z;
+        }
+      }
+    }
+  }
+}
+
+inline unsigned grid_1d(int64_t count, int threads, int64_t cap = 65536) {
+  int64_t g = (count + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+int64_t padded_k(int prec, int64_t d) {
+  int64_t bk = KROW_BYTES / (int64_t)op_bytes(prec);
+  return ((d + bk - 1) / bk) * bk;
+}
+
+size_t op_bytes(int prec) {
+  return prec == BS_PREC_F64 ? 8 : (prec == BS_PREC_F32 ? 4 : 2);
+}
+
+hipError_t prep_rows(int prec, const float* src, int64_t rows, int64_t d, int64_t Kp, void* dst,
+                     int* flag, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  unsigned g = grid_1d(rows * Kp, 256);
+  if (prec == BS_PREC_F64)
+    prep_rows_kernel<BS_PREC_F64><<<g, 256, 0, st>>>(src, rows, d, Kp, (double*)dst, flag);
+  else if (prec == BS_PREC_F32)
+    prep_rows_kernel<BS_PREC_F32><<<g, 256, 0, st>>>(src, rows, d, Kp, (float*)dst, flag);
+  else
+    prep_rows_kernel<BS_PREC_BF16><<<g, 256, 0, st>>>(src, rows, d, Kp, (uint16_t*)dst, flag);
+  return hipGetLastError();
+}
+
+hipError_t prep_w(int prec, const float* W, const float* b, int64_t d, int64_t s, int64_t Kp,
+                  void* Wt, void* bias, int* flag, hipStream_t st) {
+  dim3 g((unsigned)((s + 31) / 32), (unsigned)((Kp + 31) / 32));
+  if (prec == BS_PREC_F64) {
+    prep_w_kernel<BS_PREC_F64><<<g, 256, 0, st>>>(W, d, s, Kp, (double*)Wt, flag);
+    prep_bias_kernel<double><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (double*)bias, flag);
+  } else if (prec == BS_PREC_F32) {
+    prep_w_kernel<BS_PREC_F32><<<g, 256, 0, st>>>(W, d, s, Kp, (float*)Wt, flag);
+    prep_bias_kernel<float><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (float*)bias, flag);
+  } else {
+    prep_w_kernel<BS_PREC_BF16><<<g, 256, 0, st>>>(W, d, s, Kp, (uint16_t*)Wt, flag);
+    prep_bias_kernel<float><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (float*)bias, flag);
+  }
+  return hipGetLastError();
+}
+
+hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  check_finite_kernel<<<grid_1d(count, 256, 16384), 256, 0, st>>>(p, count, flag);
+  return hipGetLastError();
+}
+
+hipError_t regen(int prec, const void* Xp, int64_t rows, const void* Wt, int64_t cols,
+                 const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
+                 hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  int64_t tiles = ((rows + BM - 1) / BM) * ((cols + BN - 1) / BN);
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 g((unsigned)tiles);
+  if (prec == BS_PREC_F64)
+    regen_kernel<BS_PREC_F64, double><<<g, NTHREADS, 0, st>>>(
+        (const double*)Xp, rows, (const double*)Wt, cols, (const double*)bias, Kp, scale,
+        (double*)Z, ldz);
+  else if (prec == BS_PREC_F32)
+    regen_kernel<BS_PREC_F32, float><<<g, NTHREADS, 0, st>>>(
+        (const float*)Xp, rows, (const float*)Wt, cols, (const float*)bias, Kp, (float)scale,
+        (float*)Z, ldz);
+  else
+    regen_kernel<BS_PREC_BF16, uint16_t><<<g, NTHREADS, 0, st>>>(
+        (const uint16_t*)Xp, rows, (const uint16_t*)Wt, cols, (const float*)bias, Kp,
+        (float)scale, (uint16_t*)Z, ldz);
+  return hipGetLastError();
+}
+
+}  // namespace bs

@@ -1,0 +1,88 @@
+// Host-side launchers of the HIP kernels (internal to libbsadmm).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bs {
+
+// Operand row width (k padded) for a precision: multiple of the K chunk.
+int64_t padded_k(int prec, int64_t d);
+size_t op_bytes(int prec);
+
+// Rows [0, rows) of a float32 matrix (ld = d) -> operand layout (ld = Kp,
+// zero padded).  Sets *flag |= 1 if a value is not finite.
+hipError_t prep_rows(int prec, const float* src, int64_t rows, int64_t d, int64_t Kp,
+                     void* dst, int* flag, hipStream_t st);
+// W (d x s, ld = s) -> Wt (s x Kp), transposed and padded; bias copy.
+hipError_t prep_w(int prec, const float* W, const float* b, int64_t d, int64_t s, int64_t Kp,
+                  void* Wt, void* bias, int* flag, hipStream_t st);
+// Non-finite check of a float32 array.
+hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st);
+
+// Z[r][f] = scale * cos(sum_k Xp[r][k] Wt[f][k] + bias[f]) for r < rows,
+// f < cols; Z has leading dimension ldz and the operand element type
+// (double / float / bf16 bits).
+hipError_t regen(int prec, const void* Xp, int64_t rows, const void* Wt, int64_t cols,
+                 const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
+                 hipStream_t st);
+
+// The padded feature index: feature block j occupies [coff_j, coff_j + s_j)
+// with coff_j a multiple of 64; spad is the padded total; pad entries are 0.
+
+// Partial transpose products for one row block:
+// part[sp][f][c] = sum_{r in split sp} Z[r][f] * Rop[r][c], f < spad, c < mp.
+hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t spad,
+                       const void* Rop, int64_t mp, int64_t split_rows, void* part,
+                       hipStream_t st);
+// For row blocks i in [i0, i1): rhs_i = W-bar - mu'_i + U_i + sum_sp part_i[sp]
+// (part laid out [i][sp < nsplit_max][spad][mp]; the split count of block i
+// follows from the row partition of n into R blocks).
+hipError_t reduce_rhs(int prec, const void* part, int64_t nsplit_max, int64_t n, int R, int i0,
+                      int i1, int64_t split_rows, int64_t spad, int64_t mp, const double* Wbar,
+                      const double* mup, const double* U, double* rhs, hipStream_t st);
+// Pout[r][c] = sum_f Z[r][f] * Wop[f][c] for r < rows, c < mp, f < spad.
+hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t spad, const void* Wop,
+              int64_t mp, double* Pout, hipStream_t st);
+// Gram of one block (rows x [coff, coff + sj)) of Z into slot (ld = S):
+// lower 64 x 64 tiles of I + Z^T Z.
+hipError_t gram(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t coff, int64_t sj,
+                double* slot, int64_t S, hipStream_t st);
+
+// Batched FP64 factor cache.  `slots` holds `batch` matrices of S x S
+// (S multiple of 64) whose lower triangle is I + G; on exit it holds the
+// full symmetric inverse.  `work` needs batch * S * S doubles, `dinv`
+// batch * S * 64 doubles.  Pivot failures set *flag |= 2.
+hipError_t identity_pad(double* slots, int batch, int64_t S, const int64_t* sj_host,
+                        hipStream_t st);
+hipError_t spd_inverse(double* slots, int batch, int64_t S, double* work, double* dinv,
+                       int* flag, hipStream_t st);
+
+// W'_b = Q_b rhs_b for blocks b in [b0, b0 + nb) (b = i * C + j); U = rhs - W';
+// Wop = W' as operand.  coff / sjs are device arrays of length C.
+hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, const int64_t* coff,
+                 const int64_t* sjs, int64_t spad, int64_t mp, const double* rhs, double* Wp,
+                 double* U, void* Wop, hipStream_t st);
+
+// Elementwise steps (FP64 state, n x mp / s x mp, only c < m touched).
+hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int64_t m,
+                   int64_t mp, const float* Y, const double* Obar, const double* nu,
+                   const double* Dbar, double* O, void* Rop, hipStream_t st);
+hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, const double* P,
+                    double* Obar, double* nu, double* Dbar, hipStream_t st);
+hipError_t col_pre(double kappa, int64_t s, int64_t m, int64_t mp, const double* Wbar,
+                   const double* mu, double* Wc, hipStream_t st);
+hipError_t col_post(int R, int64_t s, int64_t m, int64_t mp, const double* Wc, const double* Wp,
+                    double* Wbar, double* mu, double* mup, hipStream_t st);
+// Copy between padded (ld = mp) FP64 state and a dense (ld = m) buffer.
+hipError_t unpad(const double* src, int64_t rows, int64_t m, int64_t mp, double* dst,
+                 hipStream_t st);
+hipError_t pad(const double* src, int64_t rows, int64_t m, int64_t mp, double* dst,
+               hipStream_t st);
+// Operand copy of a padded FP64 array (rows x mp) into op type.
+hipError_t to_op(int prec, const double* src, int64_t count, void* dst, hipStream_t st);
+// Scores out[r][c] = (float) P[r][c], c < m.
+hipError_t scores_out(const double* P, int64_t rows, int64_t m, int64_t mp, float* out,
+                      hipStream_t st);
+
+}  // namespace bs

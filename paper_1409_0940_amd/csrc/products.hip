@@ -1,0 +1,340 @@
+// Products against blocks of Z (Algorithm 1, steps 17 and 19; the paper's
+// step 21 is replaced by the identity Z^T Z W' = rhs - W') and the Gram
+// matrices Z_ij^T Z_ij behind the cached factors of eq. cache.
+//
+// Z lives in the iteration workspace, row-major.  Feature block j occupies
+// the 64-aligned column range starting at coff_j; the columns between s_j and
+// the next multiple of 64 are zero.  Every feature-indexed array uses this
+// padded feature index, so kernels can sweep all of it without masks.
+// All reductions run in a fixed order (split partials are summed by a second
+// kernel), so results are bitwise repeatable.
+#include "common.h"
+#include "kernels.h"
+
+#include <algorithm>
+
+namespace bs {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Partial transpose products, one row block per launch:
+// part[sp][f][c] = sum_{r in split sp} Z[r][f] Rop[r][c].
+// MFMA view: M = features, N = outputs, K = rows.  A lane loads 4 adjacent
+// features of one row; instruction q of a step uses feature 4 m + q as its
+// row m, so one 16-byte load feeds 4 instructions.  Each wave owns 64
+// features; the 4 waves of a workgroup own 256 adjacent features and read
+// the same rows of Rop.
+// ---------------------------------------------------------------------------
+template <int P, int NTC>
+__global__ void __launch_bounds__(256)
+ztr_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
+           const typename Prec<P>::op_t* __restrict__ Rop, int64_t mp, int64_t split_rows,
+           typename Prec<P>::acc_t* __restrict__ part) {
+  using op_t = typename Prec<P>::op_t;
+  using accv = typename Prec<P>::accv;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t f0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int64_t sp = blockIdx.y;
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const int64_t rbeg = sp * split_rows;
+  const int64_t rend = min(rows, rbeg + split_rows);
+  const int64_t fl = f0 + 4 * fr;  // first of this lane's 4 features (< ldz)
+
+  accv acc[4][NTC];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[q][t][r] = 0;
+
+  if (f0 < s) {
+    for (int64_t rb = rbeg; rb < rend; rb += 4) {
+      const int64_t r = rb + fg;
+      const bool ok = r < rend;
+      Frag<P> a;
+      if (ok) {
+        a = load_frag<P>(Z + r * ldz + fl);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a.v[q] = 0;
+      }
+#pragma unroll
+      for (int t = 0; t < NTC; ++t) {
+        const int nt = nc0 + t;
+        if (nt < ntiles) {
+          op_t bv = ok ? Rop[r * mp + nt * 16 + fr] : (op_t)0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if constexpr (P == BS_PREC_F64)
+              acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[q], bv, acc[q][t], 0, 0, 0);
+            else
+              acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[q], bv, acc[q][t], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // lane holds D[m = acc_row(fg, r)][n = fr]; feature = f0 + 4 m + q
+#pragma unroll
+  for (int t = 0; t < NTC; ++t) {
+    const int nt = nc0 + t;
+    if (nt >= ntiles) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t f = f0 + 4 * acc_row<typename Prec<P>::acc_t>(fg, r) + q;
+        if (f < s) part[(sp * s + f) * mp + nt * 16 + fr] = acc[q][t][r];
+      }
+  }
+}
+
+// rhs = W-bar - mu' + U + sum over splits (fixed order), per row block.
+template <typename A>
+__global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max, int64_t n,
+                                  int R, int i0, int i1, int64_t split_rows, int64_t s, int64_t mp,
+                                  const double* __restrict__ Wbar, const double* __restrict__ mup,
+                                  const double* __restrict__ U, double* __restrict__ rhs) {
+  const int64_t per = s * mp;
+  const int64_t total = (int64_t)(i1 - i0) * per;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = i0 + (int)(e / per);
+    const int64_t fc = e - (int64_t)(i - i0) * per;
+    const int64_t ni = (int64_t)(i + 1) * n / R - (int64_t)i * n / R;
+    const int64_t ns = (ni + split_rows - 1) / split_rows;
+    const A* pp = part + (int64_t)i * nsplit_max * per + fc;
+    double a = 0.0;
+    for (int64_t sp = 0; sp < ns; ++sp) a += (double)pp[sp * per];
+    const int64_t off = (int64_t)i * per + fc;
+    rhs[off] = Wbar[fc] - mup[off] + U[off] + a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward product for one row block: P[r][c] = sum_f Z[r][f] Wop[f][c].
+// MFMA view: M = rows, N = outputs, K = features.  A lane loads 4 adjacent
+// features of its row; instruction t of a step pairs feature 4 g + t with
+// row t of the matching Wop slice.  Each wave owns 16 rows, a workgroup 64.
+// Pad columns of Z and pad rows of Wop are zero.
+// ---------------------------------------------------------------------------
+template <int P, int NTC>
+__global__ void __launch_bounds__(256)
+zw_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
+          const typename Prec<P>::op_t* __restrict__ Wop, int64_t mp, double* __restrict__ Pout) {
+  using accv = typename Prec<P>::accv;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int nc0 = blockIdx.y * NTC;
+  const int ntiles = (int)(mp / 16);
+  const int64_t rl = min(r0 + fr, rows - 1);
+  accv acc[NTC];
+#pragma unroll
+  for (int t = 0; t < NTC; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[t][r] = 0;
+  if (r0 < rows) {
+    const auto* zrow = Z + rl * ldz + 4 * fg;
+    for (int64_t f0 = 0; f0 < s16; f0 += 16) {
+      Frag<P> a = load_frag<P>(zrow + f0);
+      const auto* wb = Wop + (f0 + 4 * fg) * mp + fr;
+#pragma unroll
+      for (int t = 0; t < NTC; ++t) {
+        const int nt = nc0 + t;
+        if (nt < ntiles) {
+          Frag<P> b;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) b.v[q] = wb[q * mp + nt * 16];
+          mfma_step(acc[t], a, b);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NTC; ++t) {
+    const int nt = nc0 + t;
+    if (nt >= ntiles) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + acc_row<typename Prec<P>::acc_t>(fg, r);
+      if (row < rows) Pout[row * mp + nt * 16 + fr] = (double)acc[t][r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram tile of one block: slot[a][b] tile = I + Z_b^T Z_b restricted to the
+// 64 x 64 tile (ta, tb), ta >= tb.  The 4 waves take interleaved groups of 4
+// rows and their partial sums are added in wave order through LDS.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(256)
+gram_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
+            int64_t sj, double* __restrict__ slot, int64_t S) {
+  using op_t = typename Prec<P>::op_t;
+  using acc_t = typename Prec<P>::acc_t;
+  using accv = typename Prec<P>::accv;
+  __shared__ acc_t red[64 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  // tile index -> (ta, tb), ta >= tb
+  const int64_t t = blockIdx.x;
+  int64_t ta = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
+  while (ta * (ta + 1) / 2 > t) --ta;
+  const int64_t tb = t - ta * (ta + 1) / 2;
+  const int64_t fa = 64 * ta + 4 * fr, fb = 64 * tb + 4 * fr;  // block-local features
+
+  accv acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  for (int64_t rb = 4 * wave; rb < rows; rb += 16) {
+    const int64_t r = rb + fg;
+    Frag<P> a, b;
+    if (r < rows) {
+      a = load_frag<P>(Z + r * ldz + coff + fa);
+      b = load_frag<P>(Z + r * ldz + coff + fb);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a.v[q] = b.v[q] = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (fa + q >= sj) a.v[q] = 0;
+      if (fb + q >= sj) b.v[q] = 0;
+    }
+#pragma unroll
+    for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb) {
+        if constexpr (P == BS_PREC_F64)
+          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[qa], b.v[qb], acc[qa][qb], 0, 0, 0);
+        else
+          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[qa], b.v[qb], acc[qa][qb], 0, 0, 0);
+      }
+  }
+  // element (m = acc_row(fg, r), n = fr) of instruction (qa, qb) is
+  // G[64 ta + 4 m + qa][64 tb + 4 n + qb]; local index (4 m + qa, 4 n + qb)
+  for (int w = 1; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            red[(4 * acc_row<acc_t>(fg, r) + qa) * 64 + 4 * fr + qb] = acc[qa][qb][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[qa][qb][r] += red[(4 * acc_row<acc_t>(fg, r) + qa) * 64 + 4 * fr + qb];
+    }
+    __syncthreads();
+  }
+  if (wave == 0) {
+#pragma unroll
+    for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = 64 * ta + 4 * acc_row<acc_t>(fg, r) + qa;
+          const int64_t gj = 64 * tb + 4 * fr + qb;
+          if (gi < sj && gj < sj)
+            slot[gi * S + gj] = (double)acc[qa][qb][r] + (gi == gj ? 1.0 : 0.0);
+        }
+  }
+}
+
+}  // namespace
+
+hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s,
+                       const void* Rop, int64_t mp, int64_t split_rows, void* part,
+                       hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int ntiles = (int)(mp / 16);
+  const int64_t nsplit = (rows + split_rows - 1) / split_rows;
+  if (prec == BS_PREC_F64) {
+    constexpr int NTC = 2;
+    dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
+    ztr_kernel<BS_PREC_F64, NTC><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, s,
+                                                    (const double*)Rop, mp, split_rows,
+                                                    (double*)part);
+  } else if (prec == BS_PREC_F32) {
+    constexpr int NTC = 4;
+    dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
+    ztr_kernel<BS_PREC_F32, NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, s,
+                                                    (const float*)Rop, mp, split_rows,
+                                                    (float*)part);
+  } else {
+    return hipErrorNotSupported;
+  }
+  return hipGetLastError();
+}
+
+hipError_t reduce_rhs(int prec, const void* part, int64_t nsplit_max, int64_t n, int R, int i0,
+                      int i1, int64_t split_rows, int64_t s, int64_t mp, const double* Wbar,
+                      const double* mup, const double* U, double* rhs, hipStream_t st) {
+  int64_t total = (int64_t)(i1 - i0) * s * mp;
+  if (total <= 0) return hipSuccess;
+  unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+  if (prec == BS_PREC_F64)
+    reduce_rhs_kernel<double><<<g, 256, 0, st>>>((const double*)part, nsplit_max, n, R, i0, i1,
+                                                 split_rows, s, mp, Wbar, mup, U, rhs);
+  else
+    reduce_rhs_kernel<float><<<g, 256, 0, st>>>((const float*)part, nsplit_max, n, R, i0, i1,
+                                                split_rows, s, mp, Wbar, mup, U, rhs);
+  return hipGetLastError();
+}
+
+hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Wop,
+              int64_t mp, double* Pout, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int ntiles = (int)(mp / 16);
+  const int64_t s16 = (s + 15) / 16 * 16;
+  if (prec == BS_PREC_F64) {
+    constexpr int NTC = 4;
+    dim3 g((unsigned)((rows + 63) / 64), (unsigned)((ntiles + NTC - 1) / NTC));
+    zw_kernel<BS_PREC_F64, NTC><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, s16,
+                                                   (const double*)Wop, mp, Pout);
+  } else if (prec == BS_PREC_F32) {
+    constexpr int NTC = 4;
+    dim3 g((unsigned)((rows + 63) / 64), (unsigned)((ntiles + NTC - 1) / NTC));
+    zw_kernel<BS_PREC_F32, NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, s16,
+                                                   (const float*)Wop, mp, Pout);
+  } else {
+    return hipErrorNotSupported;
+  }
+  return hipGetLastError();
+}
+
+hipError_t gram(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t coff, int64_t sj,
+                double* slot, int64_t S, hipStream_t st) {
+  const int64_t T = (sj + 63) / 64;
+  dim3 g((unsigned)(T * (T + 1) / 2));
+  if (prec == BS_PREC_F64)
+    gram_kernel<BS_PREC_F64><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, coff, sj, slot, S);
+  else if (prec == BS_PREC_F32)
+    gram_kernel<BS_PREC_F32><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, coff, sj, slot, S);
+  else
+    return hipErrorNotSupported;
+  return hipGetLastError();
+}
+
+}  // namespace bs

@@ -1,0 +1,62 @@
+"""Handle wrapper: keeps the caller-owned device inputs alive for the handle's
+lifetime and reshapes exported state.  All work happens in libbsadmm."""
+
+from __future__ import annotations
+
+import torch
+
+from . import abi
+
+
+class Solver:
+    """Block-splitting ADMM solve on one GPU (Algorithm 1 over an R x C grid)."""
+
+    def __init__(self, X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
+                 stream=None, hbm_budget_bytes=0, workspace_bytes=0):
+        self._keep = (X, Y, W, b)
+        self.n, self.d = X.shape
+        self.m = Y.shape[1]
+        self.s = W.shape[1]
+        self.R, self.C = R, C
+        self.device = X.device
+        self.stream = stream
+        self.problem = abi.make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss, precision,
+                                        stream, hbm_budget_bytes, workspace_bytes)
+        self.h = abi.bsadmm_setup(self.problem)
+
+    def iterate(self, iters, timed=False):
+        return abi.bsadmm_iterate(self.h, iters, timed)
+
+    def iterate_async(self, iters):
+        abi.bsadmm_iterate_async(self.h, iters)
+
+    def state(self, name):
+        count = abi.bsadmm_state_size(self.h, name)
+        out = torch.empty(count, dtype=torch.float64, device=self.device)
+        abi.bsadmm_export_state(self.h, name, out)
+        if name in ("O", "Obar", "nu", "Dbar"):
+            return out.view(self.n, self.m)
+        if name in ("Wc", "Wbar", "mu"):
+            return out.view(self.s, self.m)
+        return out.view(self.R, self.s, self.m)
+
+    def set_state(self, name, value):
+        abi.bsadmm_import_state(self.h, name, value.contiguous().to(torch.float64))
+
+    def coef(self):
+        out = torch.empty((self.s, self.m), dtype=torch.float64, device=self.device)
+        return abi.bsadmm_get_coef(self.h, out)
+
+    def predict(self, Xt):
+        return abi.bsadmm_predict(self.h, Xt, self.m, stream=self.stream)
+
+    def close(self):
+        if self.h is not None:
+            abi.bsadmm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
