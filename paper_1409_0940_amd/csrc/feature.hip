@@ -134,21 +134,30 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t rows,
     ldsoff[i] = r * LDS_PITCH + seg * 16;
   }
   const int64_t nchunks = Kp / BK;
-  uint4 ra[4], rb[4];
-  auto gload = [&](int64_t c) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ra[i] = *reinterpret_cast<const uint4*>(gA[i] + c * KROW_BYTES);
-      rb[i] = *reinterpret_cast<const uint4*>(gB[i] + c * KROW_BYTES);
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[i]]) = ra[i];
-      *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[i]]) = rb[i];
-    }
-  };
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+#define BS_GLOAD(c)                                                          \
+  do {                                                                       \
+    const int64_t off_ = (c) * KROW_BYTES;                                   \
+    ra0 = *reinterpret_cast<const uint4*>(gA[0] + off_);                     \
+    ra1 = *reinterpret_cast<const uint4*>(gA[1] + off_);                     \
+    ra2 = *reinterpret_cast<const uint4*>(gA[2] + off_);                     \
+    ra3 = *reinterpret_cast<const uint4*>(gA[3] + off_);                     \
+    rb0 = *reinterpret_cast<const uint4*>(gB[0] + off_);                     \
+    rb1 = *reinterpret_cast<const uint4*>(gB[1] + off_);                     \
+    rb2 = *reinterpret_cast<const uint4*>(gB[2] + off_);                     \
+    rb3 = *reinterpret_cast<const uint4*>(gB[3] + off_);                     \
+  } while (0)
+#define BS_LSTORE(buf)                                                       \
+  do {                                                                       \
+    *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[0]]) = ra0;                \
+    *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[1]]) = ra1;                \
+    *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[2]]) = ra2;                \
+    *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[3]]) = ra3;                \
+    *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[0]]) = rb0;                \
+    *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[1]]) = rb1;                \
+    *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[2]]) = rb2;                \
+    *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[3]]) = rb3;                \
+  } while (0)
 
   accv acc[4][4];
 #pragma unroll
@@ -158,13 +167,14 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t rows,
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  gload(0);
-  lstore(0);
+  BS_GLOAD(0);
+  BS_LSTORE(0);
   __syncthreads();
   const int fr = lane & 15, fg = lane >> 4;
   for (int64_t c = 0; c < nchunks; ++c) {
     const int buf = (int)(c & 1);
-    if (c + 1 < nchunks) gload(c + 1);
+    const bool more = c + 1 < nchunks;
+    if (more) BS_GLOAD(c + 1);
 #pragma unroll
     for (int ks = 0; ks < STEPS; ++ks) {
       Frag<P> fa[4], fb[4];
@@ -181,9 +191,11 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t rows,
 #pragma unroll
         for (int j = 0; j < 4; ++j) mfma_step(acc[i][j], fa[i], fb[j]);
     }
-    if (c + 1 < nchunks) lstore(buf ^ 1);
+    if (more) BS_LSTORE(buf ^ 1);
     __syncthreads();
   }
+#undef BS_GLOAD
+#undef BS_LSTORE
 
   // Epilogue: lane holds D[acc_row(lane / 16, r)][lane % 16] of each 16 x 16 tile.
 #pragma unroll

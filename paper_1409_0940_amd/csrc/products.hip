@@ -24,9 +24,10 @@ namespace {
 // features of one row; instruction q of a step uses feature 4 m + q as its
 // row m, so one 16-byte load feeds 4 instructions.  Each wave owns 64
 // features; the 4 waves of a workgroup own 256 adjacent features and read
-// the same rows of Rop.
+// the same rows of Rop.  U groups of 4 rows are loaded before they are
+// consumed so that enough bytes are in flight to cover HBM latency.
 // ---------------------------------------------------------------------------
-template <int P, int NTC>
+template <int P, int NTC, int U>
 __global__ void __launch_bounds__(256)
 ztr_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
            const typename Prec<P>::op_t* __restrict__ Rop, int64_t mp, int64_t split_rows,
@@ -52,30 +53,37 @@ ztr_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t ro
       for (int r = 0; r < 4; ++r) acc[q][t][r] = 0;
 
   if (f0 < s) {
-    for (int64_t rb = rbeg; rb < rend; rb += 4) {
-      const int64_t r = rb + fg;
-      const bool ok = r < rend;
-      Frag<P> a;
-      if (ok) {
-        a = load_frag<P>(Z + r * ldz + fl);
-      } else {
+    for (int64_t rb = rbeg; rb < rend; rb += 4 * U) {
+      Frag<P> a[U];
+      op_t bv[U][NTC];
+      bool ok[U];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a.v[q] = 0;
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = rb + 4 * u + fg;
+        ok[u] = r < rend;
+        const int64_t rl = ok[u] ? r : rend - 1;   // in-bounds row; its weight is zeroed
+        a[u] = load_frag<P>(Z + rl * ldz + fl);
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) {
+          const int nt = min(nc0 + t, ntiles - 1);
+          bv[u][t] = Rop[rl * mp + nt * 16 + fr];
+        }
       }
+      // keep all U loads issued before the first use (no re-interleaving)
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < NTC; ++t) {
-        const int nt = nc0 + t;
-        if (nt < ntiles) {
-          op_t bv = ok ? Rop[r * mp + nt * 16 + fr] : (op_t)0;
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) {
+          const op_t b = ok[u] ? bv[u][t] : (op_t)0;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             if constexpr (P == BS_PREC_F64)
-              acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[q], bv, acc[q][t], 0, 0, 0);
+              acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].v[q], b, acc[q][t], 0, 0, 0);
             else
-              acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[q], bv, acc[q][t], 0, 0, 0);
+              acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].v[q], b, acc[q][t], 0, 0, 0);
           }
         }
-      }
     }
   }
   // lane holds D[m = acc_row(fg, r)][n = fr]; feature = f0 + 4 m + q
@@ -119,52 +127,69 @@ __global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max
 // Forward product for one row block: P[r][c] = sum_f Z[r][f] Wop[f][c].
 // MFMA view: M = rows, N = outputs, K = features.  A lane loads 4 adjacent
 // features of its row; instruction t of a step pairs feature 4 g + t with
-// row t of the matching Wop slice.  Each wave owns 16 rows, a workgroup 64.
-// Pad columns of Z and pad rows of Wop are zero.
+// row t of the matching Wop slice.  Each wave owns 32 rows (two M tiles
+// sharing every Wop value), a workgroup 128; U fragment steps are loaded
+// before they are consumed.  Pad columns of Z and pad rows of Wop are zero.
 // ---------------------------------------------------------------------------
-template <int P, int NTC>
+template <int P, int NTC, int U>
 __global__ void __launch_bounds__(256)
 zw_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
           const typename Prec<P>::op_t* __restrict__ Wop, int64_t mp, double* __restrict__ Pout) {
   using accv = typename Prec<P>::accv;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
   const int nc0 = blockIdx.y * NTC;
   const int ntiles = (int)(mp / 16);
-  const int64_t rl = min(r0 + fr, rows - 1);
-  accv acc[NTC];
+  accv acc[2][NTC];
 #pragma unroll
-  for (int t = 0; t < NTC; ++t)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[t][r] = 0;
+    for (int t = 0; t < NTC; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[h][t][r] = 0;
   if (r0 < rows) {
-    const auto* zrow = Z + rl * ldz + 4 * fg;
-    for (int64_t f0 = 0; f0 < s16; f0 += 16) {
-      Frag<P> a = load_frag<P>(zrow + f0);
-      const auto* wb = Wop + (f0 + 4 * fg) * mp + fr;
+    const auto* z0 = Z + min(r0 + fr, rows - 1) * ldz + 4 * fg;
+    const auto* z1 = Z + min(r0 + 16 + fr, rows - 1) * ldz + 4 * fg;
+    for (int64_t f0 = 0; f0 < s16; f0 += 16 * U) {
+      Frag<P> a0[U], a1[U], b[U][NTC];
 #pragma unroll
-      for (int t = 0; t < NTC; ++t) {
-        const int nt = nc0 + t;
-        if (nt < ntiles) {
-          Frag<P> b;
+      for (int u = 0; u < U; ++u) {
+        a0[u] = load_frag<P>(z0 + f0 + 16 * u);
+        a1[u] = load_frag<P>(z1 + f0 + 16 * u);
+      }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) b.v[q] = wb[q * mp + nt * 16];
-          mfma_step(acc[t], a, b);
+      for (int u = 0; u < U; ++u) {
+        const auto* wb = Wop + (f0 + 16 * u + 4 * fg) * mp + fr;
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) {
+          const int nt = min(nc0 + t, ntiles - 1);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) b[u][t].v[q] = wb[q * mp + nt * 16];
         }
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) {
+          mfma_step(acc[0][t], a0[u], b[u][t]);
+          mfma_step(acc[1][t], a1[u], b[u][t]);
+        }
     }
   }
 #pragma unroll
-  for (int t = 0; t < NTC; ++t) {
-    const int nt = nc0 + t;
-    if (nt >= ntiles) continue;
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + acc_row<typename Prec<P>::acc_t>(fg, r);
-      if (row < rows) Pout[row * mp + nt * 16 + fr] = (double)acc[t][r];
+    for (int t = 0; t < NTC; ++t) {
+      const int nt = nc0 + t;
+      if (nt >= ntiles) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + 16 * h + acc_row<typename Prec<P>::acc_t>(fg, r);
+        if (row < rows) Pout[row * mp + nt * 16 + fr] = (double)acc[h][t][r];
+      }
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -264,24 +289,30 @@ gram_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t r
 
 }  // namespace
 
+template <int P, int NTC>
+static void launch_ztr(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rop,
+                       int64_t mp, int64_t split_rows, void* part, hipStream_t st) {
+  using op_t = typename Prec<P>::op_t;
+  using acc_t = typename Prec<P>::acc_t;
+  const int ntiles = (int)(mp / 16);
+  const int64_t nsplit = (rows + split_rows - 1) / split_rows;
+  dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
+  ztr_kernel<P, NTC, 8><<<g, 256, 0, st>>>((const op_t*)Z, ldz, rows, s, (const op_t*)Rop, mp,
+                                          split_rows, (acc_t*)part);
+}
+
 hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s,
                        const void* Rop, int64_t mp, int64_t split_rows, void* part,
                        hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   const int ntiles = (int)(mp / 16);
-  const int64_t nsplit = (rows + split_rows - 1) / split_rows;
   if (prec == BS_PREC_F64) {
-    constexpr int NTC = 2;
-    dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
-    ztr_kernel<BS_PREC_F64, NTC><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, s,
-                                                    (const double*)Rop, mp, split_rows,
-                                                    (double*)part);
+    if (ntiles == 1) launch_ztr<BS_PREC_F64, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else launch_ztr<BS_PREC_F64, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
   } else if (prec == BS_PREC_F32) {
-    constexpr int NTC = 4;
-    dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
-    ztr_kernel<BS_PREC_F32, NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, s,
-                                                    (const float*)Rop, mp, split_rows,
-                                                    (float*)part);
+    if (ntiles == 1) launch_ztr<BS_PREC_F32, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (ntiles == 2) launch_ztr<BS_PREC_F32, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else launch_ztr<BS_PREC_F32, 4>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
   } else {
     return hipErrorNotSupported;
   }
@@ -303,21 +334,28 @@ hipError_t reduce_rhs(int prec, const void* part, int64_t nsplit_max, int64_t n,
   return hipGetLastError();
 }
 
+template <int P, int NTC>
+static void launch_zw(const void* Z, int64_t ldz, int64_t rows, int64_t s16, const void* Wop,
+                      int64_t mp, double* Pout, hipStream_t st) {
+  using op_t = typename Prec<P>::op_t;
+  const int ntiles = (int)(mp / 16);
+  dim3 g((unsigned)((rows + 127) / 128), (unsigned)((ntiles + NTC - 1) / NTC));
+  zw_kernel<P, NTC, 4><<<g, 256, 0, st>>>((const op_t*)Z, ldz, rows, s16, (const op_t*)Wop, mp,
+                                         Pout);
+}
+
 hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Wop,
               int64_t mp, double* Pout, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   const int ntiles = (int)(mp / 16);
-  const int64_t s16 = (s + 15) / 16 * 16;
+  const int64_t s16 = (s + 63) / 64 * 64;  // multiple of the 4-step unroll (s is 64-aligned)
   if (prec == BS_PREC_F64) {
-    constexpr int NTC = 4;
-    dim3 g((unsigned)((rows + 63) / 64), (unsigned)((ntiles + NTC - 1) / NTC));
-    zw_kernel<BS_PREC_F64, NTC><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, s16,
-                                                   (const double*)Wop, mp, Pout);
+    if (ntiles == 1) launch_zw<BS_PREC_F64, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else launch_zw<BS_PREC_F64, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
   } else if (prec == BS_PREC_F32) {
-    constexpr int NTC = 4;
-    dim3 g((unsigned)((rows + 63) / 64), (unsigned)((ntiles + NTC - 1) / NTC));
-    zw_kernel<BS_PREC_F32, NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, s16,
-                                                   (const float*)Wop, mp, Pout);
+    if (ntiles == 1) launch_zw<BS_PREC_F32, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (ntiles == 2) launch_zw<BS_PREC_F32, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else launch_zw<BS_PREC_F32, 4>(Z, ldz, rows, s16, Wop, mp, Pout, st);
   } else {
     return hipErrorNotSupported;
   }
