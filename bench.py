@@ -9,14 +9,16 @@ separately.  Inputs are synthetic and resident in HBM before timing.
 
 Default workload: digit-like inputs n = 200000, d = 784, m = 10 one-hot
 classes, sigma = 10, s = 10240 random features, 4 x 4 blocks, squared loss,
-lambda = 1e-4, rho = 1, FP32 arithmetic.
+lambda = 1e-4, rho = 1, FP32 arithmetic.  The same iteration count is also
+run in the plain FP64 form, in BF16 and in refined BF16 (BF16X3); each
+model's objective is evaluated with the FP64 form's feature map and reported
+as a relative error against the FP64 form's objective.
 """
 
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -24,39 +26,45 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": ("TFLOP/s", 157.3), "fp64": ("TFLOP/s", 78.6), "bf16": ("TFLOP/s", 2500.0)}
-DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "bf16x3": 2500.0}   # dense MFMA TFLOP/s
+DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "bf16x3": "bf16x3"}
+# MFMA products issued per algorithmic phase product (BF16X3: head*head,
+# head*residual, residual*head)
+MFMA_PASSES = {"fp32": 1, "fp64": 1, "bf16": 1, "bf16x3": 3}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def gpu_run(w, precision, steps, warmup, X, Y, W, b):
+def gpu_run(w, precision, steps, warmup, dev_inputs):
+    """Setup, warm-up, timed iterations; returns (solver, record)."""
     import torch
     from paper_1409_0940_amd import Solver
 
-    dev = torch.device("cuda:0")
-    t = lambda a: torch.from_numpy(a).to(dev)
-    Xd, Yd, Wd, bd = t(X), t(Y), t(W), t(b)
+    Xd, Yd, Wd, bd = dev_inputs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = Solver(Xd, Yd, Wd, bd, w.R, w.C, w.lam, w.rho, w.sigma, w.loss, precision)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    log(f"{precision}: setup {setup_s:.2f} s")
     if warmup:
         S.iterate(warmup)
-    log(f"{precision}: warmup {warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = S.iterate(steps, timed=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log(f"{precision}: {steps} steps in {wall:.3f} s")
-    Wbar = S.coef().cpu().numpy()
-    S.close()
-    return setup_s, wall, st, Wbar
+    flops = regen_flops_per_launch(w)
+    launch_ms = st["phase_ms"]["regen"] / max(1, st["launches"])
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+    rec = {"value": steps / wall, "ms_per_step": 1e3 * wall / steps, "setup_s": setup_s,
+           "launch_ms": launch_ms, "achieved": achieved, "launches": st["launches"],
+           "phase_ms_per_step": {k: v / steps for k, v in st["phase_ms"].items()},
+           "coef": S.coef()}
+    log(f"{precision}: setup {setup_s:.2f} s, {steps} steps {wall:.3f} s "
+        f"({rec['value']:.2f} it/s), regen {launch_ms:.3f} ms/launch")
+    return S, rec
 
 
 def regen_flops_per_launch(w):
@@ -68,7 +76,6 @@ def regen_flops_per_launch(w):
 
 def cpu_baseline(w, X, Y, Wr, b):
     """Oracle iteration on one row block (R = 1, same C, s, d), scaled by R."""
-    import numpy as np
     from oracle import bsadmm_oracle as o
     try:
         from threadpoolctl import threadpool_info
@@ -81,17 +88,17 @@ def cpu_baseline(w, X, Y, Wr, b):
     t0 = time.perf_counter()
     for j in range(w.C):                       # setup: factors, not timed
         cache.chol(0, j, cache.Zblock(0, j))
-    setup = time.perf_counter() - t0
-    log(f"oracle setup on {ni} rows: {setup:.1f} s")
+    log(f"oracle setup on {ni} rows: {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     o.admm(p, 1, cache=cache)
     it = time.perf_counter() - t0
     log(f"oracle iteration on {ni} rows: {it:.1f} s")
     per_iter = it * w.R
-    return {"value": 1.0 / per_iter, "unit": "iters/s", "cores": threads, "kind": "oracle",
+    return {"value": round(1.0 / per_iter, 6), "unit": "iters/s", "cores": threads,
+            "kind": "oracle",
             "sample": f"1 iteration on row block 0 of {w.R} ({ni} x {w.d}, s={w.s}, C={w.C}), "
                       f"Z regenerated, factors built beforehand; time x {w.R} (extrapolated)",
-            "s_per_iter": per_iter}
+            "s_per_iter": round(per_iter, 3)}
 
 
 def main():
@@ -99,38 +106,56 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=list(PEAK))
     ap.add_argument("--workload", default="digits_200k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp64-steps", type=int, default=3,
-                    help="iterations of the plain FP64 form timed beside (0 = skip)")
+    ap.add_argument("--variants", default="fp64,bf16,bf16x3",
+                    help="other precisions run at the same iteration count ('' = none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
     import workloads as wl
 
     w = getattr(wl, args.workload)()
     log(f"workload {w.name}: generating inputs")
     X, Y, Wr, b = wl.make_inputs(w)
-    log("inputs ready")
-    setup_s, wall, st, Wbar = gpu_run(w, args.precision, args.steps, args.warmup, X, Y, Wr, b)
-    value = args.steps / wall
-    flops = regen_flops_per_launch(w)
-    launch_ms = st["phase_ms"]["regen"] / max(1, st["launches"])
-    achieved = flops / (launch_ms * 1e-3) / 1e12
-    unit, peak = PEAK[args.precision]
+    dev = torch.device("cuda:0")
+    dev_inputs = tuple(torch.from_numpy(a).to(dev) for a in (X, Y, Wr, b))
+    log("inputs resident on the device")
+
+    S, main_rec = gpu_run(w, args.precision, args.steps, args.warmup, dev_inputs)
+    S.close()
+    variants = [v for v in args.variants.split(",") if v and v != args.precision]
+    recs = {}
+    ref = None
+    for v in variants:
+        Sv, rv = gpu_run(w, v, args.steps, args.warmup, dev_inputs)
+        if v == "fp64":
+            ref = Sv
+        else:
+            Sv.close()
+        recs[v] = rv
+    obj = {}
+    if ref is not None:
+        f64 = ref.objective()
+        obj["fp64"] = f64
+        for name, r in [(args.precision, main_rec)] + [(k, v) for k, v in recs.items() if k != "fp64"]:
+            obj[name] = ref.objective(r["coef"])
+        ref.close()
+    rel = lambda k: (abs(obj[k] - obj["fp64"]) / abs(obj["fp64"])) if k in obj and "fp64" in obj else None
+
+    peak = PEAK[args.precision]
     out = {
         "metric": "ADMM iters/s",
-        "value": round(value, 4),
+        "value": round(main_rec["value"], 4),
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / args.steps, 3),
+        "ms_per_step": round(main_rec["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -139,23 +164,30 @@ def main():
         "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "s": w.s,
                    "grid": f"{w.R}x{w.C}", "loss": w.loss, "lambda": w.lam, "rho": w.rho,
                    "sigma": w.sigma, "precision": args.precision},
-        "roofline": {"bound": "mfma", "kernel": "regen_kernel", "achieved": round(achieved, 2),
-                     "peak": peak, "unit": unit, "frac": round(achieved / peak, 4),
-                     "traffic": None, "flops_per_launch": flops,
-                     "avg_launch_ms": round(launch_ms, 4), "launches": st["launches"]},
-        "setup_s": round(setup_s, 3),
-        "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in st["phase_ms"].items()},
+        "roofline": {"bound": "mfma", "kernel": "regen_kernel",
+                     "achieved": round(main_rec["achieved"], 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(main_rec["achieved"] / peak, 4),
+                     "traffic": None, "flops_per_launch": regen_flops_per_launch(w),
+                     "avg_launch_ms": round(main_rec["launch_ms"], 4),
+                     "launches": main_rec["launches"],
+                     "mfma_passes": MFMA_PASSES[args.precision]},
+        "setup_s": round(main_rec["setup_s"], 3),
+        "phase_ms_per_step": {k: round(v, 4) for k, v in main_rec["phase_ms_per_step"].items()},
         # feature-GEMM flops of a whole step over the step time, against the peak
-        "mfma_frac_of_step": round((2.0 * w.n * w.d * w.s) / (wall / args.steps) / 1e12 / peak, 4),
+        "mfma_frac_of_step": round(2.0 * w.n * w.d * w.s / (main_rec["ms_per_step"] * 1e-3)
+                                   / 1e12 / peak, 4),
+        "obj_rel_err_vs_fp64": rel(args.precision),
+        "objective": obj.get(args.precision),
+        "variants": {k: {"value": round(r["value"], 4), "unit": "iters/s",
+                         "ms_per_step": round(r["ms_per_step"], 3),
+                         "setup_s": round(r["setup_s"], 3),
+                         "regen_frac": round(r["achieved"] / PEAK[k], 4),
+                         "regen_tflops": round(r["achieved"], 2),
+                         "mfma_passes": MFMA_PASSES[k],
+                         "obj_rel_err_vs_fp64": rel(k)} for k, r in recs.items()},
     }
-    if args.fp64_steps and args.precision != "fp64":
-        s64, wall64, st64, W64 = gpu_run(w, "fp64", args.fp64_steps, 1, X, Y, Wr, b)
-        out["fp64_form"] = {"value": round(args.fp64_steps / wall64, 4), "unit": "iters/s",
-                            "setup_s": round(s64, 3),
-                            "ms_per_step": round(1e3 * wall64 / args.fp64_steps, 3)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, X, Y, Wr, b)
-        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 6)
     print(json.dumps(out), flush=True)
 
 

@@ -59,11 +59,17 @@ typedef enum {
 /* ------------------------------------------------------------- precision */
 /* Arithmetic of the feature regeneration and of the Z products.  The ADMM
  * state, the Cholesky factorisation and the cached inverse are always FP64.
- *   FP64: phase X W + b, cos and products in FP64 (FP64 MFMA).
- *   FP32: FP32 MFMA with FP32 accumulation, phase and cos in FP32.
- *   BF16: X, W, Z and the product right-hand sides rounded to BF16 (round to
- *         nearest even), FP32 accumulation; b is added to the FP32 phase.   */
-enum { BSADMM_FP64 = 0, BSADMM_FP32 = 1, BSADMM_BF16 = 2 };
+ *   FP64  : phase X W + b, cos and products in FP64 (FP64 MFMA).
+ *   FP32  : FP32 MFMA with FP32 accumulation, phase and cos in FP32; Z FP32.
+ *   BF16  : X and W rounded to BF16 (round to nearest even), BF16 MFMA with
+ *           FP32 accumulation, b added to the FP32 phase, cos in FP32, Z
+ *           stored in BF16; products on FP32 MFMA (Z widened, R and W' FP32).
+ *   BF16X3: refined BF16.  X and W are each split into a BF16 head and a BF16
+ *           residual (the rounding error of the head), and the phase sums the
+ *           three products head*head + head*residual + residual*head on BF16
+ *           MFMA with FP32 accumulation; Z is stored in FP32 and the products
+ *           are FP32.  rff_map returns float for BF16X3.                    */
+enum { BSADMM_FP64 = 0, BSADMM_FP32 = 1, BSADMM_BF16 = 2, BSADMM_BF16X3 = 3 };
 
 /* ------------------------------------------------------------------ loss */
 /* V(y, o) of eq. basicproblem, entering only through its prox (paragraph
@@ -102,7 +108,7 @@ typedef struct bsadmm_problem {
   int32_t C;        /* feature (column) blocks, >= 1                        */
   int32_t loss;     /* BSADMM_SQUARED | BSADMM_HINGE | BSADMM_MC_HINGE      */
   int32_t reg;      /* BSADMM_L2                                            */
-  int32_t precision;/* BSADMM_FP64 | BSADMM_FP32 | BSADMM_BF16              */
+  int32_t precision;/* BSADMM_FP64 | FP32 | BF16 | BF16X3                    */
   int32_t z_mode;   /* BSADMM_Z_AUTO | BSADMM_Z_STORE                       */
   double lambda;    /* >= 0                                                 */
   double rho;       /* > 0                                                  */
@@ -147,8 +153,8 @@ typedef struct bsadmm_handle bsadmm_handle;
  * Fourier feature map of section "Randomized Kernel Maps":
  *   Z[r][f] = sqrt(2/s) * cos(sum_k X[r][k] W[k][f] + b[f]).
  * X: device n x d float32.  W: device d x s float32.  b: device s float32.
- * Z_out: device n x s of double (FP64), float (FP32) or bf16 bits stored
- * as uint16 (BF16).  n may be 0 (no work).  Allocates and frees a small
+ * Z_out: device n x s of double (FP64), float (FP32, BF16X3) or bf16 bits
+ * stored as uint16 (BF16).  n may be 0 (no work).  Allocates and frees a small
  * operand staging buffer; synchronises the stream before returning.
  * Errors: EINVAL (null pointers with n > 0, d < 1, s < 1, bad precision),
  * ENOMEM, EDEVICE.
@@ -235,6 +241,17 @@ enum {
 BSADMM_API int bsadmm_state_size(const bsadmm_handle* h, int32_t which, int64_t* count);
 BSADMM_API int bsadmm_export_state(const bsadmm_handle* h, int32_t which, double* dst);
 BSADMM_API int bsadmm_import_state(bsadmm_handle* h, int32_t which, const double* src);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_objective -- F(W) = (1/n) sum_r V(y_r, W^T z(x_r)) + lambda ||W||_F^2
+ * (eq. problem_linear) on the handle's training data, with the handle's
+ * feature map and precision: one regeneration pass over all rows and one
+ * forward product, summed in a fixed order.  Wmodel: device s x m FP64
+ * model, or NULL for the handle's consensus W-bar.  *F: host.  Overwrites
+ * the Z workspace (no effect on the iteration).  Synchronises.
+ * Errors: EINVAL (null handle or F), ESTATE, ENOMEM, EDEVICE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F);
 
 /* bsadmm_destroy -- free everything the handle owns.  NULL is allowed. */
 BSADMM_API int bsadmm_destroy(bsadmm_handle* h);

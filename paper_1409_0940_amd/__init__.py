@@ -7,7 +7,8 @@ library is loaded on first use and raises if it has not been built.
 
 from .abi import (rff_map, bsadmm_validate, bsadmm_footprint, bsadmm_setup, bsadmm_iterate,  # noqa: F401
                   bsadmm_predict, bsadmm_get_coef, bsadmm_state_size, bsadmm_export_state,
-                  bsadmm_import_state, bsadmm_destroy, make_problem, BsadmmError, lib)
+                  bsadmm_import_state, bsadmm_objective, bsadmm_destroy, make_problem,
+                  BsadmmError, lib)
 
 
 def Solver(*args, **kwargs):  # noqa: N802 - factory keeps torch import lazy

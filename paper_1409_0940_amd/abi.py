@@ -14,7 +14,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbsadmm.so")
 
-PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 LOSS = {"squared": 0, "hinge": 1, "mc_hinge": 2}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTPD", 5: "ENONFINITE",
           6: "ESTATE", 7: "ENOTIMPL"}
@@ -24,7 +24,7 @@ PHASES = ["regen", "ztr", "solve", "zw", "row", "col"]
 
 EXPORTED = ["rff_map", "bsadmm_validate", "bsadmm_footprint", "bsadmm_setup", "bsadmm_iterate",
             "bsadmm_predict", "bsadmm_get_coef", "bsadmm_state_size", "bsadmm_export_state",
-            "bsadmm_import_state", "bsadmm_destroy", "bsadmm_last_error"]
+            "bsadmm_import_state", "bsadmm_objective", "bsadmm_destroy", "bsadmm_last_error"]
 
 
 class BsadmmProblem(ctypes.Structure):
@@ -75,6 +75,7 @@ def lib():
         L.bsadmm_state_size.argtypes = [vp, i32, ctypes.POINTER(i64)]
         L.bsadmm_export_state.argtypes = [vp, i32, vp]
         L.bsadmm_import_state.argtypes = [vp, i32, vp]
+        L.bsadmm_objective.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.bsadmm_destroy.argtypes = [vp]
         L.bsadmm_last_error.argtypes = []
         L.bsadmm_last_error.restype = ctypes.c_char_p
@@ -120,7 +121,8 @@ def rff_map(X, W, b, precision="fp32", out=None, stream=None):
     _need_cuda_f32("X", X, (n, d))
     _need_cuda_f32("W", W, (d, s))
     _need_cuda_f32("b", b, (s,))
-    dt = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16}[precision]
+    dt = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16,
+          "bf16x3": torch.float32}[precision]
     if out is None:
         out = torch.empty((n, s), dtype=dt, device=X.device)
     _check("rff_map", lib().rff_map(_ptr(X), n, d, _ptr(W), _ptr(b), s, PRECISION[precision],
@@ -210,6 +212,13 @@ def bsadmm_import_state(h, which, src):
 def bsadmm_get_coef(h, out):
     _check("bsadmm_get_coef", lib().bsadmm_get_coef(h, _ptr(out)))
     return out
+
+
+def bsadmm_objective(h, Wmodel=None):
+    """F(W) of the linearised problem for Wmodel (s x m FP64 device) or W-bar."""
+    F = ctypes.c_double(0.0)
+    _check("bsadmm_objective", lib().bsadmm_objective(h, _ptr(Wmodel), ctypes.byref(F)))
+    return F.value
 
 
 def bsadmm_destroy(h):

@@ -50,7 +50,8 @@ struct Plan {
   int64_t ws_rows = 0;
   int64_t split_rows = 2048, nsplit_max = 1;
   int fac_batch = 1;
-  size_t op = 4, accb = 4;
+  size_t op = 4, zb = 4, vb = 4;  // operand, stored Z, product-operand bytes
+  int planes = 1;
   // byte counts
   size_t b_xp = 0, b_wt = 0, b_bias = 0, b_q = 0, b_ws = 0, b_row = 0, b_rop = 0, b_col = 0,
          b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0;
@@ -71,7 +72,7 @@ int validate(const bsadmm_problem* p) {
     return fail(BSADMM_EINVAL, "unknown loss");
   if (p->loss == BSADMM_HINGE && p->m != 1) return fail(BSADMM_EINVAL, "HINGE needs m == 1");
   if (p->reg != BSADMM_L2) return fail(BSADMM_EINVAL, "unknown regulariser");
-  if (p->precision != BSADMM_FP64 && p->precision != BSADMM_FP32 && p->precision != BSADMM_BF16)
+  if (p->precision < BSADMM_FP64 || p->precision > BSADMM_BF16X3)
     return fail(BSADMM_EINVAL, "unknown precision");
   if (p->z_mode != BSADMM_Z_AUTO && p->z_mode != BSADMM_Z_STORE)
     return fail(BSADMM_EINVAL, "unknown z_mode");
@@ -93,7 +94,9 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.n = p->n; L.d = p->d; L.m = p->m; L.s = p->s; L.R = p->R; L.C = p->C;
   L.mp = rup(L.m, 16);
   L.op = bs::op_bytes(L.prec);
-  L.accb = (L.prec == BSADMM_FP64) ? 8 : 4;
+  L.planes = bs::op_planes(L.prec);
+  L.zb = bs::z_bytes(L.prec);
+  L.vb = bs::vec_bytes(L.prec);
   L.Kp = bs::padded_k(L.prec, L.d);
   L.rstart.resize(L.R + 1);
   for (int i = 0; i <= L.R; ++i) L.rstart[i] = (int64_t)i * L.n / L.R;
@@ -112,7 +115,7 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.S = rup(smax, 64);
   // Row-block groups for the Z workspace.
   size_t cap = p->workspace_bytes ? p->workspace_bytes : (size_t)32 << 30;
-  const size_t row_bytes = (size_t)L.spad * L.op;
+  const size_t row_bytes = (size_t)L.spad * L.zb;
   L.groups.clear();
   int i = 0;
   L.ws_rows = 0;
@@ -130,17 +133,17 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   const size_t slot = (size_t)L.S * L.S * 8;
   const size_t fac_cap = (size_t)4 << 30;
   L.fac_batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.R * L.C, fac_cap / slot));
-  L.b_xp = (size_t)L.n * L.Kp * L.op;
-  L.b_wt = (size_t)L.s * L.Kp * L.op;
+  L.b_xp = (size_t)L.n * L.Kp * L.op * L.planes;
+  L.b_wt = (size_t)L.s * L.Kp * L.op * L.planes;
   L.b_bias = (size_t)L.s * (L.prec == BSADMM_FP64 ? 8 : 4);
   L.b_q = (size_t)L.R * L.C * slot;
   L.b_ws = (size_t)L.ws_rows * row_bytes;
   L.b_row = (size_t)L.n * L.mp * 8;
-  L.b_rop = (size_t)L.n * L.mp * L.op;
+  L.b_rop = (size_t)L.n * L.mp * L.vb;
   L.b_col = (size_t)L.spad * L.mp * 8;
   L.b_colR = (size_t)L.R * L.spad * L.mp * 8;
-  L.b_wop = (size_t)L.R * L.spad * L.mp * L.op;
-  L.b_part = (size_t)L.R * L.nsplit_max * L.spad * L.mp * L.accb;
+  L.b_wop = (size_t)L.R * L.spad * L.mp * L.vb;
+  L.b_part = (size_t)L.R * L.nsplit_max * L.spad * L.mp * L.vb;
   L.b_small = 256 + 2 * (size_t)L.C * 8;
   L.b_fac_tmp = (size_t)L.fac_batch * (slot + (size_t)L.S * 64 * 8);
   return BSADMM_OK;
@@ -187,14 +190,15 @@ namespace {
   } while (0)
 
 // Feature regeneration of the rows of group g into the workspace.
-hipError_t regen_group(bsadmm_handle* h, int i0, int i1, const void* Xop) {
+hipError_t regen_group(bsadmm_handle* h, int i0, int i1, const void* Xop, int64_t xps) {
   const Plan& L = h->L;
   const int64_t r0 = L.rstart[i0], rows = L.rstart[i1] - r0;
+  const size_t bb = L.prec == BSADMM_FP64 ? 8 : 4;
   for (int j = 0; j < L.C; ++j) {
-    hipError_t e = bs::regen(L.prec, (const char*)Xop + (size_t)r0 * L.Kp * L.op, rows,
-                             (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.sj[j],
-                             (const char*)h->bias + (size_t)L.cstart[j] * (L.prec == BSADMM_FP64 ? 8 : 4),
-                             L.Kp, h->scale, (char*)h->Z + (size_t)L.coff[j] * L.op, L.spad, h->st);
+    hipError_t e = bs::regen(L.prec, (const char*)Xop + (size_t)r0 * L.Kp * L.op, xps, rows,
+                             (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.s * L.Kp,
+                             L.sj[j], (const char*)h->bias + (size_t)L.cstart[j] * bb, L.Kp,
+                             h->scale, (char*)h->Z + (size_t)L.coff[j] * L.zb, L.spad, h->st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -252,16 +256,16 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
       const int i0 = g.first, i1 = g.second;
       const int64_t r0 = L.rstart[i0];
       tm.begin();
-      HCHK(regen_group(h, i0, i1, h->Xp));
+      HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp));
       launches += L.C;
       tm.end(BSADMM_PH_REGEN);
       tm.begin();
       for (int i = i0; i < i1; ++i) {
         const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-        HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.op,
-                             L.spad, ni, L.spad, (const char*)h->Rop + (size_t)ri * L.mp * L.op,
+        HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb,
+                             L.spad, ni, L.spad, (const char*)h->Rop + (size_t)ri * L.mp * L.vb,
                              L.mp, L.split_rows,
-                             (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.accb,
+                             (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.vb,
                              h->st));
       }
       HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
@@ -274,8 +278,8 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
       tm.begin();
       for (int i = i0; i < i1; ++i) {
         const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-        HCHK(bs::zw(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.op, L.spad, ni,
-                    L.spad, (const char*)h->Wop + (size_t)i * L.spad * L.mp * L.op, L.mp,
+        HCHK(bs::zw(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb, L.spad, ni,
+                    L.spad, (const char*)h->Wop + (size_t)i * L.spad * L.mp * L.vb, L.mp,
                     h->P + (size_t)ri * L.mp, h->st));
       }
       tm.end(BSADMM_PH_ZW);
@@ -358,8 +362,8 @@ int do_setup(bsadmm_handle* h) {
   HCHK(hipMemsetAsync(h->Wop, 0, L.b_wop, st));
   HCHK(hipMemsetAsync(h->Z, 0, L.b_ws, st));
   // operands and input checks
-  HCHK(bs::prep_rows(L.prec, p.X, L.n, L.d, L.Kp, h->Xp, h->dflag, st));
-  HCHK(bs::prep_w(L.prec, p.W, p.b, L.d, L.s, L.Kp, h->Wt, h->bias, h->dflag, st));
+  HCHK(bs::prep_rows(L.prec, p.X, L.n, L.d, L.Kp, h->Xp, L.n * L.Kp, h->dflag, st));
+  HCHK(bs::prep_w(L.prec, p.W, p.b, L.d, L.s, L.Kp, h->Wt, L.s * L.Kp, h->bias, h->dflag, st));
   HCHK(bs::check_finite(p.Y, L.n * L.m, h->dflag, st));
   int flag = 0;
   HCHK(hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -378,10 +382,10 @@ int do_setup(bsadmm_handle* h) {
   for (const auto& g : L.groups) {
     const int i0 = g.first, i1 = g.second;
     const int64_t r0 = L.rstart[i0];
-    HCHK(regen_group(h, i0, i1, h->Xp));
+    HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp));
     for (int i = i0; i < i1; ++i)
       for (int j = 0; j < L.C; ++j)
-        HCHK(bs::gram(L.prec, (const char*)h->Z + (size_t)(L.rstart[i] - r0) * L.spad * L.op,
+        HCHK(bs::gram(L.prec, (const char*)h->Z + (size_t)(L.rstart[i] - r0) * L.spad * L.zb,
                       L.spad, L.rstart[i + 1] - L.rstart[i], L.coff[j], L.sj[j],
                       h->Q + (size_t)(i * L.C + j) * slot, L.S, st));
   }
@@ -573,21 +577,22 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
     if (wop) (void)hipFree(wop);
     if (pbuf) (void)hipFree(pbuf);
   };
-  if (hipMalloc(&xop, (size_t)chunk * L.Kp * L.op) != hipSuccess ||
-      hipMalloc(&wop, (size_t)L.spad * L.mp * L.op) != hipSuccess ||
+  if (hipMalloc(&xop, (size_t)chunk * L.Kp * L.op * L.planes) != hipSuccess ||
+      hipMalloc(&wop, (size_t)L.spad * L.mp * L.vb) != hipSuccess ||
       hipMalloc((void**)&pbuf, (size_t)chunk * L.mp * 8) != hipSuccess) {
     cleanup();
     return fail(BSADMM_ENOMEM, "hipMalloc failed in predict");
   }
+  const size_t bb = L.prec == BSADMM_FP64 ? 8 : 4;
   hipError_t e = bs::to_op(L.prec, h->Wbar, L.spad * L.mp, wop, st);
   for (int64_t r0 = 0; r0 < nt && e == hipSuccess; r0 += chunk) {
     const int64_t rows = std::min(chunk, nt - r0);
-    e = bs::prep_rows(L.prec, Xt + r0 * L.d, rows, L.d, L.Kp, xop, nullptr, st);
+    e = bs::prep_rows(L.prec, Xt + r0 * L.d, rows, L.d, L.Kp, xop, chunk * L.Kp, nullptr, st);
     for (int j = 0; j < L.C && e == hipSuccess; ++j)
-      e = bs::regen(L.prec, xop, rows, (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op,
-                    L.sj[j],
-                    (const char*)h->bias + (size_t)L.cstart[j] * (L.prec == BSADMM_FP64 ? 8 : 4),
-                    L.Kp, h->scale, (char*)h->Z + (size_t)L.coff[j] * L.op, L.spad, st);
+      e = bs::regen(L.prec, xop, chunk * L.Kp, rows,
+                    (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.s * L.Kp, L.sj[j],
+                    (const char*)h->bias + (size_t)L.cstart[j] * bb, L.Kp, h->scale,
+                    (char*)h->Z + (size_t)L.coff[j] * L.zb, L.spad, st);
     if (e == hipSuccess) e = bs::zw(L.prec, h->Z, L.spad, rows, L.spad, wop, L.mp, pbuf, st);
     if (e == hipSuccess) e = bs::scores_out(pbuf, rows, L.m, L.mp, out + r0 * L.m, st);
   }
@@ -596,6 +601,70 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
   if (e != hipSuccess) return hip_fail(e, "predict");
   if (e2 != hipSuccess) return hip_fail(e2, "predict synchronize");
   if (st != h->st) HCHK(hipStreamSynchronize(h->st));
+  return BSADMM_OK;
+}
+
+int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F) {
+  g_err.clear();
+  if (!h || !F) return fail(BSADMM_EINVAL, "NULL argument");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  const Plan& L = h->L;
+  hipStream_t st = h->st;
+  constexpr int NB = 1024;
+  double *wpad = nullptr, *part = nullptr;
+  void* wop = nullptr;
+  auto cleanup = [&]() {
+    if (wpad) (void)hipFree(wpad);
+    if (part) (void)hipFree(part);
+    if (wop) (void)hipFree(wop);
+  };
+  if (hipMalloc((void**)&wpad, (size_t)L.spad * L.mp * 8) != hipSuccess ||
+      hipMalloc((void**)&part, 2 * NB * 8) != hipSuccess ||
+      hipMalloc(&wop, (size_t)L.spad * L.mp * L.vb) != hipSuccess) {
+    cleanup();
+    return fail(BSADMM_ENOMEM, "hipMalloc failed in objective");
+  }
+  hipError_t e = hipSuccess;
+  if (Wmodel) {
+    e = hipMemsetAsync(wpad, 0, (size_t)L.spad * L.mp * 8, st);
+    for (int j = 0; j < L.C && e == hipSuccess; ++j)
+      e = bs::pad(Wmodel + (size_t)L.cstart[j] * L.m, L.sj[j], L.m, L.mp,
+                  wpad + (size_t)L.coff[j] * L.mp, st);
+  } else {
+    e = hipMemcpyAsync(wpad, h->Wbar, (size_t)L.spad * L.mp * 8, hipMemcpyDeviceToDevice, st);
+  }
+  if (e == hipSuccess) e = bs::to_op(L.prec, wpad, L.spad * L.mp, wop, st);
+  // forward pass Z W over all rows into the P buffer (free between iterations)
+  for (size_t g = 0; g < L.groups.size() && e == hipSuccess; ++g) {
+    const int i0 = L.groups[g].first, i1 = L.groups[g].second;
+    const int64_t r0 = L.rstart[i0];
+    e = regen_group(h, i0, i1, h->Xp, L.n * L.Kp);
+    for (int i = i0; i < i1 && e == hipSuccess; ++i) {
+      const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
+      e = bs::zw(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb, L.spad, ni,
+                 L.spad, wop, L.mp, h->P + (size_t)ri * L.mp, st);
+    }
+  }
+  if (e == hipSuccess)
+    e = bs::loss_partial(h->p.loss == BSADMM_SQUARED ? 0 : 1, h->P, h->p.Y, L.n, L.m, L.mp, part,
+                         NB, st);
+  if (e == hipSuccess) e = bs::sumsq_partial(wpad, L.spad * L.mp, part + NB, NB, st);
+  std::vector<double> hp(2 * NB);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, 2 * NB * 8, hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "objective");
+  }
+  if (e2 != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e2, "objective synchronize");
+  }
+  double loss = 0.0, reg = 0.0;
+  for (int k = 0; k < NB; ++k) loss += hp[k];
+  for (int k = 0; k < NB; ++k) reg += hp[NB + k];
+  *F = loss / (double)L.n + h->p.lambda * reg;
   return BSADMM_OK;
 }
 
@@ -610,14 +679,14 @@ int bsadmm_destroy(bsadmm_handle* h) {
 int rff_map(const float* X, int64_t n, int64_t d, const float* W, const float* b, int64_t s,
             int32_t precision, void* Z_out, void* stream) {
   g_err.clear();
-  if (precision != BSADMM_FP64 && precision != BSADMM_FP32 && precision != BSADMM_BF16)
+  if (precision < BSADMM_FP64 || precision > BSADMM_BF16X3)
     return fail(BSADMM_EINVAL, "unknown precision");
   if (n < 0 || d < 1 || s < 1) return fail(BSADMM_EINVAL, "need n >= 0, d >= 1, s >= 1");
   if (n == 0) return BSADMM_OK;
   if (!X || !W || !b || !Z_out) return fail(BSADMM_EINVAL, "NULL pointer");
   hipStream_t st = (hipStream_t)stream;
   const int64_t Kp = bs::padded_k(precision, d);
-  const size_t op = bs::op_bytes(precision);
+  const size_t op = bs::op_bytes(precision) * bs::op_planes(precision);
   void *xop = nullptr, *wt = nullptr, *bias = nullptr;
   auto cleanup = [&]() {
     if (xop) (void)hipFree(xop);
@@ -629,10 +698,11 @@ int rff_map(const float* X, int64_t n, int64_t d, const float* W, const float* b
     cleanup();
     return fail(BSADMM_ENOMEM, "hipMalloc failed in rff_map");
   }
-  hipError_t e = bs::prep_rows(precision, X, n, d, Kp, xop, nullptr, st);
-  if (e == hipSuccess) e = bs::prep_w(precision, W, b, d, s, Kp, wt, bias, nullptr, st);
-  if (e == hipSuccess) e = bs::regen(precision, xop, n, wt, s, bias, Kp, std::sqrt(2.0 / (double)s),
-                                     Z_out, s, st);
+  hipError_t e = bs::prep_rows(precision, X, n, d, Kp, xop, n * Kp, nullptr, st);
+  if (e == hipSuccess) e = bs::prep_w(precision, W, b, d, s, Kp, wt, s * Kp, bias, nullptr, st);
+  if (e == hipSuccess)
+    e = bs::regen(precision, xop, n * Kp, n, wt, s * Kp, s, bias, Kp, std::sqrt(2.0 / (double)s),
+                  Z_out, s, st);
   hipError_t e2 = hipStreamSynchronize(st);
   cleanup();
   if (e != hipSuccess) return hip_fail(e, "rff_map");

@@ -8,10 +8,14 @@
 #define BS_PREC_F64 0
 #define BS_PREC_F32 1
 #define BS_PREC_BF16 2
+#define BS_PREC_BF16X3 3  // BF16 head + BF16 residual operands, three products
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+// 16-byte staging register.  A native vector type: arrays of it stay in
+// registers, where arrays of HIP's struct-based uint4 end up in scratch.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------------------
 // Precision traits.  op_t is the MFMA operand element, acc_t the accumulator
@@ -41,12 +45,20 @@ template <> struct Prec<BS_PREC_BF16> {
   static constexpr int VEC = 8;
   static constexpr int KC = 32;
 };
+template <> struct Prec<BS_PREC_BF16X3> {
+  using op_t = uint16_t;
+  using acc_t = float;
+  using accv = v4f;
+  static constexpr int VEC = 8;
+  static constexpr int KC = 32;
+};
 
 // A fragment: the VEC consecutive-k operand values one lane holds.
 template <int P> struct Frag;
 template <> struct Frag<BS_PREC_F64> { double v[4]; };
 template <> struct Frag<BS_PREC_F32> { float v[4]; };
 template <> struct Frag<BS_PREC_BF16> { uint16_t v[8]; };
+template <> struct Frag<BS_PREC_BF16X3> { uint16_t v[8]; };
 
 // One fragment step of a 16x16 output tile.  Lane l holds rows/cols
 // (l % 16) of its operand and the k values kbase + VEC * (l / 16) + t.
@@ -71,6 +83,41 @@ __device__ __forceinline__ void mfma_step(v4f& acc, const Frag<BS_PREC_BF16>& a,
   __builtin_memcpy(&bv, b.v, 16);
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
 }
+__device__ __forceinline__ void mfma_step(v4f& acc, const Frag<BS_PREC_BF16X3>& a,
+                                          const Frag<BS_PREC_BF16X3>& b) {
+  v8bf av, bv;
+  __builtin_memcpy(&av, a.v, 16);
+  __builtin_memcpy(&bv, b.v, 16);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+}
+
+// Four adjacent elements of a stored Z (double, float or bf16 bits) as MFMA
+// operands of the product kernels (FP64 for double, FP32 otherwise).
+template <typename ZT> struct ZAcc { using type = float; };
+template <> struct ZAcc<double> { using type = double; };
+template <typename ZT>
+__device__ __forceinline__ void load_z4(const ZT* p, typename ZAcc<ZT>::type (&v)[4]) {
+  if constexpr (sizeof(ZT) == 8) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    double2 x = q[0], y = q[1];
+    v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+  } else if constexpr (sizeof(ZT) == 4) {
+    float4 x = *reinterpret_cast<const float4*>(p);
+    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+  } else {
+    uint2 x = *reinterpret_cast<const uint2*>(p);
+    v[0] = __builtin_bit_cast(float, x.x << 16);
+    v[1] = __builtin_bit_cast(float, x.x & 0xffff0000u);
+    v[2] = __builtin_bit_cast(float, x.y << 16);
+    v[3] = __builtin_bit_cast(float, x.y & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 // Row (within a 16 x 16 tile) of the accumulator element a lane of group
 // g = lane / 16 holds in register r; its column is lane % 16.  The FP32
@@ -91,7 +138,7 @@ __device__ __forceinline__ Frag<P> load_frag(const typename Prec<P>::op_t* p) {
   } else if constexpr (P == BS_PREC_F32) {
     float4 x = *reinterpret_cast<const float4*>(p);
     f.v[0] = x.x; f.v[1] = x.y; f.v[2] = x.z; f.v[3] = x.w;
-  } else {
+  } else {  // BF16 / BF16X3: 8 bf16
     uint4 x = *reinterpret_cast<const uint4*>(p);
     __builtin_memcpy(f.v, &x, 16);
   }

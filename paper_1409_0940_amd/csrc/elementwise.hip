@@ -128,7 +128,61 @@ __global__ void scores_kernel(const double* __restrict__ P, int64_t rows, int64_
   }
 }
 
+// Fixed-order block reduction helper: 256 threads, result in red[0].
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// part[block] = sum over this block's grid-stride elements of V(y, o)
+// (squared: (y - o)^2; hinge: max(0, 1 - y o)).
+__global__ void loss_partial_kernel(int loss, const double* __restrict__ P,
+                                    const float* __restrict__ Y, int64_t n, int64_t m, int64_t mp,
+                                    double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  GRID_STRIDE(e, n * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const double o = P[r * mp + c], y = (double)Y[e];
+    if (loss == 0) {
+      const double d = y - o;
+      acc += d * d;
+    } else {
+      const double h = 1.0 - y * o;
+      acc += h > 0.0 ? h : 0.0;
+    }
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void sumsq_partial_kernel(const double* __restrict__ a, int64_t count,
+                                     double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  GRID_STRIDE(e, count) acc += a[e] * a[e];
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 }  // namespace
+
+hipError_t loss_partial(int loss, const double* P, const float* Y, int64_t n, int64_t m,
+                        int64_t mp, double* part, int nblocks, hipStream_t st) {
+  loss_partial_kernel<<<nblocks, 256, 0, st>>>(loss, P, Y, n, m, mp, part);
+  return hipGetLastError();
+}
+
+hipError_t sumsq_partial(const double* a, int64_t count, double* part, int nblocks,
+                         hipStream_t st) {
+  sumsq_partial_kernel<<<nblocks, 256, 0, st>>>(a, count, part);
+  return hipGetLastError();
+}
 
 hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int64_t m, int64_t mp,
                    const float* Y, const double* Obar, const double* nu, const double* Dbar,
@@ -137,12 +191,9 @@ hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int64
   if (prec == BS_PREC_F64)
     row_pre_kernel<double><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
                                                (double*)Rop);
-  else if (prec == BS_PREC_F32)
+  else
     row_pre_kernel<float><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
                                               (float*)Rop);
-  else
-    row_pre_kernel<uint16_t><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
-                                                 (uint16_t*)Rop);
   return hipGetLastError();
 }
 
@@ -184,10 +235,8 @@ hipError_t to_op(int prec, const double* src, int64_t count, void* dst, hipStrea
   unsigned g = grid_for(count);
   if (prec == BS_PREC_F64)
     to_op_kernel<double><<<g, 256, 0, st>>>(src, count, (double*)dst);
-  else if (prec == BS_PREC_F32)
-    to_op_kernel<float><<<g, 256, 0, st>>>(src, count, (float*)dst);
   else
-    to_op_kernel<uint16_t><<<g, 256, 0, st>>>(src, count, (uint16_t*)dst);
+    to_op_kernel<float><<<g, 256, 0, st>>>(src, count, (float*)dst);
   return hipGetLastError();
 }
 

@@ -351,12 +351,9 @@ hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, co
   if (prec == BS_PREC_F64)
     solve_kernel<BS_PREC_F64, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
                                                       (double*)Wop);
-  else if (prec == BS_PREC_F32)
+  else  // the product operands are FP32 for every other precision
     solve_kernel<BS_PREC_F32, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
                                                       (float*)Wop);
-  else
-    solve_kernel<BS_PREC_BF16, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
-                                                       (uint16_t*)Wop);
   return hipGetLastError();
 }
 

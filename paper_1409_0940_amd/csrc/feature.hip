@@ -12,20 +12,19 @@ namespace {
 
 constexpr int BM = 128;          // rows of Z per workgroup
 constexpr int BN = 128;          // features of Z per workgroup
-constexpr int KROW_BYTES = 128;  // bytes of k per LDS row and chunk
-constexpr int LDS_PITCH = KROW_BYTES + 16;
 constexpr int NTHREADS = 256;
 constexpr int GROUP_M = 8;
 
-template <int P> constexpr int bk_elems() { return KROW_BYTES / (int)sizeof(typename Prec<P>::op_t); }
 
 // ---------------------------------------------------------------------------
 // Operand preparation
 // ---------------------------------------------------------------------------
+// Row operands; BF16X3 writes the head plane at dst and the residual plane at
+// dst + plane (elements).
 template <int P>
 __global__ void prep_rows_kernel(const float* __restrict__ src, int64_t rows, int64_t d,
                                  int64_t Kp, typename Prec<P>::op_t* __restrict__ dst,
-                                 int* __restrict__ flag) {
+                                 int64_t plane, int* __restrict__ flag) {
   using op_t = typename Prec<P>::op_t;
   int64_t total = rows * Kp;
   int bad = 0;
@@ -34,7 +33,9 @@ __global__ void prep_rows_kernel(const float* __restrict__ src, int64_t rows, in
     int64_t r = e / Kp, k = e - r * Kp;
     float v = (k < d) ? src[r * d + k] : 0.0f;
     if (!__builtin_isfinite(v)) bad = 1;
-    dst[e] = cvt_from_float<op_t>(v);
+    const op_t h = cvt_from_float<op_t>(v);
+    dst[e] = h;
+    if constexpr (P == BS_PREC_BF16X3) dst[plane + e] = f32_to_bf16(v - bf16_to_f32(h));
   }
   if (bad && flag) atomicOr(flag, 1);
 }
@@ -42,7 +43,8 @@ __global__ void prep_rows_kernel(const float* __restrict__ src, int64_t rows, in
 // W is d x s (ld = s); Wt is s x Kp.  32 x 32 tiles through LDS.
 template <int P>
 __global__ void prep_w_kernel(const float* __restrict__ W, int64_t d, int64_t s, int64_t Kp,
-                              typename Prec<P>::op_t* __restrict__ Wt, int* __restrict__ flag) {
+                              typename Prec<P>::op_t* __restrict__ Wt, int64_t plane,
+                              int* __restrict__ flag) {
   using op_t = typename Prec<P>::op_t;
   __shared__ float tile[32][33];
   int64_t f0 = (int64_t)blockIdx.x * 32, k0 = (int64_t)blockIdx.y * 32;
@@ -57,7 +59,12 @@ __global__ void prep_w_kernel(const float* __restrict__ W, int64_t d, int64_t s,
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
     int64_t f = f0 + yy, k = k0 + tx;
-    if (f < s && k < Kp) Wt[f * Kp + k] = cvt_from_float<op_t>(tile[tx][yy]);
+    if (f < s && k < Kp) {
+      const float v = tile[tx][yy];
+      const op_t h = cvt_from_float<op_t>(v);
+      Wt[f * Kp + k] = h;
+      if constexpr (P == BS_PREC_BF16X3) Wt[plane + f * Kp + k] = f32_to_bf16(v - bf16_to_f32(h));
+    }
   }
   if (bad && flag) atomicOr(flag, 1);
 }
@@ -85,13 +92,22 @@ __global__ void check_finite_kernel(const float* __restrict__ p, int64_t count, 
 // Regeneration GEMM.  Xp (rows x Kp) and Wt (cols x Kp) are both k-contiguous.
 // A 256-thread workgroup computes a 128 x 128 tile of Z; its 4 waves each own
 // a 64 x 64 quadrant made of 4 x 4 MFMA 16 x 16 tiles.  k advances in chunks
-// of 128 bytes staged through double-buffered LDS; the next chunk's global
-// loads are in flight while the current one feeds the MFMAs.
+// staged through double-buffered LDS; the next chunk's global loads are in
+// flight while the current one feeds the MFMAs.
+//
+// BF16X3 operands come in two planes (plane stride xps / wps elements): the
+// BF16 head h = bf16(v) and the BF16 residual l = bf16(v - h).  The phase
+// accumulates h_x h_w + h_x l_w + l_x h_w in FP32 (the dropped l_x l_w term is
+// ~2^-16 of the product), so the phase keeps ~16 significant bits instead of
+// the ~8 of a single BF16 product.
 // ---------------------------------------------------------------------------
+template <int P> constexpr int planes() { return P == BS_PREC_BF16X3 ? 2 : 1; }
+template <int P> constexpr int krow_bytes() { return P == BS_PREC_BF16X3 ? 64 : 128; }
+
 template <int P, typename ZT>
 __global__ void __launch_bounds__(NTHREADS, 2)
-regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t rows,
-             const typename Prec<P>::op_t* __restrict__ Wt, int64_t cols,
+regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t rows,
+             const typename Prec<P>::op_t* __restrict__ Wt, int64_t wps, int64_t cols,
              const typename Prec<P>::acc_t* __restrict__ bias, int64_t Kp,
              typename Prec<P>::acc_t scale, ZT* __restrict__ Z, int64_t ldz) {
   using op_t = typename Prec<P>::op_t;
@@ -99,10 +115,15 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t rows,
   using accv = typename Prec<P>::accv;
   constexpr int VEC = Prec<P>::VEC;
   constexpr int KC = Prec<P>::KC;
-  constexpr int BK = bk_elems<P>();
-  constexpr int STEPS = BK / KC;  // fragment steps per chunk
+  constexpr int NPL = planes<P>();
+  constexpr int KROW = krow_bytes<P>();
+  constexpr int PITCH = KROW + 16;
+  constexpr int BK = KROW / (int)sizeof(op_t);
+  constexpr int STEPS = BK / KC;           // fragment steps per chunk
+  constexpr int SEGS = KROW / 16;          // 16-byte segments per staged row
+  constexpr int NS = BM * SEGS / NTHREADS; // staged segments per thread, per plane
 
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2][BM * LDS_PITCH];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2][NPL][BM * PITCH];
 
   const int tiles_m = (int)((rows + BM - 1) / BM);
   const int tiles_n = (int)((cols + BN - 1) / BN);
@@ -119,45 +140,22 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t rows,
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  // global -> register staging: 128 rows x 128 bytes per operand = 1024 x 16 B
-  const unsigned char* gA[4];
-  const unsigned char* gB[4];
-  int ldsoff[4];
+  const unsigned char* gA[NS];
+  const unsigned char* gB[NS];
+  int ldsoff[NS];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    int idx = tid + NTHREADS * i;
-    int r = idx >> 3, seg = idx & 7;
-    int64_t ra = min(row0 + r, rows - 1);
-    int64_t rb = min(col0 + r, cols - 1);
+  for (int i = 0; i < NS; ++i) {
+    const int idx = tid + NTHREADS * i;
+    const int r = idx / SEGS, seg = idx % SEGS;
+    const int64_t ra = min(row0 + r, rows - 1);
+    const int64_t rb = min(col0 + r, cols - 1);
     gA[i] = reinterpret_cast<const unsigned char*>(Xp + ra * Kp) + seg * 16;
     gB[i] = reinterpret_cast<const unsigned char*>(Wt + rb * Kp) + seg * 16;
-    ldsoff[i] = r * LDS_PITCH + seg * 16;
+    ldsoff[i] = r * PITCH + seg * 16;
   }
+  const int64_t xpb = xps * (int64_t)sizeof(op_t), wpb = wps * (int64_t)sizeof(op_t);
   const int64_t nchunks = Kp / BK;
-  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-#define BS_GLOAD(c)                                                          \
-  do {                                                                       \
-    const int64_t off_ = (c) * KROW_BYTES;                                   \
-    ra0 = *reinterpret_cast<const uint4*>(gA[0] + off_);                     \
-    ra1 = *reinterpret_cast<const uint4*>(gA[1] + off_);                     \
-    ra2 = *reinterpret_cast<const uint4*>(gA[2] + off_);                     \
-    ra3 = *reinterpret_cast<const uint4*>(gA[3] + off_);                     \
-    rb0 = *reinterpret_cast<const uint4*>(gB[0] + off_);                     \
-    rb1 = *reinterpret_cast<const uint4*>(gB[1] + off_);                     \
-    rb2 = *reinterpret_cast<const uint4*>(gB[2] + off_);                     \
-    rb3 = *reinterpret_cast<const uint4*>(gB[3] + off_);                     \
-  } while (0)
-#define BS_LSTORE(buf)                                                       \
-  do {                                                                       \
-    *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[0]]) = ra0;                \
-    *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[1]]) = ra1;                \
-    *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[2]]) = ra2;                \
-    *reinterpret_cast<uint4*>(&lds[buf][0][ldsoff[3]]) = ra3;                \
-    *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[0]]) = rb0;                \
-    *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[1]]) = rb1;                \
-    *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[2]]) = rb2;                \
-    *reinterpret_cast<uint4*>(&lds[buf][1][ldsoff[3]]) = rb3;                \
-  } while (0)
+  u32x4 sa[NPL][NS], sb[NPL][NS];
 
   accv acc[4][4];
 #pragma unroll
@@ -167,35 +165,71 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t rows,
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  BS_GLOAD(0);
-  BS_LSTORE(0);
+  // prologue: chunk 0 into LDS buffer 0
+#pragma unroll
+  for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      sa[pl][i] = *reinterpret_cast<const u32x4*>(gA[i] + pl * xpb);
+      sb[pl][i] = *reinterpret_cast<const u32x4*>(gB[i] + pl * wpb);
+    }
+#pragma unroll
+  for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      *reinterpret_cast<u32x4*>(&lds[0][0][pl][ldsoff[i]]) = sa[pl][i];
+      *reinterpret_cast<u32x4*>(&lds[0][1][pl][ldsoff[i]]) = sb[pl][i];
+    }
   __syncthreads();
   const int fr = lane & 15, fg = lane >> 4;
   for (int64_t c = 0; c < nchunks; ++c) {
     const int buf = (int)(c & 1);
     const bool more = c + 1 < nchunks;
-    if (more) BS_GLOAD(c + 1);
+    if (more) {
+      const int64_t off = (c + 1) * KROW;
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          sa[pl][i] = *reinterpret_cast<const u32x4*>(gA[i] + pl * xpb + off);
+          sb[pl][i] = *reinterpret_cast<const u32x4*>(gB[i] + pl * wpb + off);
+        }
+    }
 #pragma unroll
     for (int ks = 0; ks < STEPS; ++ks) {
-      Frag<P> fa[4], fb[4];
       const int kbyte = (ks * KC + VEC * fg) * (int)sizeof(op_t);
+      Frag<P> fa[NPL][4], fb[NPL][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        fa[i] = load_frag<P>(reinterpret_cast<const op_t*>(
-            &lds[buf][0][(wm * 64 + i * 16 + fr) * LDS_PITCH + kbyte]));
-        fb[i] = load_frag<P>(reinterpret_cast<const op_t*>(
-            &lds[buf][1][(wn * 64 + i * 16 + fr) * LDS_PITCH + kbyte]));
-      }
+      for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          fa[pl][i] = load_frag<P>(reinterpret_cast<const op_t*>(
+              &lds[buf][0][pl][(wm * 64 + i * 16 + fr) * PITCH + kbyte]));
+          fb[pl][i] = load_frag<P>(reinterpret_cast<const op_t*>(
+              &lds[buf][1][pl][(wn * 64 + i * 16 + fr) * PITCH + kbyte]));
+        }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) mfma_step(acc[i][j], fa[i], fb[j]);
+        for (int j = 0; j < 4; ++j) {
+          mfma_step(acc[i][j], fa[0][i], fb[0][j]);
+          if constexpr (NPL == 2) {
+            mfma_step(acc[i][j], fa[0][i], fb[1][j]);
+            mfma_step(acc[i][j], fa[1][i], fb[0][j]);
+          }
+        }
     }
-    if (more) BS_LSTORE(buf ^ 1);
+    if (more) {
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          *reinterpret_cast<u32x4*>(&lds[buf ^ 1][0][pl][ldsoff[i]]) = sa[pl][i];
+          *reinterpret_cast<u32x4*>(&lds[buf ^ 1][1][pl][ldsoff[i]]) = sb[pl][i];
+        }
+    }
     __syncthreads();
   }
-#undef BS_GLOAD
-#undef BS_LSTORE
 
   // Epilogue: lane holds D[acc_row(lane / 16, r)][lane % 16] of each 16 x 16 tile.
 #pragma unroll
@@ -235,7 +269,7 @@ inline unsigned grid_1d(int64_t count, int threads, int64_t cap = 65536) {
 }  // namespace
 
 int64_t padded_k(int prec, int64_t d) {
-  int64_t bk = KROW_BYTES / (int64_t)op_bytes(prec);
+  const int64_t bk = (prec == BS_PREC_BF16X3 ? 64 : 128) / (int64_t)op_bytes(prec);
   return ((d + bk - 1) / bk) * bk;
 }
 
@@ -243,31 +277,55 @@ size_t op_bytes(int prec) {
   return prec == BS_PREC_F64 ? 8 : (prec == BS_PREC_F32 ? 4 : 2);
 }
 
+int op_planes(int prec) { return prec == BS_PREC_BF16X3 ? 2 : 1; }
+
+size_t z_bytes(int prec) {
+  return prec == BS_PREC_F64 ? 8 : (prec == BS_PREC_BF16 ? 2 : 4);
+}
+
+size_t vec_bytes(int prec) { return prec == BS_PREC_F64 ? 8 : 4; }
+
 hipError_t prep_rows(int prec, const float* src, int64_t rows, int64_t d, int64_t Kp, void* dst,
-                     int* flag, hipStream_t st) {
+                     int64_t plane, int* flag, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   unsigned g = grid_1d(rows * Kp, 256);
-  if (prec == BS_PREC_F64)
-    prep_rows_kernel<BS_PREC_F64><<<g, 256, 0, st>>>(src, rows, d, Kp, (double*)dst, flag);
-  else if (prec == BS_PREC_F32)
-    prep_rows_kernel<BS_PREC_F32><<<g, 256, 0, st>>>(src, rows, d, Kp, (float*)dst, flag);
-  else
-    prep_rows_kernel<BS_PREC_BF16><<<g, 256, 0, st>>>(src, rows, d, Kp, (uint16_t*)dst, flag);
+  switch (prec) {
+    case BS_PREC_F64:
+      prep_rows_kernel<BS_PREC_F64><<<g, 256, 0, st>>>(src, rows, d, Kp, (double*)dst, plane, flag);
+      break;
+    case BS_PREC_F32:
+      prep_rows_kernel<BS_PREC_F32><<<g, 256, 0, st>>>(src, rows, d, Kp, (float*)dst, plane, flag);
+      break;
+    case BS_PREC_BF16:
+      prep_rows_kernel<BS_PREC_BF16><<<g, 256, 0, st>>>(src, rows, d, Kp, (uint16_t*)dst, plane,
+                                                         flag);
+      break;
+    default:
+      prep_rows_kernel<BS_PREC_BF16X3><<<g, 256, 0, st>>>(src, rows, d, Kp, (uint16_t*)dst, plane,
+                                                           flag);
+  }
   return hipGetLastError();
 }
 
 hipError_t prep_w(int prec, const float* W, const float* b, int64_t d, int64_t s, int64_t Kp,
-                  void* Wt, void* bias, int* flag, hipStream_t st) {
+                  void* Wt, int64_t plane, void* bias, int* flag, hipStream_t st) {
   dim3 g((unsigned)((s + 31) / 32), (unsigned)((Kp + 31) / 32));
-  if (prec == BS_PREC_F64) {
-    prep_w_kernel<BS_PREC_F64><<<g, 256, 0, st>>>(W, d, s, Kp, (double*)Wt, flag);
-    prep_bias_kernel<double><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (double*)bias, flag);
-  } else if (prec == BS_PREC_F32) {
-    prep_w_kernel<BS_PREC_F32><<<g, 256, 0, st>>>(W, d, s, Kp, (float*)Wt, flag);
-    prep_bias_kernel<float><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (float*)bias, flag);
-  } else {
-    prep_w_kernel<BS_PREC_BF16><<<g, 256, 0, st>>>(W, d, s, Kp, (uint16_t*)Wt, flag);
-    prep_bias_kernel<float><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (float*)bias, flag);
+  switch (prec) {
+    case BS_PREC_F64:
+      prep_w_kernel<BS_PREC_F64><<<g, 256, 0, st>>>(W, d, s, Kp, (double*)Wt, plane, flag);
+      prep_bias_kernel<double><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (double*)bias, flag);
+      break;
+    case BS_PREC_F32:
+      prep_w_kernel<BS_PREC_F32><<<g, 256, 0, st>>>(W, d, s, Kp, (float*)Wt, plane, flag);
+      prep_bias_kernel<float><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (float*)bias, flag);
+      break;
+    case BS_PREC_BF16:
+      prep_w_kernel<BS_PREC_BF16><<<g, 256, 0, st>>>(W, d, s, Kp, (uint16_t*)Wt, plane, flag);
+      prep_bias_kernel<float><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (float*)bias, flag);
+      break;
+    default:
+      prep_w_kernel<BS_PREC_BF16X3><<<g, 256, 0, st>>>(W, d, s, Kp, (uint16_t*)Wt, plane, flag);
+      prep_bias_kernel<float><<<grid_1d(s, 256), 256, 0, st>>>(b, s, (float*)bias, flag);
   }
   return hipGetLastError();
 }
@@ -278,25 +336,34 @@ hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t regen(int prec, const void* Xp, int64_t rows, const void* Wt, int64_t cols,
-                 const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
+hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
+                 int64_t cols, const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
                  hipStream_t st) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   int64_t tiles = ((rows + BM - 1) / BM) * ((cols + BN - 1) / BN);
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
   dim3 g((unsigned)tiles);
-  if (prec == BS_PREC_F64)
-    regen_kernel<BS_PREC_F64, double><<<g, NTHREADS, 0, st>>>(
-        (const double*)Xp, rows, (const double*)Wt, cols, (const double*)bias, Kp, scale,
-        (double*)Z, ldz);
-  else if (prec == BS_PREC_F32)
-    regen_kernel<BS_PREC_F32, float><<<g, NTHREADS, 0, st>>>(
-        (const float*)Xp, rows, (const float*)Wt, cols, (const float*)bias, Kp, (float)scale,
-        (float*)Z, ldz);
-  else
-    regen_kernel<BS_PREC_BF16, uint16_t><<<g, NTHREADS, 0, st>>>(
-        (const uint16_t*)Xp, rows, (const uint16_t*)Wt, cols, (const float*)bias, Kp,
-        (float)scale, (uint16_t*)Z, ldz);
+  switch (prec) {
+    case BS_PREC_F64:
+      regen_kernel<BS_PREC_F64, double><<<g, NTHREADS, 0, st>>>(
+          (const double*)Xp, xps, rows, (const double*)Wt, wps, cols, (const double*)bias, Kp,
+          scale, (double*)Z, ldz);
+      break;
+    case BS_PREC_F32:
+      regen_kernel<BS_PREC_F32, float><<<g, NTHREADS, 0, st>>>(
+          (const float*)Xp, xps, rows, (const float*)Wt, wps, cols, (const float*)bias, Kp,
+          (float)scale, (float*)Z, ldz);
+      break;
+    case BS_PREC_BF16:
+      regen_kernel<BS_PREC_BF16, uint16_t><<<g, NTHREADS, 0, st>>>(
+          (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,
+          (float)scale, (uint16_t*)Z, ldz);
+      break;
+    default:
+      regen_kernel<BS_PREC_BF16X3, float><<<g, NTHREADS, 0, st>>>(
+          (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,
+          (float)scale, (float*)Z, ldz);
+  }
   return hipGetLastError();
 }
 

@@ -8,23 +8,31 @@ namespace bs {
 
 // Operand row width (k padded) for a precision: multiple of the K chunk.
 int64_t padded_k(int prec, int64_t d);
+// Bytes of one operand element (per plane), operand planes (2 for BF16X3:
+// head and residual), bytes of one stored Z element, and bytes of one
+// element of the product operands R and W' (FP64 or FP32).
 size_t op_bytes(int prec);
+int op_planes(int prec);
+size_t z_bytes(int prec);
+size_t vec_bytes(int prec);
 
 // Rows [0, rows) of a float32 matrix (ld = d) -> operand layout (ld = Kp,
-// zero padded).  Sets *flag |= 1 if a value is not finite.
+// zero padded; BF16X3 writes the residual plane at dst + plane elements).
+// Sets *flag |= 1 if a value is not finite.
 hipError_t prep_rows(int prec, const float* src, int64_t rows, int64_t d, int64_t Kp,
-                     void* dst, int* flag, hipStream_t st);
-// W (d x s, ld = s) -> Wt (s x Kp), transposed and padded; bias copy.
+                     void* dst, int64_t plane, int* flag, hipStream_t st);
+// W (d x s, ld = s) -> Wt (s x Kp), transposed and padded (residual plane at
+// Wt + plane); bias copy.
 hipError_t prep_w(int prec, const float* W, const float* b, int64_t d, int64_t s, int64_t Kp,
-                  void* Wt, void* bias, int* flag, hipStream_t st);
+                  void* Wt, int64_t plane, void* bias, int* flag, hipStream_t st);
 // Non-finite check of a float32 array.
 hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st);
 
 // Z[r][f] = scale * cos(sum_k Xp[r][k] Wt[f][k] + bias[f]) for r < rows,
-// f < cols; Z has leading dimension ldz and the operand element type
-// (double / float / bf16 bits).
-hipError_t regen(int prec, const void* Xp, int64_t rows, const void* Wt, int64_t cols,
-                 const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
+// f < cols; Z has leading dimension ldz and the stored type of the precision
+// (double / float / bf16 bits / float).  xps, wps: plane strides (BF16X3).
+hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
+                 int64_t cols, const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
                  hipStream_t st);
 
 // The padded feature index: feature block j occupies [coff_j, coff_j + s_j)
@@ -81,6 +89,13 @@ hipError_t pad(const double* src, int64_t rows, int64_t m, int64_t mp, double* d
                hipStream_t st);
 // Operand copy of a padded FP64 array (rows x mp) into op type.
 hipError_t to_op(int prec, const double* src, int64_t count, void* dst, hipStream_t st);
+// Deterministic partial sums (one per workgroup, nblocks <= 65536, summed by
+// the caller in order): sum of V(y_rc, P_rc) over r < n, c < m (loss 0:
+// squared, otherwise hinge), and sum of squares of a.
+hipError_t loss_partial(int loss, const double* P, const float* Y, int64_t n, int64_t m,
+                        int64_t mp, double* part, int nblocks, hipStream_t st);
+hipError_t sumsq_partial(const double* a, int64_t count, double* part, int nblocks,
+                         hipStream_t st);
 // Scores out[r][c] = (float) P[r][c], c < m.
 hipError_t scores_out(const double* P, int64_t rows, int64_t m, int64_t mp, float* out,
                       hipStream_t st);

@@ -17,6 +17,10 @@ namespace bs {
 
 namespace {
 
+template <typename T> struct V4;
+template <> struct V4<double> { using type = v4d; };
+template <> struct V4<float> { using type = v4f; };
+
 // ---------------------------------------------------------------------------
 // Partial transpose products, one row block per launch:
 // part[sp][f][c] = sum_{r in split sp} Z[r][f] Rop[r][c].
@@ -27,13 +31,13 @@ namespace {
 // the same rows of Rop.  U groups of 4 rows are loaded before they are
 // consumed so that enough bytes are in flight to cover HBM latency.
 // ---------------------------------------------------------------------------
-template <int P, int NTC, int U>
+template <typename ZT, int NTC, int U>
 __global__ void __launch_bounds__(256)
-ztr_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
-           const typename Prec<P>::op_t* __restrict__ Rop, int64_t mp, int64_t split_rows,
-           typename Prec<P>::acc_t* __restrict__ part) {
-  using op_t = typename Prec<P>::op_t;
-  using accv = typename Prec<P>::accv;
+ztr_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
+           const typename ZAcc<ZT>::type* __restrict__ Rop, int64_t mp, int64_t split_rows,
+           typename ZAcc<ZT>::type* __restrict__ part) {
+  using op_t = typename ZAcc<ZT>::type;
+  using accv = typename V4<op_t>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
   const int64_t f0 = (int64_t)blockIdx.x * 256 + wave * 64;
@@ -54,7 +58,7 @@ ztr_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t ro
 
   if (f0 < s) {
     for (int64_t rb = rbeg; rb < rend; rb += 4 * U) {
-      Frag<P> a[U];
+      op_t a[U][4];
       op_t bv[U][NTC];
       bool ok[U];
 #pragma unroll
@@ -62,7 +66,7 @@ ztr_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t ro
         const int64_t r = rb + 4 * u + fg;
         ok[u] = r < rend;
         const int64_t rl = ok[u] ? r : rend - 1;   // in-bounds row; its weight is zeroed
-        a[u] = load_frag<P>(Z + rl * ldz + fl);
+        load_z4<ZT>(Z + rl * ldz + fl, a[u]);
 #pragma unroll
         for (int t = 0; t < NTC; ++t) {
           const int nt = min(nc0 + t, ntiles - 1);
@@ -77,12 +81,7 @@ ztr_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t ro
         for (int t = 0; t < NTC; ++t) {
           const op_t b = ok[u] ? bv[u][t] : (op_t)0;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if constexpr (P == BS_PREC_F64)
-              acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].v[q], b, acc[q][t], 0, 0, 0);
-            else
-              acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u].v[q], b, acc[q][t], 0, 0, 0);
-          }
+          for (int q = 0; q < 4; ++q) acc[q][t] = mfma4(a[u][q], b, acc[q][t]);
         }
     }
   }
@@ -95,7 +94,7 @@ ztr_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t ro
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t f = f0 + 4 * acc_row<typename Prec<P>::acc_t>(fg, r) + q;
+        const int64_t f = f0 + 4 * acc_row<op_t>(fg, r) + q;
         if (f < s) part[(sp * s + f) * mp + nt * 16 + fr] = acc[q][t][r];
       }
   }
@@ -131,11 +130,12 @@ __global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max
 // sharing every Wop value), a workgroup 128; U fragment steps are loaded
 // before they are consumed.  Pad columns of Z and pad rows of Wop are zero.
 // ---------------------------------------------------------------------------
-template <int P, int NTC, int U>
+template <typename ZT, int NTC, int U>
 __global__ void __launch_bounds__(256)
-zw_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
-          const typename Prec<P>::op_t* __restrict__ Wop, int64_t mp, double* __restrict__ Pout) {
-  using accv = typename Prec<P>::accv;
+zw_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
+          const typename ZAcc<ZT>::type* __restrict__ Wop, int64_t mp, double* __restrict__ Pout) {
+  using op_t = typename ZAcc<ZT>::type;
+  using accv = typename V4<op_t>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
@@ -152,11 +152,11 @@ zw_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t row
     const auto* z0 = Z + min(r0 + fr, rows - 1) * ldz + 4 * fg;
     const auto* z1 = Z + min(r0 + 16 + fr, rows - 1) * ldz + 4 * fg;
     for (int64_t f0 = 0; f0 < s16; f0 += 16 * U) {
-      Frag<P> a0[U], a1[U], b[U][NTC];
+      op_t a0[U][4], a1[U][4], b[U][NTC][4];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        a0[u] = load_frag<P>(z0 + f0 + 16 * u);
-        a1[u] = load_frag<P>(z1 + f0 + 16 * u);
+        load_z4<ZT>(z0 + f0 + 16 * u, a0[u]);
+        load_z4<ZT>(z1 + f0 + 16 * u, a1[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -165,17 +165,19 @@ zw_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t row
         for (int t = 0; t < NTC; ++t) {
           const int nt = min(nc0 + t, ntiles - 1);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) b[u][t].v[q] = wb[q * mp + nt * 16];
+          for (int q = 0; q < 4; ++q) b[u][t][q] = wb[q * mp + nt * 16];
         }
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int t = 0; t < NTC; ++t) {
-          mfma_step(acc[0][t], a0[u], b[u][t]);
-          mfma_step(acc[1][t], a1[u], b[u][t]);
-        }
+        for (int t = 0; t < NTC; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc[0][t] = mfma4(a0[u][q], b[u][t][q], acc[0][t]);
+            acc[1][t] = mfma4(a1[u][q], b[u][t][q], acc[1][t]);
+          }
     }
   }
 #pragma unroll
@@ -186,7 +188,7 @@ zw_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t row
       if (nt >= ntiles) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + 16 * h + acc_row<typename Prec<P>::acc_t>(fg, r);
+        const int64_t row = r0 + 16 * h + acc_row<op_t>(fg, r);
         if (row < rows) Pout[row * mp + nt * 16 + fr] = (double)acc[h][t][r];
       }
     }
@@ -197,13 +199,12 @@ zw_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t row
 // 64 x 64 tile (ta, tb), ta >= tb.  The 4 waves take interleaved groups of 4
 // rows and their partial sums are added in wave order through LDS.
 // ---------------------------------------------------------------------------
-template <int P>
+template <typename ZT>
 __global__ void __launch_bounds__(256)
-gram_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
+gram_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
             int64_t sj, double* __restrict__ slot, int64_t S) {
-  using op_t = typename Prec<P>::op_t;
-  using acc_t = typename Prec<P>::acc_t;
-  using accv = typename Prec<P>::accv;
+  using acc_t = typename ZAcc<ZT>::type;
+  using accv = typename V4<acc_t>::type;
   __shared__ acc_t red[64 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
@@ -225,28 +226,23 @@ gram_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t r
 
   for (int64_t rb = 4 * wave; rb < rows; rb += 16) {
     const int64_t r = rb + fg;
-    Frag<P> a, b;
+    acc_t a[4], b[4];
     if (r < rows) {
-      a = load_frag<P>(Z + r * ldz + coff + fa);
-      b = load_frag<P>(Z + r * ldz + coff + fb);
+      load_z4<ZT>(Z + r * ldz + coff + fa, a);
+      load_z4<ZT>(Z + r * ldz + coff + fb, b);
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a.v[q] = b.v[q] = 0;
+      for (int q = 0; q < 4; ++q) a[q] = b[q] = 0;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (fa + q >= sj) a.v[q] = 0;
-      if (fb + q >= sj) b.v[q] = 0;
+      if (fa + q >= sj) a[q] = 0;
+      if (fb + q >= sj) b[q] = 0;
     }
 #pragma unroll
     for (int qa = 0; qa < 4; ++qa)
 #pragma unroll
-      for (int qb = 0; qb < 4; ++qb) {
-        if constexpr (P == BS_PREC_F64)
-          acc[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.v[qa], b.v[qb], acc[qa][qb], 0, 0, 0);
-        else
-          acc[qa][qb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[qa], b.v[qb], acc[qa][qb], 0, 0, 0);
-      }
+      for (int qb = 0; qb < 4; ++qb) acc[qa][qb] = mfma4(a[qa], b[qb], acc[qa][qb]);
   }
   // element (m = acc_row(fg, r), n = fr) of instruction (qa, qb) is
   // G[64 ta + 4 m + qa][64 tb + 4 n + qb]; local index (4 m + qa, 4 n + qb)
@@ -287,35 +283,35 @@ gram_kernel(const typename Prec<P>::op_t* __restrict__ Z, int64_t ldz, int64_t r
   }
 }
 
-}  // namespace
-
-template <int P, int NTC>
+template <typename ZT, int NTC>
 static void launch_ztr(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rop,
                        int64_t mp, int64_t split_rows, void* part, hipStream_t st) {
-  using op_t = typename Prec<P>::op_t;
-  using acc_t = typename Prec<P>::acc_t;
+  using op_t = typename ZAcc<ZT>::type;
   const int ntiles = (int)(mp / 16);
   const int64_t nsplit = (rows + split_rows - 1) / split_rows;
   dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
-  ztr_kernel<P, NTC, 8><<<g, 256, 0, st>>>((const op_t*)Z, ldz, rows, s, (const op_t*)Rop, mp,
-                                          split_rows, (acc_t*)part);
+  ztr_kernel<ZT, NTC, 8><<<g, 256, 0, st>>>((const ZT*)Z, ldz, rows, s, (const op_t*)Rop, mp,
+                                           split_rows, (op_t*)part);
 }
+
+template <typename ZT>
+static void ztr_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rop,
+                         int64_t mp, int64_t split_rows, void* part, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  if (ntiles == 1) launch_ztr<ZT, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+  else if (ntiles == 2 || sizeof(ZT) == 8) launch_ztr<ZT, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+  else launch_ztr<ZT, 4>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+}
+
+}  // namespace
 
 hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s,
                        const void* Rop, int64_t mp, int64_t split_rows, void* part,
                        hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  const int ntiles = (int)(mp / 16);
-  if (prec == BS_PREC_F64) {
-    if (ntiles == 1) launch_ztr<BS_PREC_F64, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else launch_ztr<BS_PREC_F64, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-  } else if (prec == BS_PREC_F32) {
-    if (ntiles == 1) launch_ztr<BS_PREC_F32, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else if (ntiles == 2) launch_ztr<BS_PREC_F32, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else launch_ztr<BS_PREC_F32, 4>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-  } else {
-    return hipErrorNotSupported;
-  }
+  if (prec == BS_PREC_F64) ztr_dispatch<double>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+  else if (prec == BS_PREC_BF16) ztr_dispatch<uint16_t>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+  else ztr_dispatch<float>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
   return hipGetLastError();
 }
 
@@ -334,31 +330,36 @@ hipError_t reduce_rhs(int prec, const void* part, int64_t nsplit_max, int64_t n,
   return hipGetLastError();
 }
 
-template <int P, int NTC>
+namespace {
+
+template <typename ZT, int NTC>
 static void launch_zw(const void* Z, int64_t ldz, int64_t rows, int64_t s16, const void* Wop,
                       int64_t mp, double* Pout, hipStream_t st) {
-  using op_t = typename Prec<P>::op_t;
+  using op_t = typename ZAcc<ZT>::type;
   const int ntiles = (int)(mp / 16);
   dim3 g((unsigned)((rows + 127) / 128), (unsigned)((ntiles + NTC - 1) / NTC));
-  zw_kernel<P, NTC, 4><<<g, 256, 0, st>>>((const op_t*)Z, ldz, rows, s16, (const op_t*)Wop, mp,
-                                         Pout);
+  zw_kernel<ZT, NTC, 4><<<g, 256, 0, st>>>((const ZT*)Z, ldz, rows, s16, (const op_t*)Wop, mp,
+                                          Pout);
 }
+
+template <typename ZT>
+static void zw_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s16, const void* Wop,
+                        int64_t mp, double* Pout, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  if (ntiles == 1) launch_zw<ZT, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+  else if (ntiles == 2 || sizeof(ZT) == 8) launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+  else launch_zw<ZT, 4>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+}
+
+}  // namespace
 
 hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Wop,
               int64_t mp, double* Pout, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  const int ntiles = (int)(mp / 16);
   const int64_t s16 = (s + 63) / 64 * 64;  // multiple of the 4-step unroll (s is 64-aligned)
-  if (prec == BS_PREC_F64) {
-    if (ntiles == 1) launch_zw<BS_PREC_F64, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else launch_zw<BS_PREC_F64, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-  } else if (prec == BS_PREC_F32) {
-    if (ntiles == 1) launch_zw<BS_PREC_F32, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (ntiles == 2) launch_zw<BS_PREC_F32, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else launch_zw<BS_PREC_F32, 4>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-  } else {
-    return hipErrorNotSupported;
-  }
+  if (prec == BS_PREC_F64) zw_dispatch<double>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+  else if (prec == BS_PREC_BF16) zw_dispatch<uint16_t>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+  else zw_dispatch<float>(Z, ldz, rows, s16, Wop, mp, Pout, st);
   return hipGetLastError();
 }
 
@@ -367,11 +368,11 @@ hipError_t gram(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t coff
   const int64_t T = (sj + 63) / 64;
   dim3 g((unsigned)(T * (T + 1) / 2));
   if (prec == BS_PREC_F64)
-    gram_kernel<BS_PREC_F64><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, coff, sj, slot, S);
-  else if (prec == BS_PREC_F32)
-    gram_kernel<BS_PREC_F32><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, coff, sj, slot, S);
+    gram_kernel<double><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, coff, sj, slot, S);
+  else if (prec == BS_PREC_BF16)
+    gram_kernel<uint16_t><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, coff, sj, slot, S);
   else
-    return hipErrorNotSupported;
+    gram_kernel<float><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, coff, sj, slot, S);
   return hipGetLastError();
 }
 

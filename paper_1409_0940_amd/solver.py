@@ -47,6 +47,12 @@ class Solver:
         out = torch.empty((self.s, self.m), dtype=torch.float64, device=self.device)
         return abi.bsadmm_get_coef(self.h, out)
 
+    def objective(self, Wmodel=None):
+        """F(W-bar) (or F(Wmodel)) = (1/n) sum V + lambda ||W||^2 on the device."""
+        if Wmodel is not None:
+            Wmodel = Wmodel.contiguous().to(torch.float64)
+        return abi.bsadmm_objective(self.h, Wmodel)
+
     def predict(self, Xt):
         return abi.bsadmm_predict(self.h, Xt, self.m, stream=self.stream)
 

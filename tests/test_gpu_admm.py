@@ -2,9 +2,10 @@
 C ABI) against the FP64 oracle, on the same seeded inputs.
 
 Bars: relative objective error at the same iteration count <= 1e-6 for the
-FP64 path and <= 1e-4 for FP32; every exported state array is also compared
-element by element (max error over the array's max magnitude), with 1e-9 for
-FP64 and 1e-3 for FP32.
+FP64 path, <= 1e-4 for FP32 and refined BF16 (BF16X3), <= 1e-2 for plain BF16;
+every exported state array is also compared element by element (max error
+over the array's max magnitude), with 1e-9 for FP64, 1e-3 for FP32 and BF16X3
+and 5e-2 for BF16.
 """
 
 import numpy as np
@@ -71,6 +72,53 @@ def test_fp32_iterates_match_oracle(case):
     Wg = S.coef().cpu().numpy()
     assert rel_obj_err(p.loss, X, Y, W, b, Wg, st["Wbar"], p.lam) <= 1e-4
     S.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_bf16x3_iterates_match_oracle(case):
+    S, p, (X, Y, W, b) = _solver(case, "bf16x3")
+    S.iterate(20)
+    st, _ = o.admm(p, 20)
+    _compare(S, st, 1e-3)
+    Wg = S.coef().cpu().numpy()
+    assert rel_obj_err(p.loss, X, Y, W, b, Wg, st["Wbar"], p.lam) <= 1e-4
+    S.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_bf16_objective_within_1e2(case):
+    """Plain BF16 is bounded by its objective error (<= 1e-2) and its model error.
+
+    State arrays such as Delta-bar = O - sum_j O'_ij are differences of nearly
+    equal terms, so BF16's ~2^-9 relative error in Z is amplified there; they
+    are not compared element by element in this mode.
+    """
+    S, p, (X, Y, W, b) = _solver(case, "bf16")
+    S.iterate(20)
+    st, _ = o.admm(p, 20)
+    Wg = S.coef().cpu().numpy()
+    assert rel_err(Wg, st["Wbar"]) <= 0.1
+    assert rel_obj_err(p.loss, X, Y, W, b, Wg, st["Wbar"], p.lam) <= 1e-2
+    S.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("bf16x3", 1e-5)])
+def test_objective_entry_point(prec, tol):
+    """bsadmm_objective: F(W-bar) and F(W) for a passed model, against the oracle."""
+    import torch
+    for case in (CASES[2], CASES[4]):
+        S, p, (X, Y, W, b) = _solver(case, prec)
+        S.iterate(6)
+        st, _ = o.admm(p, 6)
+        Wg = S.coef().cpu().numpy()
+        f_gpu = S.objective()
+        f_ref = o.objective(p.loss, o.rff(X, W, b), Y, Wg, p.lam)
+        assert abs(f_gpu - f_ref) <= tol * abs(f_ref), (case[0], f_gpu, f_ref)
+        Wm = torch.from_numpy(st["Wbar"]).to("cuda")
+        f2 = S.objective(Wm)
+        f2_ref = o.objective(p.loss, o.rff(X, W, b), Y, st["Wbar"], p.lam)
+        assert abs(f2 - f2_ref) <= tol * abs(f2_ref)
+        S.close()
 
 
 def test_ridge_fp64_reaches_closed_form():

@@ -6,6 +6,9 @@ Bars (the random-feature map of section "Randomized Kernel Maps"):
   the summation bound of the FP32 phase plus the cosine's own error.
 * BF16: against the oracle evaluated on the BF16-rounded X and W, with the
   FP32 phase bound plus one BF16 rounding of the output (2^-8 relative).
+* BF16X3: x = h + l + e with h = bf16(x), l = bf16(x - h), |l| <= 2^-8 |x|,
+  |e| <= 2^-17 |x| (same for w); the dropped terms l_x l_w, e_x w, x e_w give a
+  phase error <= 3 * 2^-16 sum|x||w| on top of the FP32 accumulation bound.
 """
 
 import numpy as np
@@ -53,6 +56,24 @@ def test_rff_bf16(n, d, s):
     ref = o.rff(Xr, Wr, b)
     tol = s_scale(s) * (phase_bound_f32(Xr, Wr, b) + 4e-7 + 2.0 ** -8)
     assert (np.abs(Z - ref) <= tol).all()
+
+
+@pytest.mark.parametrize("n,d,s", SHAPES)
+def test_rff_bf16x3(n, d, s):
+    X, _, W, b = inputs("sine", n, d, s, 1, n + 4 * s, 2.0)
+    Z = _run("bf16x3", X, W, b)
+    ref = o.rff(X, W, b)
+    mag = np.abs(X.astype(np.float64)) @ np.abs(W.astype(np.float64))
+    tol = s_scale(s) * (3 * phase_bound_f32(X, W, b) + 3 * 2.0 ** -16 * mag + 4e-7)
+    assert (np.abs(Z - ref) <= tol).all()
+
+
+def test_rff_bf16x3_is_much_closer_than_bf16():
+    X, _, W, b = inputs("digits", 600, 784, 1024, 10, 5, 10.0)
+    ref = o.rff(X, W, b)
+    e3 = np.abs(_run("bf16x3", X, W, b) - ref).max()
+    e1 = np.abs(_run("bf16", X, W, b) - ref).max()
+    assert e3 < e1 / 30
 
 
 def test_rff_digits_and_speech_shapes():
