@@ -111,6 +111,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="fp64,bf16,bf16x3",
                     help="other precisions run at the same iteration count ('' = none)")
+    ap.add_argument("--serving", type=int, default=256,
+                    help="requests of the serving stream to run after the step timing (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -186,6 +188,12 @@ def main():
                          "mfma_passes": MFMA_PASSES[k],
                          "obj_rel_err_vs_fp64": rel(k)} for k, r in recs.items()},
     }
+    if args.serving:
+        from paper_1409_0940_amd.serving import serve_stream
+        log(f"serving stream: {args.serving} requests at 20/s")
+        summ, _ = serve_stream(args.serving)
+        out["serving"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+        log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, X, Y, Wr, b)
     print(json.dumps(out), flush=True)

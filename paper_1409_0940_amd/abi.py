@@ -95,6 +95,13 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _addr(t):
+    """Device address of a tensor, an int as given, anything else 0."""
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t if isinstance(t, int) else 0
+
+
 def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -148,7 +155,7 @@ def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="f
     p.precision = PRECISION[precision] if isinstance(precision, str) else precision
     p.z_mode = 0
     p.lam, p.rho, p.sigma = lam, rho, sigma
-    p.X, p.Y, p.W, p.b = (t.data_ptr() if hasattr(t, "data_ptr") else t for t in (X, Y, W, b))
+    p.X, p.Y, p.W, p.b = (_addr(t) for t in (X, Y, W, b))
     p.stream = _stream(stream).value if check else None
     p.hbm_budget_bytes = hbm_budget_bytes
     p.workspace_bytes = workspace_bytes

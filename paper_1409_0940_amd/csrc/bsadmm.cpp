@@ -168,16 +168,18 @@ struct bsadmm_handle {
   bool poisoned = false;
   std::vector<hipEvent_t> evpool;
 
+  // Stream-ordered allocations on the handle's stream: freeing a handle does
+  // not synchronise the device, so other solves keep running.
   hipError_t alloc(void** ptr, size_t bytes) {
     *ptr = nullptr;
     if (bytes == 0) return hipSuccess;
-    hipError_t e = hipMalloc(ptr, bytes);
+    hipError_t e = hipMallocAsync(ptr, bytes, st);
     if (e == hipSuccess) allocs.push_back(*ptr);
     return e;
   }
   ~bsadmm_handle() {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
-    for (void* a : allocs) (void)hipFree(a);
+    for (void* a : allocs) (void)hipFreeAsync(a, st);
   }
 };
 
@@ -322,7 +324,7 @@ int do_setup(bsadmm_handle* h) {
 #define ALLOC(ptr, bytes)                                                         \
   do {                                                                            \
     hipError_t e_ = h->alloc((void**)&(ptr), (bytes));                            \
-    if (e_ != hipSuccess) return fail(BSADMM_ENOMEM, "hipMalloc failed for " #ptr); \
+    if (e_ != hipSuccess) return fail(BSADMM_ENOMEM, "device allocation failed for " #ptr); \
   } while (0)
   ALLOC(h->Xp, L.b_xp);
   ALLOC(h->Wt, L.b_wt);
@@ -395,8 +397,8 @@ int do_setup(bsadmm_handle* h) {
   HCHK(bs::identity_pad(h->Q, L.R * L.C, L.S, sjb.data(), st));
   double* work = nullptr;
   {
-    hipError_t e = hipMalloc((void**)&work, L.b_fac_tmp);
-    if (e != hipSuccess) return fail(BSADMM_ENOMEM, "hipMalloc failed for factor workspace");
+    hipError_t e = hipMallocAsync((void**)&work, L.b_fac_tmp, st);
+    if (e != hipSuccess) return fail(BSADMM_ENOMEM, "device allocation failed for the factor workspace");
   }
   double* dinv = work + (size_t)L.fac_batch * slot;
   int rc = BSADMM_OK;
@@ -407,7 +409,7 @@ int do_setup(bsadmm_handle* h) {
   }
   hipError_t e1 = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, st);
   hipError_t e2 = hipStreamSynchronize(st);
-  (void)hipFree(work);
+  (void)hipFreeAsync(work, st);
   if (rc) return rc;
   if (e1 != hipSuccess) return hip_fail(e1, "flag copy");
   if (e2 != hipSuccess) return hip_fail(e2, "setup synchronize");
@@ -573,15 +575,15 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
   void *xop = nullptr, *wop = nullptr;
   double* pbuf = nullptr;
   auto cleanup = [&]() {
-    if (xop) (void)hipFree(xop);
-    if (wop) (void)hipFree(wop);
-    if (pbuf) (void)hipFree(pbuf);
+    if (xop) (void)hipFreeAsync(xop, st);
+    if (wop) (void)hipFreeAsync(wop, st);
+    if (pbuf) (void)hipFreeAsync(pbuf, st);
   };
-  if (hipMalloc(&xop, (size_t)chunk * L.Kp * L.op * L.planes) != hipSuccess ||
-      hipMalloc(&wop, (size_t)L.spad * L.mp * L.vb) != hipSuccess ||
-      hipMalloc((void**)&pbuf, (size_t)chunk * L.mp * 8) != hipSuccess) {
+  if (hipMallocAsync(&xop, (size_t)chunk * L.Kp * L.op * L.planes, st) != hipSuccess ||
+      hipMallocAsync(&wop, (size_t)L.spad * L.mp * L.vb, st) != hipSuccess ||
+      hipMallocAsync((void**)&pbuf, (size_t)chunk * L.mp * 8, st) != hipSuccess) {
     cleanup();
-    return fail(BSADMM_ENOMEM, "hipMalloc failed in predict");
+    return fail(BSADMM_ENOMEM, "device allocation failed in predict");
   }
   const size_t bb = L.prec == BSADMM_FP64 ? 8 : 4;
   hipError_t e = bs::to_op(L.prec, h->Wbar, L.spad * L.mp, wop, st);
@@ -614,15 +616,15 @@ int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F) {
   double *wpad = nullptr, *part = nullptr;
   void* wop = nullptr;
   auto cleanup = [&]() {
-    if (wpad) (void)hipFree(wpad);
-    if (part) (void)hipFree(part);
-    if (wop) (void)hipFree(wop);
+    if (wpad) (void)hipFreeAsync(wpad, st);
+    if (part) (void)hipFreeAsync(part, st);
+    if (wop) (void)hipFreeAsync(wop, st);
   };
-  if (hipMalloc((void**)&wpad, (size_t)L.spad * L.mp * 8) != hipSuccess ||
-      hipMalloc((void**)&part, 2 * NB * 8) != hipSuccess ||
-      hipMalloc(&wop, (size_t)L.spad * L.mp * L.vb) != hipSuccess) {
+  if (hipMallocAsync((void**)&wpad, (size_t)L.spad * L.mp * 8, st) != hipSuccess ||
+      hipMallocAsync((void**)&part, 2 * NB * 8, st) != hipSuccess ||
+      hipMallocAsync(&wop, (size_t)L.spad * L.mp * L.vb, st) != hipSuccess) {
     cleanup();
-    return fail(BSADMM_ENOMEM, "hipMalloc failed in objective");
+    return fail(BSADMM_ENOMEM, "device allocation failed in objective");
   }
   hipError_t e = hipSuccess;
   if (Wmodel) {
@@ -689,14 +691,15 @@ int rff_map(const float* X, int64_t n, int64_t d, const float* W, const float* b
   const size_t op = bs::op_bytes(precision) * bs::op_planes(precision);
   void *xop = nullptr, *wt = nullptr, *bias = nullptr;
   auto cleanup = [&]() {
-    if (xop) (void)hipFree(xop);
-    if (wt) (void)hipFree(wt);
-    if (bias) (void)hipFree(bias);
+    if (xop) (void)hipFreeAsync(xop, st);
+    if (wt) (void)hipFreeAsync(wt, st);
+    if (bias) (void)hipFreeAsync(bias, st);
   };
-  if (hipMalloc(&xop, (size_t)n * Kp * op) != hipSuccess ||
-      hipMalloc(&wt, (size_t)s * Kp * op) != hipSuccess || hipMalloc(&bias, (size_t)s * 8) != hipSuccess) {
+  if (hipMallocAsync(&xop, (size_t)n * Kp * op, st) != hipSuccess ||
+      hipMallocAsync(&wt, (size_t)s * Kp * op, st) != hipSuccess ||
+      hipMallocAsync(&bias, (size_t)s * 8, st) != hipSuccess) {
     cleanup();
-    return fail(BSADMM_ENOMEM, "hipMalloc failed in rff_map");
+    return fail(BSADMM_ENOMEM, "device allocation failed in rff_map");
   }
   hipError_t e = bs::prep_rows(precision, X, n, d, Kp, xop, n * Kp, nullptr, st);
   if (e == hipSuccess) e = bs::prep_w(precision, W, b, d, s, Kp, wt, s * Kp, bias, nullptr, st);

@@ -1,0 +1,282 @@
+"""Continuous-batching serving of ridge / hinge solves on one GPU.
+
+Requests arrive over time (Poisson stream).  A request is admitted as soon as
+an execution slot is free and its device footprint (bsadmm_footprint plus its
+input buffers) fits in the memory budget; admitted solves run concurrently on
+their own HIP streams, each as a sequence of chunks of ADMM iterations, and
+new arrivals are admitted while others are running (no batch barrier).  A solve
+stops when the relative change of its objective between two checks falls
+below `rtol`, or at `max_iters`; its consensus model is then copied out, its
+handle destroyed (stream-ordered frees) and its memory returned to the budget.
+
+Every solve owns its handle, buffers and stream, and every kernel is
+deterministic, so a request's result does not depend on what else is running:
+the same model, bit for bit, alone or in the mix.
+
+The scheduler is plain host logic over an executor interface, so it can be
+driven by a GPU executor (``GpuExecutor``) or by a test double.
+"""
+
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+
+@dataclass
+class Job:
+    rid: int
+    arrival_s: float
+    spec: object                 # workloads.Request (sizes, loss, lambda, sigma, ...)
+    inputs: tuple = None         # host (X, Y, W, b) float32
+    footprint: int = 0
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival_s: float
+    admitted_s: float
+    finished_s: float
+    iters: int
+    objective: float
+    coef: object = None          # host numpy array (s x m)
+    status: str = "ok"
+
+    @property
+    def latency_s(self):
+        return self.finished_s - self.arrival_s
+
+
+@dataclass
+class Slot:
+    job: Job
+    handle: object
+    admitted_s: float
+    iters: int = 0
+    prev_obj: float = None
+    checks: list = field(default_factory=list)
+
+
+class Scheduler:
+    """FIFO admission by footprint with a fixed number of execution slots."""
+
+    def __init__(self, executor, budget_bytes, max_active=8, check_every=10, max_iters=200,
+                 rtol=2e-6, clock=time.perf_counter, idle_sleep=2e-4):
+        self.ex = executor
+        self.budget = budget_bytes
+        self.max_active = max_active
+        self.check_every = check_every
+        self.max_iters = max_iters
+        self.rtol = rtol
+        self.clock = clock
+        self.idle_sleep = idle_sleep
+        self.used = 0
+        self.peak_used = 0
+        self.peak_active = 0
+        self.trace = []          # (t, event, rid, used)
+
+    def _converged(self, slot, obj):
+        prev = slot.prev_obj
+        return prev is not None and abs(obj - prev) <= self.rtol * max(abs(obj), 1e-300)
+
+    def run(self, jobs, time_scale=1.0):
+        """Serve `jobs` (arrival times scaled by `time_scale`); returns results by rid."""
+        pending = deque(sorted(jobs, key=lambda j: (j.arrival_s, j.rid)))
+        waiting = deque()
+        active = []
+        results = {}
+        t0 = self.clock()
+        now = lambda: self.clock() - t0
+        while pending or waiting or active:
+            progressed = False
+            t = now()
+            while pending and pending[0].arrival_s * time_scale <= t:
+                j = pending.popleft()
+                j.footprint = self.ex.footprint(j)
+                waiting.append(j)
+                self.trace.append((t, "arrive", j.rid, self.used))
+            while waiting and len(active) < self.max_active:
+                j = waiting[0]
+                if j.footprint > self.budget:
+                    waiting.popleft()
+                    results[j.rid] = Result(j.rid, j.arrival_s * time_scale, now(), now(), 0,
+                                            math.nan, None, "rejected: footprint above budget")
+                    self.trace.append((now(), "reject", j.rid, self.used))
+                    progressed = True
+                    continue
+                if self.used + j.footprint > self.budget:
+                    break                      # wait for memory to free up (FIFO)
+                waiting.popleft()
+                self.used += j.footprint
+                self.peak_used = max(self.peak_used, self.used)
+                ta = now()
+                h = self.ex.start(j)
+                self.ex.enqueue(h, self.check_every)
+                active.append(Slot(j, h, ta))
+                self.peak_active = max(self.peak_active, len(active))
+                self.trace.append((ta, "admit", j.rid, self.used))
+                progressed = True
+            for slot in list(active):
+                if not self.ex.ready(slot.handle):
+                    continue
+                progressed = True
+                slot.iters += self.check_every
+                obj = self.ex.objective(slot.handle)
+                slot.checks.append(obj)
+                if self._converged(slot, obj) or slot.iters >= self.max_iters:
+                    coef = self.ex.finish(slot.handle)
+                    active.remove(slot)
+                    self.used -= slot.job.footprint
+                    tf = now()
+                    results[slot.job.rid] = Result(slot.job.rid, slot.job.arrival_s * time_scale,
+                                                   slot.admitted_s, tf, slot.iters, obj, coef)
+                    self.trace.append((tf, "finish", slot.job.rid, self.used))
+                else:
+                    slot.prev_obj = obj
+                    self.ex.enqueue(slot.handle, self.check_every)
+            if not progressed:
+                if not active and not waiting and pending:
+                    wait = pending[0].arrival_s * time_scale - now()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.01))
+                else:
+                    time.sleep(self.idle_sleep)
+        return results
+
+
+def latency_summary(results, wall_s):
+    """p50 / p99 latency, solves/s and iterations/s over the served requests."""
+    ok = [r for r in results.values() if r.status == "ok"]
+    lat = sorted(r.latency_s for r in ok)
+
+    def pct(p):
+        if not lat:
+            return math.nan
+        k = max(0, min(len(lat) - 1, int(math.ceil(p / 100.0 * len(lat))) - 1))
+        return lat[k]
+
+    iters = sum(r.iters for r in ok)
+    return {"requests": len(results), "served": len(ok),
+            "rejected": len(results) - len(ok),
+            "p50_ms": 1e3 * pct(50), "p99_ms": 1e3 * pct(99), "max_ms": 1e3 * (lat[-1] if lat else math.nan),
+            "wall_s": wall_s, "solves_per_s": len(ok) / wall_s if wall_s > 0 else math.nan,
+            "iters_per_s": iters / wall_s if wall_s > 0 else math.nan, "total_iters": iters}
+
+
+# ---------------------------------------------------------------------------
+# GPU executor: one libbsadmm handle and one HIP stream per admitted solve.
+# ---------------------------------------------------------------------------
+
+class GpuExecutor:
+    def __init__(self, precision="bf16x3", max_streams=8, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.precision = precision
+        self.device = torch.device(device)
+        self.free_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_streams)]
+
+    def footprint(self, job):
+        from . import abi
+        X, Y, W, b = job.inputs
+        r = job.spec
+        C = max(1, -(-r.s // 4096))
+        p = abi.make_problem(X, Y, W, b, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision,
+                             check=False)
+        p.X = p.Y = p.W = p.b = 256       # sizes only: footprint never touches memory
+        inputs = sum(a.nbytes for a in job.inputs)
+        return abi.bsadmm_footprint(p) + inputs
+
+    def start(self, job):
+        from .solver import Solver
+        torch = self.torch
+        stream = self.free_streams.pop()
+        X, Y, W, b = job.inputs
+        r = job.spec
+        C = max(1, -(-r.s // 4096))
+        with torch.cuda.stream(stream):
+            dev = [torch.from_numpy(a).to(self.device, non_blocking=False) for a in (X, Y, W, b)]
+        S = Solver(*dev, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision, stream=stream)
+        return {"S": S, "stream": stream, "dev": dev, "event": None}
+
+    def enqueue(self, h, iters):
+        torch = self.torch
+        h["S"].iterate_async(iters)
+        ev = torch.cuda.Event()
+        ev.record(h["stream"])
+        h["event"] = ev
+
+    def ready(self, h):
+        return h["event"] is None or h["event"].query()
+
+    def objective(self, h):
+        return h["S"].objective()
+
+    def finish(self, h):
+        coef = h["S"].coef().cpu().numpy()
+        h["S"].close()
+        h["stream"].synchronize()
+        self.free_streams.append(h["stream"])
+        h["dev"] = None
+        return coef
+
+
+def _loss(job):
+    r = job.spec
+    if r.loss == "squared":
+        return "squared"
+    return "hinge" if r.m == 1 else "mc_hinge"
+
+
+def make_jobs(requests, workers=8):
+    """Draw every request's inputs on the host (in parallel) before serving."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    # spawned workers: they never touch the GPU, whatever the parent has done
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as pool:
+        inputs = list(pool.map(_request_inputs, requests, chunksize=4))
+    return [Job(r.rid, r.arrival_s, r, inp) for r, inp in zip(requests, inputs)]
+
+
+def _request_inputs(r):
+    import workloads as wl
+    return wl.make_inputs(wl.request_workload(r))
+
+
+def serve_stream(count=256, rate_per_s=20.0, precision="bf16x3", budget_gb=160.0, max_active=8,
+                 max_iters=300, check_every=10, rtol=2e-6, workers=8, n_range=(2000, 200000)):
+    """Run the request stream of the serving workload end to end; returns (summary, results)."""
+    import workloads as wl
+    reqs = wl.serving_stream(count, rate_per_s, n_range=n_range)
+    t = time.perf_counter()
+    jobs = make_jobs(reqs, workers)
+    gen_s = time.perf_counter() - t
+    ex = GpuExecutor(precision, max_active)
+    sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active, check_every, max_iters, rtol)
+    t = time.perf_counter()
+    res = sch.run(jobs)
+    wall = time.perf_counter() - t
+    summ = latency_summary(res, wall)
+    summ.update({"precision": precision, "max_active": max_active, "budget_gb": budget_gb,
+                 "peak_active": sch.peak_active, "peak_used_gb": sch.peak_used / (1 << 30),
+                 "input_generation_s": gen_s, "rate_per_s": rate_per_s,
+                 "check_every": check_every, "max_iters": max_iters, "rtol": rtol})
+    return summ, res
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--max-active", type=int, default=8)
+    args = ap.parse_args()
+    summ, _ = serve_stream(args.requests, args.rate, args.precision, max_active=args.max_active)
+    print(json.dumps(summ))

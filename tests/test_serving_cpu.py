@@ -1,0 +1,128 @@
+"""Host-side tests of the serving scheduler with a simulated executor.
+
+The executor double models each solve as a fixed device time per chunk of
+iterations and an objective that converges geometrically; a virtual clock
+advances by the simulated work, so the tests are exact and fast.
+"""
+
+import math
+
+import pytest
+
+from paper_1409_0940_amd.serving import Job, Scheduler, latency_summary
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeExecutor:
+    """Each solve: footprint from its spec; a chunk takes chunk_s of virtual
+    time; objective after k iterations is f* (1 + 0.5^(k / 10))."""
+
+    def __init__(self, clock, chunk_s=0.01):
+        self.clock = clock
+        self.chunk_s = chunk_s
+        self.log = []
+        self.live = set()
+
+    def footprint(self, job):
+        return job.spec["bytes"]
+
+    def start(self, job):
+        self.live.add(job.rid)
+        self.log.append(("start", job.rid, self.clock.t))
+        return {"job": job, "iters": 0, "done_at": None}
+
+    def enqueue(self, h, iters):
+        h["iters"] += iters
+        h["done_at"] = self.clock.t + self.chunk_s
+
+    def ready(self, h):
+        if h["done_at"] <= self.clock.t:
+            return True
+        self.clock.t += 1e-4          # time passes while polling
+        return False
+
+    def objective(self, h):
+        return 1.0 + 0.5 ** (h["iters"] / 10.0)
+
+    def finish(self, h):
+        self.live.discard(h["job"].rid)
+        return h["iters"]
+
+
+def _jobs(sizes, gap=0.0):
+    return [Job(i, i * gap, {"bytes": b}) for i, b in enumerate(sizes)]
+
+
+def test_all_served_and_budget_respected():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    sch = Scheduler(ex, budget_bytes=100, max_active=4, check_every=10, max_iters=60, rtol=1e-3,
+                    clock=clk, idle_sleep=0)
+    res = sch.run(_jobs([30, 30, 30, 30, 50, 10, 90], gap=0.001))
+    assert sorted(res) == list(range(7))
+    assert all(r.status == "ok" for r in res.values())
+    assert sch.peak_used <= 100
+    assert sch.peak_active <= 4
+    assert not ex.live
+    # every trace point respects the budget
+    assert all(u <= 100 for (_, _, _, u) in sch.trace)
+
+
+def test_fifo_admission_order_and_continuous_batching():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    sch = Scheduler(ex, budget_bytes=60, max_active=8, check_every=10, max_iters=40, rtol=0.0,
+                    clock=clk, idle_sleep=0)
+    sch.run(_jobs([40, 40, 10, 10], gap=0.0))
+    starts = [rid for (ev, rid, _) in ex.log if ev == "start"]
+    assert starts == [0, 1, 2, 3]          # FIFO: job 2 waits behind job 1
+    t_start = {rid: t for (ev, rid, t) in ex.log if ev == "start"}
+    # job 1 is admitted while job 0 is still running? no: 40 + 40 > 60, it waits
+    # for job 0's memory; jobs 2 and 3 then join job 1 without waiting for it
+    assert t_start[1] > t_start[0]
+    finish = {rid: t for (t, ev, rid, _) in sch.trace if ev == "finish"}
+    assert t_start[2] < finish[1] and t_start[3] < finish[1]
+
+
+def test_oversize_request_rejected_others_served():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    sch = Scheduler(ex, budget_bytes=50, max_active=2, check_every=10, max_iters=30, rtol=0.0,
+                    clock=clk, idle_sleep=0)
+    res = sch.run(_jobs([20, 80, 20]))
+    assert res[1].status.startswith("rejected")
+    assert res[0].status == "ok" and res[2].status == "ok"
+
+
+def test_stopping_rule_and_iteration_cap():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    sch = Scheduler(ex, budget_bytes=10, max_active=1, check_every=10, max_iters=1000, rtol=1e-3,
+                    clock=clk, idle_sleep=0)
+    res = sch.run(_jobs([5]))
+    # objective change between checks k-10 and k: 0.5^(k/10) (1 - 0.5) ... <= 1e-3 (1 + ...)
+    k = res[0].iters
+    change = 0.5 ** ((k - 10) / 10.0) - 0.5 ** (k / 10.0)
+    assert change <= 1e-3 * (1 + 0.5 ** (k / 10.0))
+    prev_change = 0.5 ** ((k - 20) / 10.0) - 0.5 ** ((k - 10) / 10.0)
+    assert prev_change > 1e-3 * (1 + 0.5 ** ((k - 10) / 10.0))
+    sch2 = Scheduler(FakeExecutor(clk), 10, 1, 10, 30, 0.0, clock=clk, idle_sleep=0)
+    assert sch2.run(_jobs([5]))[0].iters == 30
+
+
+def test_latency_summary_percentiles():
+    from paper_1409_0940_amd.serving import Result
+    res = {i: Result(i, 0.0, 0.0, (i + 1) / 100.0, 10, 1.0) for i in range(100)}
+    s = latency_summary(res, wall_s=2.0)
+    assert s["p50_ms"] == pytest.approx(500.0)
+    assert s["p99_ms"] == pytest.approx(990.0)
+    assert s["solves_per_s"] == pytest.approx(50.0)
+    assert s["iters_per_s"] == pytest.approx(500.0)
+    assert math.isclose(s["max_ms"], 1000.0)
