@@ -37,7 +37,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def gpu_run(w, precision, steps, warmup, dev_inputs):
+def gpu_run(w, precision, steps, warmup, dev_inputs, z_mode="auto"):
     """Setup, warm-up, timed iterations; returns (solver, record)."""
     import torch
     from paper_1409_0940_amd import Solver
@@ -45,7 +45,8 @@ def gpu_run(w, precision, steps, warmup, dev_inputs):
     Xd, Yd, Wd, bd = dev_inputs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    S = Solver(Xd, Yd, Wd, bd, w.R, w.C, w.lam, w.rho, w.sigma, w.loss, precision)
+    S = Solver(Xd, Yd, Wd, bd, w.R, w.C, w.lam, w.rho, w.sigma, w.loss, precision,
+               z_mode=z_mode)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     if warmup:
@@ -56,13 +57,13 @@ def gpu_run(w, precision, steps, warmup, dev_inputs):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     flops = regen_flops_per_launch(w)
-    launch_ms = st["phase_ms"]["regen"] / max(1, st["launches"])
-    achieved = flops / (launch_ms * 1e-3) / 1e12
+    launch_ms = st["phase_ms"]["regen"] / max(1, st["launches"]) if st["launches"] else 0.0
+    achieved = flops / (launch_ms * 1e-3) / 1e12 if launch_ms else 0.0
     rec = {"value": steps / wall, "ms_per_step": 1e3 * wall / steps, "setup_s": setup_s,
            "launch_ms": launch_ms, "achieved": achieved, "launches": st["launches"],
            "phase_ms_per_step": {k: v / steps for k, v in st["phase_ms"].items()},
            "coef": S.coef()}
-    log(f"{precision}: setup {setup_s:.2f} s, {steps} steps {wall:.3f} s "
+    log(f"{precision}/{z_mode}: setup {setup_s:.2f} s, {steps} steps {wall:.3f} s "
         f"({rec['value']:.2f} it/s), regen {launch_ms:.3f} ms/launch")
     return S, rec
 
@@ -109,8 +110,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=list(PEAK))
     ap.add_argument("--workload", default="digits_200k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp64,bf16,bf16x3",
-                    help="other precisions run at the same iteration count ('' = none)")
+    ap.add_argument("--variants", default="fp64,bf16,bf16x3,fp32:keep,bf16:keep",
+                    help="other precision[:z_mode] runs at the same iteration count ('' = none);"
+                         " z_mode keep = Z generated once and kept in HBM")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run after the step timing (0 = skip)")
     args = ap.parse_args()
@@ -134,7 +136,9 @@ def main():
     recs = {}
     ref = None
     for v in variants:
-        Sv, rv = gpu_run(w, v, args.steps, args.warmup, dev_inputs)
+        prec, _, zm = v.partition(":")
+        Sv, rv = gpu_run(w, prec, args.steps, args.warmup, dev_inputs, zm or "auto")
+        rv["prec"] = prec
         if v == "fp64":
             ref = Sv
         else:
@@ -183,16 +187,18 @@ def main():
         "variants": {k: {"value": round(r["value"], 4), "unit": "iters/s",
                          "ms_per_step": round(r["ms_per_step"], 3),
                          "setup_s": round(r["setup_s"], 3),
-                         "regen_frac": round(r["achieved"] / PEAK[k], 4),
+                         "regen_frac": round(r["achieved"] / PEAK[r["prec"]], 4),
                          "regen_tflops": round(r["achieved"], 2),
-                         "mfma_passes": MFMA_PASSES[k],
+                         "mfma_passes": MFMA_PASSES[r["prec"]],
+                         "phase_ms_per_step": {p: round(t, 4)
+                                               for p, t in r["phase_ms_per_step"].items()},
                          "obj_rel_err_vs_fp64": rel(k)} for k, r in recs.items()},
     }
     if args.serving:
         from paper_1409_0940_amd.serving import serve_stream
         log(f"serving stream: {args.serving} requests at 20/s")
         summ, _ = serve_stream(args.serving)
-        out["serving"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+        out["serving"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in summ.items()}
         log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, X, Y, Wr, b)

@@ -89,8 +89,13 @@ enum { BSADMM_L2 = 0 };
  *        blocks once into a library workspace and both products of the
  *        iteration read them (the paper keeps Z_ij for the products of one
  *        block visit, steps 15-21); nothing of Z survives the iteration.
- * AUTO : STORE with the largest row-block groups that fit the budget.      */
-enum { BSADMM_Z_AUTO = 0, BSADMM_Z_STORE = 1 };
+ * AUTO : STORE with the largest row-block groups that fit the workspace cap.
+ * KEEP : Z is generated once, at setup, for all rows and kept in HBM for
+ *        every iteration (no regeneration).  Needs n x spad elements of
+ *        workspace (spad = sum_j s_j rounded up to 64 per block); setup fails
+ *        with ENOMEM if workspace_bytes is set and smaller.  Results equal
+ *        STORE bit for bit.                                                 */
+enum { BSADMM_Z_AUTO = 0, BSADMM_Z_STORE = 1, BSADMM_Z_KEEP = 2 };
 
 /* -------------------------------------------------------------- problem */
 /* Problem of eq. problem_linear with Z = sqrt(2/s) cos(X W + b):
@@ -109,7 +114,7 @@ typedef struct bsadmm_problem {
   int32_t loss;     /* BSADMM_SQUARED | BSADMM_HINGE | BSADMM_MC_HINGE      */
   int32_t reg;      /* BSADMM_L2                                            */
   int32_t precision;/* BSADMM_FP64 | FP32 | BF16 | BF16X3                    */
-  int32_t z_mode;   /* BSADMM_Z_AUTO | BSADMM_Z_STORE                       */
+  int32_t z_mode;   /* BSADMM_Z_AUTO | BSADMM_Z_STORE | BSADMM_Z_KEEP       */
   double lambda;    /* >= 0                                                 */
   double rho;       /* > 0                                                  */
   double sigma;     /* kernel bandwidth the caller drew W with; > 0; used
@@ -252,6 +257,22 @@ BSADMM_API int bsadmm_import_state(bsadmm_handle* h, int32_t which, const double
  * Errors: EINVAL (null handle or F), ESTATE, ENOMEM, EDEVICE.
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_monitor -- enqueue on the handle's stream, without synchronising,
+ * fixed-order reductions of the state left by the last iteration into the
+ * caller-owned device array out[0..3] (doubles):
+ *   out[0] = sum_r V(y_r, o'_r), o' = sum_j Z_ij W'_ij (outputs of the local
+ *            models of step 19),
+ *   out[1] = (1/R) sum_i ||W'_i||_F^2,
+ *   out[2] = sum_i ||W'_i - W-bar||_F^2  (consensus residual, steps 28-29),
+ *   out[3] = ||Delta-bar||_F^2           (exchange residual, step 25).
+ * With R = 1, out[0] / n + lambda out[1] is the objective F of the local
+ * model W' (eq. problem_linear) at no extra feature regeneration; a serving
+ * loop reads it asynchronously as its stopping statistic.
+ * Errors: EINVAL (null argument), ESTATE, EDEVICE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_monitor(bsadmm_handle* h, double* out);
 
 /* bsadmm_destroy -- free everything the handle owns.  NULL is allowed. */
 BSADMM_API int bsadmm_destroy(bsadmm_handle* h);

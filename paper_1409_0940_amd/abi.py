@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(PKG, "libbsadmm.so")
 
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 LOSS = {"squared": 0, "hinge": 1, "mc_hinge": 2}
+Z_MODE = {"auto": 0, "store": 1, "keep": 2}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTPD", 5: "ENONFINITE",
           6: "ESTATE", 7: "ENOTIMPL"}
 STATE = {"O": 0, "Obar": 1, "nu": 2, "Dbar": 3, "Wc": 4, "Wbar": 5, "mu": 6, "Wp": 7,
@@ -24,7 +25,8 @@ PHASES = ["regen", "ztr", "solve", "zw", "row", "col"]
 
 EXPORTED = ["rff_map", "bsadmm_validate", "bsadmm_footprint", "bsadmm_setup", "bsadmm_iterate",
             "bsadmm_predict", "bsadmm_get_coef", "bsadmm_state_size", "bsadmm_export_state",
-            "bsadmm_import_state", "bsadmm_objective", "bsadmm_destroy", "bsadmm_last_error"]
+            "bsadmm_import_state", "bsadmm_objective", "bsadmm_monitor", "bsadmm_destroy",
+            "bsadmm_last_error"]
 
 
 class BsadmmProblem(ctypes.Structure):
@@ -76,6 +78,7 @@ def lib():
         L.bsadmm_export_state.argtypes = [vp, i32, vp]
         L.bsadmm_import_state.argtypes = [vp, i32, vp]
         L.bsadmm_objective.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.bsadmm_monitor.argtypes = [vp, vp]
         L.bsadmm_destroy.argtypes = [vp]
         L.bsadmm_last_error.argtypes = []
         L.bsadmm_last_error.restype = ctypes.c_char_p
@@ -138,7 +141,7 @@ def rff_map(X, W, b, precision="fp32", out=None, stream=None):
 
 
 def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
-                 stream=None, hbm_budget_bytes=0, workspace_bytes=0, check=True):
+                 stream=None, hbm_budget_bytes=0, workspace_bytes=0, check=True, z_mode="auto"):
     n, d = X.shape
     m = Y.shape[1]
     s = W.shape[1]
@@ -153,7 +156,7 @@ def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="f
     p.loss = LOSS[loss] if isinstance(loss, str) else loss
     p.reg = 0
     p.precision = PRECISION[precision] if isinstance(precision, str) else precision
-    p.z_mode = 0
+    p.z_mode = Z_MODE[z_mode] if isinstance(z_mode, str) else z_mode
     p.lam, p.rho, p.sigma = lam, rho, sigma
     p.X, p.Y, p.W, p.b = (_addr(t) for t in (X, Y, W, b))
     p.stream = _stream(stream).value if check else None
@@ -226,6 +229,12 @@ def bsadmm_objective(h, Wmodel=None):
     F = ctypes.c_double(0.0)
     _check("bsadmm_objective", lib().bsadmm_objective(h, _ptr(Wmodel), ctypes.byref(F)))
     return F.value
+
+
+def bsadmm_monitor(h, out):
+    """Enqueue the convergence reductions into out (4 float64 on the device)."""
+    _check("bsadmm_monitor", lib().bsadmm_monitor(h, _ptr(out)))
+    return out
 
 
 def bsadmm_destroy(h):

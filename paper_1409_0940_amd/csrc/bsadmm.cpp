@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -40,6 +41,8 @@ int hip_fail(hipError_t e, const char* what) {
 
 inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+constexpr int kMonBlocks = 256;  // partial sums per monitored quantity
+
 // Sizes and layout derived from a problem; computed on the host only.
 struct Plan {
   int prec = 0;
@@ -50,6 +53,7 @@ struct Plan {
   int64_t ws_rows = 0;
   int64_t split_rows = 2048, nsplit_max = 1;
   int fac_batch = 1;
+  bool keep = false;             // Z generated once and kept (BSADMM_Z_KEEP)
   size_t op = 4, zb = 4, vb = 4;  // operand, stored Z, product-operand bytes
   int planes = 1;
   // byte counts
@@ -74,7 +78,7 @@ int validate(const bsadmm_problem* p) {
   if (p->reg != BSADMM_L2) return fail(BSADMM_EINVAL, "unknown regulariser");
   if (p->precision < BSADMM_FP64 || p->precision > BSADMM_BF16X3)
     return fail(BSADMM_EINVAL, "unknown precision");
-  if (p->z_mode != BSADMM_Z_AUTO && p->z_mode != BSADMM_Z_STORE)
+  if (p->z_mode != BSADMM_Z_AUTO && p->z_mode != BSADMM_Z_STORE && p->z_mode != BSADMM_Z_KEEP)
     return fail(BSADMM_EINVAL, "unknown z_mode");
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(BSADMM_EINVAL, "need lambda >= 0");
   if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return fail(BSADMM_EINVAL, "need rho > 0");
@@ -113,9 +117,13 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   }
   L.spad = off;
   L.S = rup(smax, 64);
-  // Row-block groups for the Z workspace.
-  size_t cap = p->workspace_bytes ? p->workspace_bytes : (size_t)32 << 30;
+  // Row-block groups for the Z workspace (one group of all rows when Z is kept).
+  L.keep = p->z_mode == BSADMM_Z_KEEP;
   const size_t row_bytes = (size_t)L.spad * L.zb;
+  if (L.keep && p->workspace_bytes && p->workspace_bytes < (size_t)L.n * row_bytes)
+    return fail(BSADMM_ENOMEM, "BSADMM_Z_KEEP needs " + std::to_string((size_t)L.n * row_bytes) +
+                                   " B of workspace, workspace_bytes is smaller");
+  size_t cap = L.keep ? SIZE_MAX : (p->workspace_bytes ? p->workspace_bytes : (size_t)32 << 30);
   L.groups.clear();
   int i = 0;
   L.ws_rows = 0;
@@ -144,7 +152,7 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.b_colR = (size_t)L.R * L.spad * L.mp * 8;
   L.b_wop = (size_t)L.R * L.spad * L.mp * L.vb;
   L.b_part = (size_t)L.R * L.nsplit_max * L.spad * L.mp * L.vb;
-  L.b_small = 256 + 2 * (size_t)L.C * 8;
+  L.b_small = 256 + 2 * (size_t)L.C * 8 + 4 * kMonBlocks * 8;
   L.b_fac_tmp = (size_t)L.fac_batch * (slot + (size_t)L.S * 64 * 8);
   return BSADMM_OK;
 }
@@ -163,6 +171,7 @@ struct bsadmm_handle {
          *P = nullptr, *Wbar = nullptr, *mu = nullptr, *Wc = nullptr, *Wp = nullptr,
          *mup = nullptr, *U = nullptr, *rhs = nullptr;
   int64_t *d_coff = nullptr, *d_sj = nullptr;
+  double* mon_part = nullptr;
   int* dflag = nullptr;
   int64_t iters = 0;
   bool poisoned = false;
@@ -257,10 +266,12 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
     for (const auto& g : L.groups) {
       const int i0 = g.first, i1 = g.second;
       const int64_t r0 = L.rstart[i0];
-      tm.begin();
-      HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp));
-      launches += L.C;
-      tm.end(BSADMM_PH_REGEN);
+      if (!L.keep) {  // a kept Z was generated at setup
+        tm.begin();
+        HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp));
+        launches += L.C;
+        tm.end(BSADMM_PH_REGEN);
+      }
       tm.begin();
       for (int i = i0; i < i1; ++i) {
         const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
@@ -350,6 +361,7 @@ int do_setup(bsadmm_handle* h) {
   h->dflag = (int*)tmp;
   h->d_coff = (int64_t*)((char*)tmp + 256);
   h->d_sj = h->d_coff + L.C;
+  h->mon_part = (double*)(h->d_sj + L.C);
   hipStream_t st = h->st;
   HCHK(hipMemcpyAsync(h->d_coff, L.coff.data(), L.C * 8, hipMemcpyHostToDevice, st));
   HCHK(hipMemcpyAsync(h->d_sj, L.sj.data(), L.C * 8, hipMemcpyHostToDevice, st));
@@ -571,22 +583,26 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
     HCHK(hipStreamWaitEvent(st, e, 0));
     (void)hipEventDestroy(e);
   }
-  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nt, L.ws_rows));
-  void *xop = nullptr, *wop = nullptr;
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nt, std::min<int64_t>(L.ws_rows, 65536)));
+  void *xop = nullptr, *wop = nullptr, *zt = nullptr;
   double* pbuf = nullptr;
   auto cleanup = [&]() {
     if (xop) (void)hipFreeAsync(xop, st);
     if (wop) (void)hipFreeAsync(wop, st);
+    if (zt) (void)hipFreeAsync(zt, st);
     if (pbuf) (void)hipFreeAsync(pbuf, st);
   };
+  // own feature buffer: the handle's workspace may hold a kept Z
   if (hipMallocAsync(&xop, (size_t)chunk * L.Kp * L.op * L.planes, st) != hipSuccess ||
       hipMallocAsync(&wop, (size_t)L.spad * L.mp * L.vb, st) != hipSuccess ||
+      hipMallocAsync(&zt, (size_t)chunk * L.spad * L.zb, st) != hipSuccess ||
       hipMallocAsync((void**)&pbuf, (size_t)chunk * L.mp * 8, st) != hipSuccess) {
     cleanup();
     return fail(BSADMM_ENOMEM, "device allocation failed in predict");
   }
   const size_t bb = L.prec == BSADMM_FP64 ? 8 : 4;
-  hipError_t e = bs::to_op(L.prec, h->Wbar, L.spad * L.mp, wop, st);
+  hipError_t e = hipMemsetAsync(zt, 0, (size_t)chunk * L.spad * L.zb, st);  // pad columns
+  if (e == hipSuccess) e = bs::to_op(L.prec, h->Wbar, L.spad * L.mp, wop, st);
   for (int64_t r0 = 0; r0 < nt && e == hipSuccess; r0 += chunk) {
     const int64_t rows = std::min(chunk, nt - r0);
     e = bs::prep_rows(L.prec, Xt + r0 * L.d, rows, L.d, L.Kp, xop, chunk * L.Kp, nullptr, st);
@@ -594,8 +610,8 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
       e = bs::regen(L.prec, xop, chunk * L.Kp, rows,
                     (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.s * L.Kp, L.sj[j],
                     (const char*)h->bias + (size_t)L.cstart[j] * bb, L.Kp, h->scale,
-                    (char*)h->Z + (size_t)L.coff[j] * L.zb, L.spad, st);
-    if (e == hipSuccess) e = bs::zw(L.prec, h->Z, L.spad, rows, L.spad, wop, L.mp, pbuf, st);
+                    (char*)zt + (size_t)L.coff[j] * L.zb, L.spad, st);
+    if (e == hipSuccess) e = bs::zw(L.prec, zt, L.spad, rows, L.spad, wop, L.mp, pbuf, st);
     if (e == hipSuccess) e = bs::scores_out(pbuf, rows, L.m, L.mp, out + r0 * L.m, st);
   }
   hipError_t e2 = hipStreamSynchronize(st);
@@ -603,6 +619,21 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
   if (e != hipSuccess) return hip_fail(e, "predict");
   if (e2 != hipSuccess) return hip_fail(e2, "predict synchronize");
   if (st != h->st) HCHK(hipStreamSynchronize(h->st));
+  return BSADMM_OK;
+}
+
+int bsadmm_monitor(bsadmm_handle* h, double* out) {
+  g_err.clear();
+  if (!h || !out) return fail(BSADMM_EINVAL, "NULL argument");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  const Plan& L = h->L;
+  hipError_t e = bs::monitor(h->p.loss == BSADMM_SQUARED ? 0 : 1, h->P, h->p.Y, h->Wp, h->Wbar,
+                             h->Dbar, L.R, L.n, L.spad, L.m, L.mp, h->mon_part, kMonBlocks, out,
+                             h->st);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "monitor");
+  }
   return BSADMM_OK;
 }
 
@@ -640,7 +671,7 @@ int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F) {
   for (size_t g = 0; g < L.groups.size() && e == hipSuccess; ++g) {
     const int i0 = L.groups[g].first, i1 = L.groups[g].second;
     const int64_t r0 = L.rstart[i0];
-    e = regen_group(h, i0, i1, h->Xp, L.n * L.Kp);
+    if (!L.keep) e = regen_group(h, i0, i1, h->Xp, L.n * L.Kp);
     for (int i = i0; i < i1 && e == hipSuccess; ++i) {
       const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
       e = bs::zw(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb, L.spad, ni,

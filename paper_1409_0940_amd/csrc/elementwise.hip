@@ -170,7 +170,51 @@ __global__ void sumsq_partial_kernel(const double* __restrict__ a, int64_t count
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// part[block] = sum over this block's share of sum_i (Wp_i - Wbar)^2 on the
+// first `rows * m` entries of each padded (rows x mp) array.
+__global__ void diffsq_partial_kernel(const double* __restrict__ Wp, const double* __restrict__ Wbar,
+                                      int R, int64_t rows, int64_t m, int64_t mp,
+                                      double* __restrict__ part) {
+  __shared__ double red[256];
+  const int64_t per = rows * mp;
+  double acc = 0.0;
+  GRID_STRIDE(e, rows * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    const double wb = Wbar[o];
+    for (int i = 0; i < R; ++i) {
+      const double d = Wp[(int64_t)i * per + o] - wb;
+      acc += d * d;
+    }
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// out[q] = scale[q] * sum_k part[q * nb + k], one workgroup per quantity.
+__global__ void final_reduce_kernel(const double* __restrict__ part, int nb, double s0, double s1,
+                                    double s2, double s3, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int q = blockIdx.x;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) acc += part[q * nb + k];
+  const double t = block_sum(acc, red);
+  const double sc = q == 0 ? s0 : (q == 1 ? s1 : (q == 2 ? s2 : s3));
+  if (threadIdx.x == 0) out[q] = sc * t;
+}
+
 }  // namespace
+
+hipError_t monitor(int loss, const double* P, const float* Y, const double* Wp,
+                   const double* Wbar, const double* Dbar, int R, int64_t n, int64_t spad,
+                   int64_t m, int64_t mp, double* part, int nb, double* out, hipStream_t st) {
+  loss_partial_kernel<<<nb, 256, 0, st>>>(loss, P, Y, n, m, mp, part);
+  sumsq_partial_kernel<<<nb, 256, 0, st>>>(Wp, (int64_t)R * spad * mp, part + nb);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Wp, Wbar, R, spad, m, mp, part + 2 * nb);
+  sumsq_partial_kernel<<<nb, 256, 0, st>>>(Dbar, n * mp, part + 3 * nb);
+  final_reduce_kernel<<<4, 256, 0, st>>>(part, nb, 1.0, 1.0 / (double)R, 1.0, 1.0, out);
+  return hipGetLastError();
+}
 
 hipError_t loss_partial(int loss, const double* P, const float* Y, int64_t n, int64_t m,
                         int64_t mp, double* part, int nblocks, hipStream_t st) {

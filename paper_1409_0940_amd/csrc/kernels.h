@@ -96,6 +96,12 @@ hipError_t loss_partial(int loss, const double* P, const float* Y, int64_t n, in
                         int64_t mp, double* part, int nblocks, hipStream_t st);
 hipError_t sumsq_partial(const double* a, int64_t count, double* part, int nblocks,
                          hipStream_t st);
+// Convergence monitor (no synchronisation): out[0] = sum V(y, P),
+// out[1] = sum_i ||Wp_i||^2 / R, out[2] = sum_i ||Wp_i - Wbar||^2,
+// out[3] = ||Dbar||^2, via nb partial sums per quantity in `part` (4 nb).
+hipError_t monitor(int loss, const double* P, const float* Y, const double* Wp,
+                   const double* Wbar, const double* Dbar, int R, int64_t n, int64_t spad,
+                   int64_t m, int64_t mp, double* part, int nb, double* out, hipStream_t st);
 // Scores out[r][c] = (float) P[r][c], c < m.
 hipError_t scores_out(const double* P, int64_t rows, int64_t m, int64_t mp, float* out,
                       hipStream_t st);

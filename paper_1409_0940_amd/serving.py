@@ -171,12 +171,33 @@ def latency_summary(results, wall_s):
 # ---------------------------------------------------------------------------
 
 class GpuExecutor:
-    def __init__(self, precision="bf16x3", max_streams=8, device="cuda:0"):
+    """One libbsadmm handle and one HIP stream per admitted solve.
+
+    Setup (input upload, Gram, FP64 inverse cache) runs on a worker thread
+    (the ctypes call releases the GIL), so the scheduler keeps feeding the
+    other solves while a new one is being set up.  After every chunk of
+    iterations the library's monitor reductions are enqueued on the solve's
+    stream and copied to pinned host memory; the scheduler reads them once
+    the chunk's event has completed, without synchronising any stream.  The
+    stopping statistic is F(W') = sum V(y, Z W') / n + lambda ||W'||^2, the
+    objective of the local model (R = 1).
+
+    By default each solve keeps its whole feature matrix in HBM
+    (BSADMM_Z_KEEP): Z is generated once at setup and iterations only stream
+    it through the two products; its bytes are part of the admission
+    footprint.  ``z_mode="store"`` regenerates Z every iteration instead.
+    """
+
+    def __init__(self, precision="bf16x3", max_streams=8, device="cuda:0", setup_workers=2,
+                 z_mode="keep"):
         import torch
+        from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
         self.precision = precision
+        self.z_mode = z_mode
         self.device = torch.device(device)
         self.free_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_streams)]
+        self.pool = ThreadPoolExecutor(max_workers=setup_workers)
 
     def footprint(self, job):
         from . import abi
@@ -184,42 +205,74 @@ class GpuExecutor:
         r = job.spec
         C = max(1, -(-r.s // 4096))
         p = abi.make_problem(X, Y, W, b, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision,
-                             check=False)
+                             check=False, z_mode=self.z_mode)
         p.X = p.Y = p.W = p.b = 256       # sizes only: footprint never touches memory
         inputs = sum(a.nbytes for a in job.inputs)
         return abi.bsadmm_footprint(p) + inputs
 
-    def start(self, job):
+    def _setup(self, job, stream):
         from .solver import Solver
         torch = self.torch
-        stream = self.free_streams.pop()
         X, Y, W, b = job.inputs
         r = job.spec
         C = max(1, -(-r.s // 4096))
         with torch.cuda.stream(stream):
-            dev = [torch.from_numpy(a).to(self.device, non_blocking=False) for a in (X, Y, W, b)]
-        S = Solver(*dev, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision, stream=stream)
-        return {"S": S, "stream": stream, "dev": dev, "event": None}
+            dev = [torch.from_numpy(a).to(self.device) for a in (X, Y, W, b)]
+            mon = torch.zeros(4, dtype=torch.float64, device=self.device)
+        S = Solver(*dev, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision, stream=stream,
+                   z_mode=self.z_mode)
+        return S, dev, mon
+
+    def start(self, job):
+        torch = self.torch
+        stream = self.free_streams.pop()
+        h = {"stream": stream, "job": job, "pending": 0, "event": None,
+             "host": torch.zeros(4, dtype=torch.float64).pin_memory()}
+        h["future"] = self.pool.submit(self._setup, job, stream)
+        return h
+
+    def _ensure_setup(self, h):
+        if "S" in h:
+            return True
+        if not h["future"].done():
+            return False
+        h["S"], h["dev"], h["mon"] = h["future"].result()
+        return True
 
     def enqueue(self, h, iters):
+        if not self._ensure_setup(h):
+            h["pending"] += iters
+            return
         torch = self.torch
-        h["S"].iterate_async(iters)
+        S = h["S"]
+        S.iterate_async(iters + h["pending"])
+        h["pending"] = 0
+        S.monitor_async(h["mon"])
+        with torch.cuda.stream(h["stream"]):
+            h["host"].copy_(h["mon"], non_blocking=True)
         ev = torch.cuda.Event()
         ev.record(h["stream"])
         h["event"] = ev
 
     def ready(self, h):
-        return h["event"] is None or h["event"].query()
+        if not self._ensure_setup(h):
+            return False
+        if h["pending"]:
+            self.enqueue(h, 0)
+            return False
+        return h["event"] is not None and h["event"].query()
 
     def objective(self, h):
-        return h["S"].objective()
+        v = h["host"].tolist()
+        r = h["job"].spec
+        return v[0] / r.n + r.lam * v[1]
 
     def finish(self, h):
         coef = h["S"].coef().cpu().numpy()
         h["S"].close()
         h["stream"].synchronize()
         self.free_streams.append(h["stream"])
-        h["dev"] = None
+        h["dev"] = h["mon"] = None
         return coef
 
 
@@ -246,20 +299,22 @@ def _request_inputs(r):
 
 
 def serve_stream(count=256, rate_per_s=20.0, precision="bf16x3", budget_gb=160.0, max_active=8,
-                 max_iters=300, check_every=10, rtol=2e-6, workers=8, n_range=(2000, 200000)):
+                 max_iters=300, check_every=10, rtol=2e-6, workers=8, n_range=(2000, 200000),
+                 z_mode="keep"):
     """Run the request stream of the serving workload end to end; returns (summary, results)."""
     import workloads as wl
     reqs = wl.serving_stream(count, rate_per_s, n_range=n_range)
     t = time.perf_counter()
     jobs = make_jobs(reqs, workers)
     gen_s = time.perf_counter() - t
-    ex = GpuExecutor(precision, max_active)
+    ex = GpuExecutor(precision, max_active, z_mode=z_mode)
     sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active, check_every, max_iters, rtol)
     t = time.perf_counter()
     res = sch.run(jobs)
     wall = time.perf_counter() - t
     summ = latency_summary(res, wall)
-    summ.update({"precision": precision, "max_active": max_active, "budget_gb": budget_gb,
+    summ.update({"precision": precision, "z_mode": z_mode, "max_active": max_active,
+                 "budget_gb": budget_gb,
                  "peak_active": sch.peak_active, "peak_used_gb": sch.peak_used / (1 << 30),
                  "input_generation_s": gen_s, "rate_per_s": rate_per_s,
                  "check_every": check_every, "max_iters": max_iters, "rtol": rtol})
@@ -277,6 +332,8 @@ if __name__ == "__main__":
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--precision", default="bf16x3")
     ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--z-mode", default="keep", choices=["keep", "store"])
     args = ap.parse_args()
-    summ, _ = serve_stream(args.requests, args.rate, args.precision, max_active=args.max_active)
+    summ, _ = serve_stream(args.requests, args.rate, args.precision, max_active=args.max_active,
+                           z_mode=args.z_mode)
     print(json.dumps(summ))

@@ -12,7 +12,7 @@ class Solver:
     """Block-splitting ADMM solve on one GPU (Algorithm 1 over an R x C grid)."""
 
     def __init__(self, X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
-                 stream=None, hbm_budget_bytes=0, workspace_bytes=0):
+                 stream=None, hbm_budget_bytes=0, workspace_bytes=0, z_mode="auto"):
         self._keep = (X, Y, W, b)
         self.n, self.d = X.shape
         self.m = Y.shape[1]
@@ -21,7 +21,7 @@ class Solver:
         self.device = X.device
         self.stream = stream
         self.problem = abi.make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss, precision,
-                                        stream, hbm_budget_bytes, workspace_bytes)
+                                        stream, hbm_budget_bytes, workspace_bytes, z_mode=z_mode)
         self.h = abi.bsadmm_setup(self.problem)
 
     def iterate(self, iters, timed=False):
@@ -52,6 +52,10 @@ class Solver:
         if Wmodel is not None:
             Wmodel = Wmodel.contiguous().to(torch.float64)
         return abi.bsadmm_objective(self.h, Wmodel)
+
+    def monitor_async(self, out):
+        """Enqueue [sum V(y, Z W'), mean ||W'_i||^2, sum ||W'_i - W-bar||^2, ||Delta-bar||^2]."""
+        return abi.bsadmm_monitor(self.h, out)
 
     def predict(self, Xt):
         return abi.bsadmm_predict(self.h, Xt, self.m, stream=self.stream)

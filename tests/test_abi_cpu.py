@@ -124,6 +124,17 @@ def test_workspace_cap_forms_row_groups():
     assert capped < big
 
 
+def test_keep_mode_needs_the_whole_z():
+    whole = abi.bsadmm_footprint(_problem(n=100000, s=8192, R=8, C=2, z_mode=2))
+    store = abi.bsadmm_footprint(_problem(n=100000, s=8192, R=8, C=2, z_mode=1,
+                                          ws=8192 * 4 * 30000))
+    assert whole > store
+    with pytest.raises(abi.BsadmmError) as ei:
+        abi.bsadmm_footprint(_problem(n=100000, s=8192, R=8, C=2, z_mode=2, ws=1 << 20))
+    assert ei.value.status == "ENOMEM"
+    assert abi.bsadmm_validate(_problem(z_mode=3)) == 1
+
+
 def test_last_error_is_thread_local():
     import threading
     abi.bsadmm_validate(_problem(R=0))

@@ -121,6 +121,27 @@ def test_objective_entry_point(prec, tol):
         S.close()
 
 
+@pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=[CASES[1][0], CASES[3][0]])
+def test_monitor_matches_oracle_state(case):
+    """bsadmm_monitor reductions against the oracle's state after 7 iterations."""
+    import torch
+    S, p, (X, Y, W, b) = _solver(case, "fp64")
+    S.iterate(7)
+    st, _ = o.admm(p, 7)
+    out = torch.zeros(4, dtype=torch.float64, device="cuda")
+    S.monitor_async(out)
+    got = out.cpu().numpy()
+    rows, cols = o.partition(p.n, p.R), o.partition(p.s, p.C)
+    osum = np.zeros_like(st["O"])
+    for i, (r0, r1) in enumerate(rows):
+        for j, (c0, c1) in enumerate(cols):
+            osum[r0:r1] += o.rff_block(X, W, b, (r0, r1), (c0, c1), p.s) @ st["Wp"][i, c0:c1]
+    ref = [o.loss_sum(p.loss, Y, osum), (st["Wp"] ** 2).sum() / p.R,
+           ((st["Wp"] - st["Wbar"][None]) ** 2).sum(), (st["Dbar"] ** 2).sum()]
+    np.testing.assert_allclose(got, ref, rtol=1e-9)
+    S.close()
+
+
 def test_ridge_fp64_reaches_closed_form():
     """n=4096, d=16, s=512, 1x2 grid: 1000 iterations reach (Z^T Z + n lam I)^{-1} Z^T Y."""
     case = CASES[0]
@@ -206,6 +227,28 @@ def test_budget_enomem_and_zero_iterations():
     r = S.iterate(0)
     assert r["iters_done"] == 0 and not S.coef().abs().max().item()
     S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_kept_z_matches_regenerated_z(prec):
+    """BSADMM_Z_KEEP (Z generated once at setup) gives the regenerated path's
+    iterates bit for bit; predict and the objective leave the kept Z intact."""
+    from paper_1409_0940_amd import Solver
+    X, Y, W, b = inputs("digits", 1500, 784, 384, 10, 3, 10.0)
+    args = (to_dev(X), to_dev(Y), to_dev(W), to_dev(b), 3, 3, 1e-4, 1.0, 10.0, "squared", prec)
+    A = Solver(*args, z_mode="store")
+    B = Solver(*args, z_mode="keep")
+    A.iterate(4)
+    B.iterate(4)
+    B.predict(to_dev(X[:100] * 0.3))
+    fa, fb = A.objective(), B.objective()
+    A.iterate(4)
+    B.iterate(4)
+    assert fa == fb
+    for name in ("Wbar", "O", "nu", "Wp"):
+        assert np.array_equal(A.state(name).cpu().numpy(), B.state(name).cpu().numpy()), name
+    A.close()
+    B.close()
 
 
 def test_row_groups_match_single_group():
