@@ -33,6 +33,33 @@ DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "bf16x3": "bf16x3"}
 MFMA_PASSES = {"fp32": 1, "fp64": 1, "bf16": 1, "bf16x3": 3}
 
 
+TRAFFIC_PROFILE = {("digits_n200000_d784_s10240_m10", "fp32"):
+                   "profiles/regen_fp32_digits_n200000_s10240_traffic.md"}
+KERNEL_SOURCES = ["paper_1409_0940_amd/csrc/feature.hip", "paper_1409_0940_amd/csrc/common.h"]
+
+
+def recorded_traffic(workload, precision):
+    """HBM bytes per regeneration launch from the committed counter summary, or
+    None if there is none for this workload or the kernel source changed since."""
+    import hashlib
+    path = TRAFFIC_PROFILE.get((workload, precision))
+    if not path or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    with open(os.path.join(ROOT, path)) as fh:
+        for line in fh:
+            k, _, v = line.partition(":")
+            if k in ("kernel_source_sha256", "traffic_bytes_per_launch"):
+                vals[k] = v.strip()
+    if vals.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -113,6 +140,8 @@ def main():
     ap.add_argument("--variants", default="fp64,bf16,bf16x3,fp32:keep,bf16:keep",
                     help="other precision[:z_mode] runs at the same iteration count ('' = none);"
                          " z_mode keep = Z generated once and kept in HBM")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 4 device copies of 1 GiB (HBM counter calibration) and exit")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run after the step timing (0 = skip)")
     args = ap.parse_args()
@@ -122,6 +151,17 @@ def main():
 
     import torch
     import workloads as wl
+
+    if args.calibrate_copy:
+        # known traffic: each copy reads 1 GiB and writes 1 GiB
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                          "copies": 4}))
+        return
 
     w = getattr(wl, args.workload)()
     log(f"workload {w.name}: generating inputs")
@@ -173,7 +213,8 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "regen_kernel",
                      "achieved": round(main_rec["achieved"], 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(main_rec["achieved"] / peak, 4),
-                     "traffic": None, "flops_per_launch": regen_flops_per_launch(w),
+                     "traffic": recorded_traffic(w.name, args.precision),
+                     "flops_per_launch": regen_flops_per_launch(w),
                      "avg_launch_ms": round(main_rec["launch_ms"], 4),
                      "launches": main_rec["launches"],
                      "mfma_passes": MFMA_PASSES[args.precision]},
