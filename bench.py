@@ -83,23 +83,20 @@ def gpu_run(w, precision, steps, warmup, dev_inputs, z_mode="auto"):
     st = S.iterate(steps, timed=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    flops = regen_flops_per_launch(w)
-    launch_ms = st["phase_ms"]["regen"] / max(1, st["launches"]) if st["launches"] else 0.0
+    # algorithmic flops of the regeneration launches (2 n d s per step, spread
+    # over one launch per feature block and row-block group) over their time
+    launches = st["launches"]
+    flops = 2.0 * w.n * w.d * w.s * steps / launches if launches else 0.0
+    launch_ms = st["phase_ms"]["regen"] / launches if launches else 0.0
     achieved = flops / (launch_ms * 1e-3) / 1e12 if launch_ms else 0.0
     rec = {"value": steps / wall, "ms_per_step": 1e3 * wall / steps, "setup_s": setup_s,
-           "launch_ms": launch_ms, "achieved": achieved, "launches": st["launches"],
+           "launch_ms": launch_ms, "achieved": achieved, "launches": launches,
+           "flops_per_launch": flops,
            "phase_ms_per_step": {k: v / steps for k, v in st["phase_ms"].items()},
            "coef": S.coef()}
     log(f"{precision}/{z_mode}: setup {setup_s:.2f} s, {steps} steps {wall:.3f} s "
         f"({rec['value']:.2f} it/s), regen {launch_ms:.3f} ms/launch")
     return S, rec
-
-
-def regen_flops_per_launch(w):
-    # one launch regenerates one feature block of one row-block group (all
-    # rows fit one group here): 2 * rows * d * s_j multiply-adds of the phase
-    sj = [(j + 1) * w.s // w.C - j * w.s // w.C for j in range(w.C)]
-    return 2.0 * w.n * w.d * (sum(sj) / len(sj))
 
 
 def cpu_baseline(w, X, Y, Wr, b):
@@ -214,7 +211,7 @@ def main():
                      "achieved": round(main_rec["achieved"], 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(main_rec["achieved"] / peak, 4),
                      "traffic": recorded_traffic(w.name, args.precision),
-                     "flops_per_launch": regen_flops_per_launch(w),
+                     "flops_per_launch": main_rec["flops_per_launch"],
                      "avg_launch_ms": round(main_rec["launch_ms"], 4),
                      "launches": main_rec["launches"],
                      "mfma_passes": MFMA_PASSES[args.precision]},

@@ -209,6 +209,15 @@ __device__ __forceinline__ float rff_cosf(float x) {
   return (q == 1 || q == 2) ? -v : v;
 }
 
+// cos for values that are rounded to BF16 afterwards: the hardware cosine
+// (v_cos_f32 takes revolutions) on the argument reduced to [-1/2, 1/2]
+// revolutions.  Its error is orders of magnitude below one BF16 rounding.
+__device__ __forceinline__ float rff_cos_bf16out(float x) {
+  float r = x * 0x1.45f306p-3f;  // x / (2 pi)
+  r = r - __builtin_rintf(r);
+  return __builtin_amdgcn_cosf(r);
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   // Workgroups are dealt round-robin over the 8 XCDs; give each XCD a
   // contiguous range of tile ids so neighbouring tiles share its L2.

@@ -247,6 +247,8 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
           acc_t z;
           if constexpr (P == BS_PREC_F64)
             z = scale * cos(th);
+          else if constexpr (P == BS_PREC_BF16)
+            z = scale * rff_cos_bf16out(th);
           else
             z = scale * rff_cosf(th);
           if constexpr (sizeof(ZT) == 2)

@@ -283,6 +283,11 @@ gram_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
   }
 }
 
+// Loads batched per wave before their MFMAs: more when each load feeds few
+// instructions (few output tiles), fewer when the tile count is large.
+template <int NTC> constexpr int ztr_unroll() { return NTC <= 2 ? 8 : 4; }
+template <int NTC> constexpr int zw_unroll() { return NTC <= 2 ? 4 : (NTC <= 6 ? 2 : 1); }
+
 template <typename ZT, int NTC>
 static void launch_ztr(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rop,
                        int64_t mp, int64_t split_rows, void* part, hipStream_t st) {
@@ -290,17 +295,31 @@ static void launch_ztr(const void* Z, int64_t ldz, int64_t rows, int64_t s, cons
   const int ntiles = (int)(mp / 16);
   const int64_t nsplit = (rows + split_rows - 1) / split_rows;
   dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
-  ztr_kernel<ZT, NTC, 8><<<g, 256, 0, st>>>((const ZT*)Z, ldz, rows, s, (const op_t*)Rop, mp,
-                                           split_rows, (op_t*)part);
+  ztr_kernel<ZT, NTC, ztr_unroll<NTC>()><<<g, 256, 0, st>>>(
+      (const ZT*)Z, ldz, rows, s, (const op_t*)Rop, mp, split_rows, (op_t*)part);
 }
 
+// One pass over Z covers all output tiles when there are at most 12 (FP32
+// operands) or 2 (FP64); beyond that, passes of 8 (FP32) or 2 (FP64) tiles.
+// The FP64 branch is resolved at compile time so its wide variants are never
+// instantiated.
 template <typename ZT>
 static void ztr_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rop,
                          int64_t mp, int64_t split_rows, void* part, hipStream_t st) {
-  const int ntiles = (int)(mp / 16);
-  if (ntiles == 1) launch_ztr<ZT, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-  else if (ntiles == 2 || sizeof(ZT) == 8) launch_ztr<ZT, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-  else launch_ztr<ZT, 4>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+  const int nt = (int)(mp / 16);
+  if constexpr (sizeof(ZT) == 8) {
+    if (nt == 1) launch_ztr<ZT, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else launch_ztr<ZT, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+  } else {
+    if (nt == 1) launch_ztr<ZT, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt == 2) launch_ztr<ZT, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 4) launch_ztr<ZT, 4>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 6) launch_ztr<ZT, 6>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 8) launch_ztr<ZT, 8>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 10) launch_ztr<ZT, 10>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 12) launch_ztr<ZT, 12>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else launch_ztr<ZT, 8>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+  }
 }
 
 }  // namespace
@@ -338,17 +357,27 @@ static void launch_zw(const void* Z, int64_t ldz, int64_t rows, int64_t s16, con
   using op_t = typename ZAcc<ZT>::type;
   const int ntiles = (int)(mp / 16);
   dim3 g((unsigned)((rows + 127) / 128), (unsigned)((ntiles + NTC - 1) / NTC));
-  zw_kernel<ZT, NTC, 4><<<g, 256, 0, st>>>((const ZT*)Z, ldz, rows, s16, (const op_t*)Wop, mp,
-                                          Pout);
+  zw_kernel<ZT, NTC, zw_unroll<NTC>()><<<g, 256, 0, st>>>((const ZT*)Z, ldz, rows, s16,
+                                                         (const op_t*)Wop, mp, Pout);
 }
 
 template <typename ZT>
 static void zw_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s16, const void* Wop,
                         int64_t mp, double* Pout, hipStream_t st) {
-  const int ntiles = (int)(mp / 16);
-  if (ntiles == 1) launch_zw<ZT, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-  else if (ntiles == 2 || sizeof(ZT) == 8) launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-  else launch_zw<ZT, 4>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+  const int nt = (int)(mp / 16);
+  if constexpr (sizeof(ZT) == 8) {
+    if (nt == 1) launch_zw<ZT, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+  } else {
+    if (nt == 1) launch_zw<ZT, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt == 2) launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 4) launch_zw<ZT, 4>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 6) launch_zw<ZT, 6>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 8) launch_zw<ZT, 8>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 10) launch_zw<ZT, 10>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 12) launch_zw<ZT, 12>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else launch_zw<ZT, 8>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+  }
 }
 
 }  // namespace
