@@ -52,6 +52,7 @@ struct Plan {
   std::vector<std::pair<int, int>> groups;  // row-block ranges [i0, i1)
   int64_t ws_rows = 0;
   int64_t split_rows = 2048, nsplit_max = 1;
+  int64_t nbpad = 0;             // per-block row segment of the transposed BF16 R
   int fac_batch = 1;
   bool keep = false;             // Z generated once and kept (BSADMM_Z_KEEP)
   size_t op = 4, zb = 4, vb = 4;  // operand, stored Z, product-operand bytes
@@ -59,6 +60,8 @@ struct Plan {
   // byte counts
   size_t b_xp = 0, b_wt = 0, b_bias = 0, b_q = 0, b_ws = 0, b_row = 0, b_rop = 0, b_col = 0,
          b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0;
+  // operand elements between the W' copies of consecutive row blocks
+  int64_t wop_stride() const { return prec == BSADMM_BF16 ? 2 * mp * spad : spad * mp; }
   size_t total() const {
     return b_xp + b_wt + b_bias + b_q + b_ws + 5 * b_row + b_rop + 3 * b_col + 4 * b_colR + b_wop +
            b_part + b_small + b_fac_tmp;
@@ -136,7 +139,8 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   }
   int64_t nmax = 0;
   for (int r = 0; r < L.R; ++r) nmax = std::max(nmax, L.rstart[r + 1] - L.rstart[r]);
-  L.split_rows = std::max<int64_t>(2048, rup((nmax + 63) / 64, 4));
+  L.split_rows = std::max<int64_t>(2048, rup((nmax + 63) / 64, 32));
+  L.nbpad = rup(nmax, 32) + 32;
   L.nsplit_max = (nmax + L.split_rows - 1) / L.split_rows;
   const size_t slot = (size_t)L.S * L.S * 8;
   const size_t fac_cap = (size_t)4 << 30;
@@ -147,7 +151,8 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.b_q = (size_t)L.R * L.C * slot;
   L.b_ws = (size_t)L.ws_rows * row_bytes;
   L.b_row = (size_t)L.n * L.mp * 8;
-  L.b_rop = (size_t)L.n * L.mp * L.vb;
+  L.b_rop = L.prec == BSADMM_BF16 ? (size_t)2 * L.mp * L.R * L.nbpad * 2
+                                  : (size_t)L.n * L.mp * L.vb;
   L.b_col = (size_t)L.spad * L.mp * 8;
   L.b_colR = (size_t)L.R * L.spad * L.mp * 8;
   L.b_wop = (size_t)L.R * L.spad * L.mp * L.vb;
@@ -257,8 +262,8 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
   const double cfac = 1.0 / (double)(L.C + 1);
   for (int it = 0; it < iters; ++it) {
     tm.begin();
-    HCHK(bs::row_pre(L.prec, h->p.loss == BSADMM_SQUARED ? 0 : 1, h->tau, cfac, L.n, L.m, L.mp,
-                     h->p.Y, h->Obar, h->nu, h->Dbar, h->O, h->Rop, h->st));
+    HCHK(bs::row_pre(L.prec, h->p.loss == BSADMM_SQUARED ? 0 : 1, h->tau, cfac, L.n, L.R, L.m,
+                     L.mp, L.nbpad, h->p.Y, h->Obar, h->nu, h->Dbar, h->O, h->Rop, h->st));
     tm.end(BSADMM_PH_ROW);
     tm.begin();
     HCHK(bs::col_pre(h->kappa, L.spad, L.m, L.mp, h->Wbar, h->mu, h->Wc, h->st));
@@ -275,9 +280,11 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
       tm.begin();
       for (int i = i0; i < i1; ++i) {
         const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
+        const char* Ri = L.prec == BSADMM_BF16
+                             ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
+                             : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
         HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb,
-                             L.spad, ni, L.spad, (const char*)h->Rop + (size_t)ri * L.mp * L.vb,
-                             L.mp, L.split_rows,
+                             L.spad, ni, L.spad, Ri, (int64_t)L.R * L.nbpad, L.mp, L.split_rows,
                              (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.vb,
                              h->st));
       }
@@ -289,12 +296,8 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
                      L.spad, L.mp, h->rhs, h->Wp, h->U, h->Wop, h->st));
       tm.end(BSADMM_PH_SOLVE);
       tm.begin();
-      for (int i = i0; i < i1; ++i) {
-        const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-        HCHK(bs::zw(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb, L.spad, ni,
-                    L.spad, (const char*)h->Wop + (size_t)i * L.spad * L.mp * L.vb, L.mp,
-                    h->P + (size_t)ri * L.mp, h->st));
-      }
+      HCHK(bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, h->Wop, L.wop_stride(), L.mp,
+                  h->P, h->st));
       tm.end(BSADMM_PH_ZW);
     }
     tm.begin();
@@ -472,7 +475,7 @@ int copy_state(const bsadmm_handle* h, int which, double* dense, bool to_dense) 
   }
   if (!to_dense && which == BSADMM_ST_WP) {
     // keep the operand copy of W' in step with the imported state
-    HCHK(bs::to_op(L.prec, h->Wp, (int64_t)L.R * L.spad * L.mp, h->Wop, st));
+    HCHK(bs::to_wop(L.prec, h->Wp, L.R, L.spad, L.mp, h->Wop, st));
   }
   HCHK(hipStreamSynchronize(st));
   return BSADMM_OK;
@@ -602,7 +605,7 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
   }
   const size_t bb = L.prec == BSADMM_FP64 ? 8 : 4;
   hipError_t e = hipMemsetAsync(zt, 0, (size_t)chunk * L.spad * L.zb, st);  // pad columns
-  if (e == hipSuccess) e = bs::to_op(L.prec, h->Wbar, L.spad * L.mp, wop, st);
+  if (e == hipSuccess) e = bs::to_wop(L.prec, h->Wbar, 1, L.spad, L.mp, wop, st);
   for (int64_t r0 = 0; r0 < nt && e == hipSuccess; r0 += chunk) {
     const int64_t rows = std::min(chunk, nt - r0);
     e = bs::prep_rows(L.prec, Xt + r0 * L.d, rows, L.d, L.Kp, xop, chunk * L.Kp, nullptr, st);
@@ -611,7 +614,7 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
                     (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.s * L.Kp, L.sj[j],
                     (const char*)h->bias + (size_t)L.cstart[j] * bb, L.Kp, h->scale,
                     (char*)zt + (size_t)L.coff[j] * L.zb, L.spad, st);
-    if (e == hipSuccess) e = bs::zw(L.prec, zt, L.spad, rows, L.spad, wop, L.mp, pbuf, st);
+    if (e == hipSuccess) e = bs::zw(L.prec, zt, L.spad, rows, 1, 0, 1, L.spad, wop, 0, L.mp, pbuf, st);
     if (e == hipSuccess) e = bs::scores_out(pbuf, rows, L.m, L.mp, out + r0 * L.m, st);
   }
   hipError_t e2 = hipStreamSynchronize(st);
@@ -666,17 +669,13 @@ int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F) {
   } else {
     e = hipMemcpyAsync(wpad, h->Wbar, (size_t)L.spad * L.mp * 8, hipMemcpyDeviceToDevice, st);
   }
-  if (e == hipSuccess) e = bs::to_op(L.prec, wpad, L.spad * L.mp, wop, st);
+  if (e == hipSuccess) e = bs::to_wop(L.prec, wpad, 1, L.spad, L.mp, wop, st);
   // forward pass Z W over all rows into the P buffer (free between iterations)
   for (size_t g = 0; g < L.groups.size() && e == hipSuccess; ++g) {
     const int i0 = L.groups[g].first, i1 = L.groups[g].second;
-    const int64_t r0 = L.rstart[i0];
     if (!L.keep) e = regen_group(h, i0, i1, h->Xp, L.n * L.Kp);
-    for (int i = i0; i < i1 && e == hipSuccess; ++i) {
-      const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-      e = bs::zw(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb, L.spad, ni,
-                 L.spad, wop, L.mp, h->P + (size_t)ri * L.mp, st);
-    }
+    if (e == hipSuccess)
+      e = bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, wop, 0, L.mp, h->P, st);
   }
   if (e == hipSuccess)
     e = bs::loss_partial(h->p.loss == BSADMM_SQUARED ? 0 : 1, h->P, h->p.Y, L.n, L.m, L.mp, part,

@@ -16,6 +16,8 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 // 16-byte staging register.  A native vector type: arrays of it stay in
 // registers, where arrays of HIP's struct-based uint4 end up in scratch.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef short v4s __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------------------
 // Precision traits.  op_t is the MFMA operand element, acc_t the accumulator
@@ -119,6 +121,17 @@ __device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 products with 16-byte (8 values) and 8-byte (4 values) fragments per
+// lane; same lane layout as the other 16 x 16 instructions.
+__device__ __forceinline__ v4f mfma_bf16x8(u32x4 a, u32x4 b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                 __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma_bf16x4(u32x2 a, u32x2 b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, a),
+                                                   __builtin_bit_cast(v4s, b), c, 0, 0, 0);
+}
+
 // Row (within a 16 x 16 tile) of the accumulator element a lane of group
 // g = lane / 16 holds in register r; its column is lane % 16.  The FP32
 // accumulators of the 16x16x4 / 16x16x32 instructions hold rows 4 g + r,
@@ -155,11 +168,25 @@ __host__ __device__ __forceinline__ uint16_t f32_to_bf16(float x) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
+// Two FP32 values to a packed pair of BF16 (low half = a), round to nearest
+// even through the gfx950 conversion instruction; equal to f32_to_bf16 on
+// every non-NaN input.
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  const bf16x2_t v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
 __host__ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   uint32_t u = ((uint32_t)h) << 16;
   float x;
   __builtin_memcpy(&x, &u, 4);
   return x;
+}
+// A value as a BF16 head h = bf16(v) and a BF16 residual l = bf16(v - h):
+// h + l carries about 16 significant bits of v.
+__device__ __forceinline__ void split_bf16(double v, uint16_t& h, uint16_t& l) {
+  h = f32_to_bf16((float)v);
+  l = f32_to_bf16((float)(v - (double)bf16_to_f32(h)));
 }
 
 template <typename T> __device__ __forceinline__ T cvt_from_double(double x);

@@ -51,6 +51,31 @@ __global__ void row_pre_kernel(int loss, double tau, double cfac, int64_t n, int
   }
 }
 
+// BF16 products: R as BF16 head and residual planes stored transposed,
+// Rt[plane][c][i * nbpad + (r - first row of block i)].
+__global__ void row_pre_bf16_kernel(int loss, double tau, double cfac, int64_t n, int R,
+                                    int64_t m, int64_t mp, int64_t nbpad,
+                                    const float* __restrict__ Y, const double* __restrict__ Obar,
+                                    const double* __restrict__ nu, const double* __restrict__ Dbar,
+                                    double* __restrict__ O, uint16_t* __restrict__ Rt) {
+  const int64_t ldr = (int64_t)R * nbpad;
+  GRID_STRIDE(e, n * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    const double nv = nu[o];
+    O[o] = prox_loss(loss, Obar[o] - nv, (double)Y[e], tau);
+    // row block of r: the largest i with floor(i n / R) <= r
+    int64_t i = r * R / n;
+    while (i + 1 < R && (i + 1) * n / R <= r) ++i;
+    while (i > 0 && i * n / R > r) --i;
+    uint16_t hi, lo;
+    split_bf16(Dbar[o] * cfac + nv, hi, lo);
+    const int64_t t = c * ldr + i * nbpad + (r - i * n / R);
+    Rt[t] = hi;
+    Rt[t + mp * ldr] = lo;
+  }
+}
+
 __global__ void row_post_kernel(int64_t n, int64_t m, int64_t mp, double a, double bfac,
                                 const double* __restrict__ O, const double* __restrict__ P,
                                 double* __restrict__ Obar, double* __restrict__ nu,
@@ -228,11 +253,14 @@ hipError_t sumsq_partial(const double* a, int64_t count, double* part, int nbloc
   return hipGetLastError();
 }
 
-hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int64_t m, int64_t mp,
-                   const float* Y, const double* Obar, const double* nu, const double* Dbar,
-                   double* O, void* Rop, hipStream_t st) {
+hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int R, int64_t m,
+                   int64_t mp, int64_t nbpad, const float* Y, const double* Obar, const double* nu,
+                   const double* Dbar, double* O, void* Rop, hipStream_t st) {
   unsigned g = grid_for(n * m);
-  if (prec == BS_PREC_F64)
+  if (prec == BS_PREC_BF16)
+    row_pre_bf16_kernel<<<g, 256, 0, st>>>(loss, tau, cfac, n, R, m, mp, nbpad, Y, Obar, nu, Dbar,
+                                           O, (uint16_t*)Rop);
+  else if (prec == BS_PREC_F64)
     row_pre_kernel<double><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
                                                (double*)Rop);
   else
@@ -271,6 +299,33 @@ hipError_t pad(const double* src, int64_t rows, int64_t m, int64_t mp, double* d
                hipStream_t st) {
   if (rows * m == 0) return hipSuccess;
   pad_kernel<<<grid_for(rows * m), 256, 0, st>>>(src, rows, m, mp, dst);
+  return hipGetLastError();
+}
+
+namespace {
+// W' (blocks of [spad][mp] doubles) as BF16 head and residual planes stored
+// transposed, [b][plane][mp][spad].
+__global__ void to_wop_bf16_kernel(const double* __restrict__ src, int64_t nblk, int64_t spad,
+                                   int64_t mp, uint16_t* __restrict__ dst) {
+  const int64_t per = spad * mp;
+  GRID_STRIDE(e, nblk * per) {
+    const int64_t b = e / per, rem = e - b * per;
+    const int64_t f = rem / mp, c = rem - f * mp;
+    uint16_t hi, lo;
+    split_bf16(src[e], hi, lo);
+    const int64_t t = (b * 2 * mp + c) * spad + f;
+    dst[t] = hi;
+    dst[t + mp * spad] = lo;
+  }
+}
+}  // namespace
+
+hipError_t to_wop(int prec, const double* src, int64_t nblk, int64_t spad, int64_t mp, void* dst,
+                  hipStream_t st) {
+  if (prec != BS_PREC_BF16) return to_op(prec, src, nblk * spad * mp, dst, st);
+  if (nblk * spad * mp == 0) return hipSuccess;
+  to_wop_bf16_kernel<<<grid_for(nblk * spad * mp), 256, 0, st>>>(src, nblk, spad, mp,
+                                                                 (uint16_t*)dst);
   return hipGetLastError();
 }
 

@@ -254,13 +254,15 @@ __global__ void identity_pad_kernel(double* __restrict__ slot, int64_t S, int64_
 // rows of W'_b and up to NTC column tiles; a lane loads 4 adjacent doubles of
 // a row of Q and the 4 matching rhs rows feed 4 MFMA instructions.
 // ---------------------------------------------------------------------------
-template <int P, int NTC>
+// OUT is the type of the operand copy of W' for the forward products:
+// double or float in W''s own layout, or uint16_t for BF16 head and residual
+// planes stored transposed, [i][plane][mp][spad].
+template <typename OUT, int NTC>
 __global__ void __launch_bounds__(256)
 solve_kernel(const double* __restrict__ Q, int64_t S, int C, int b0, const int64_t* __restrict__ coff,
              const int64_t* __restrict__ sjs, int64_t spad, int64_t mp,
              const double* __restrict__ rhs, double* __restrict__ Wp, double* __restrict__ U,
-             typename Prec<P>::op_t* __restrict__ Wop) {
-  using op_t = typename Prec<P>::op_t;
+             OUT* __restrict__ Wop) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
   const int b = b0 + (int)blockIdx.y;
@@ -306,7 +308,15 @@ solve_kernel(const double* __restrict__ Q, int64_t S, int C, int b0, const int64
         const double w = acc[t][r];
         Wp[o] = w;
         U[o] = rhs[o] - w;
-        Wop[o] = cvt_from_double<op_t>(w);
+        if constexpr (sizeof(OUT) == 2) {
+          uint16_t hi, lo;
+          split_bf16(w, hi, lo);
+          const int64_t tcol = ((int64_t)i * 2 * mp + nt * 16 + fr) * spad + coff[j] + row;
+          Wop[tcol] = hi;
+          Wop[tcol + mp * spad] = lo;
+        } else {
+          Wop[o] = (OUT)w;
+        }
       }
     }
   }
@@ -349,11 +359,14 @@ hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, co
   if (nb <= 0) return hipSuccess;
   dim3 g((unsigned)(S / 64), (unsigned)nb, (unsigned)((ntiles + NTC - 1) / NTC));
   if (prec == BS_PREC_F64)
-    solve_kernel<BS_PREC_F64, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
-                                                      (double*)Wop);
-  else  // the product operands are FP32 for every other precision
-    solve_kernel<BS_PREC_F32, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
-                                                      (float*)Wop);
+    solve_kernel<double, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
+                                                 (double*)Wop);
+  else if (prec == BS_PREC_BF16)
+    solve_kernel<uint16_t, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
+                                                   (uint16_t*)Wop);
+  else  // FP32 and BF16X3 multiply FP32 operands
+    solve_kernel<float, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
+                                                (float*)Wop);
   return hipGetLastError();
 }
 

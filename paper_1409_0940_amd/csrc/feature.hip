@@ -261,6 +261,182 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wide-tile regeneration for single-plane BF16 operands.  A 512-thread
+// workgroup computes a 256 x 256 tile of Z (8 waves of 128 rows x 64
+// features, 32 MFMA 16x16x32 tiles each), so each staged k-chunk feeds twice
+// the MFMA work of the 128 x 128 kernel per byte moved from L2.
+// Double-buffered LDS (147 KB) keeps one workgroup per CU.  The staging loads
+// are raw buffer loads whose descriptor ends at the tile's last valid row, so
+// rows past the edge read as zero and one 32-bit offset per thread addresses
+// all of its segments.  The feature tile is the MFMA's M operand and the row
+// tile its N operand: a lane ends with 4 adjacent features of one row, packed
+// to BF16 and stored as one 8-byte write.  The k-steps are those of
+// regen_kernel.
+// ---------------------------------------------------------------------------
+constexpr int WBM = 256, WBN = 256, WNT = 512, WKROW = 128, WPITCH = WKROW + 16;
+constexpr int WSEG = WKROW / 16;                 // 16-byte segments per staged row
+constexpr int WNS = WBM * WSEG / WNT;            // segments per thread and operand (4)
+constexpr int WRSTEP = WNT / WSEG;               // rows between a thread's segments (64)
+constexpr int WTJ = 4;                           // feature tiles per wave
+
+// Raw buffer descriptor over [p, p + bytes): loads past the end return zero.
+// p and bytes are wave-uniform; rebuilding them from readfirstlane halves
+// keeps the descriptor in scalar registers even where their arithmetic was
+// done in vector registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wide_rsrc(const void* p, int64_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const int nb = __builtin_amdgcn_readfirstlane((int)bytes);
+  void* q = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, nb, 0x00020000);
+}
+
+__device__ __forceinline__ void wide_load(__amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
+                                          int voff, int rowb, int koff, u32x4 (&sa)[WNS],
+                                          u32x4 (&sb)[WNS]) {
+#pragma unroll
+  for (int i = 0; i < WNS; ++i)
+    sa[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                          ra, voff, i * WRSTEP * rowb + koff, 0));
+#pragma unroll
+  for (int i = 0; i < WNS; ++i)
+    sb[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                          rb, voff, i * WRSTEP * rowb + koff, 0));
+}
+
+__device__ __forceinline__ void wide_store(unsigned char* buf, int lofs, const u32x4 (&sa)[WNS],
+                                           const u32x4 (&sb)[WNS]) {
+#pragma unroll
+  for (int i = 0; i < WNS; ++i)
+    *reinterpret_cast<u32x4*>(buf + lofs + i * WRSTEP * WPITCH) = sa[i];
+#pragma unroll
+  for (int i = 0; i < WNS; ++i)
+    *reinterpret_cast<u32x4*>(buf + WBM * WPITCH + lofs + i * WRSTEP * WPITCH) = sb[i];
+}
+
+// The MFMA work of one staged chunk (64 k values, two 16x16x32 steps).
+__device__ __forceinline__ void wide_mfma(const unsigned char* buf, int wm, int wn, int fr, int fg,
+                                          v4f (&acc)[WTJ][8]) {
+#pragma unroll
+  for (int ks = 0; ks < WKROW / 64; ++ks) {
+    const int kbyte = ks * 64 + 16 * fg;
+    Frag<BS_PREC_BF16> fw[WTJ];
+#pragma unroll
+    for (int j = 0; j < WTJ; ++j)
+      fw[j] = load_frag<BS_PREC_BF16>(reinterpret_cast<const uint16_t*>(
+          buf + (WBM + wn * (16 * WTJ) + j * 16 + fr) * WPITCH + kbyte));
+    // row tiles in two halves of 4: fewer fragments live at once
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      Frag<BS_PREC_BF16> fx[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        fx[i] = load_frag<BS_PREC_BF16>(reinterpret_cast<const uint16_t*>(
+            buf + (wm * 128 + (4 * h + i) * 16 + fr) * WPITCH + kbyte));
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WTJ; ++j) mfma_step(acc[j][4 * h + i], fw[j], fx[i]);
+      // keep the next fragment loads behind these products (registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(WNT, 1)
+regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
+                       const uint16_t* __restrict__ Wt, int64_t cols,
+                       const float* __restrict__ bias, int64_t Kp, float scale,
+                       uint16_t* __restrict__ Z, int64_t ldz) {
+  constexpr int TJ = WTJ;
+  constexpr int BK = WKROW / 2;               // 64 bf16 per chunk
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][(WBM + WBN) * WPITCH];
+
+  const int tiles_m = (int)((rows + WBM - 1) / WBM);
+  const int tiles_n = (int)((cols + WBN - 1) / WBN);
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_group = GROUP_M * tiles_n;
+  const int g = t / per_group;
+  const int first_m = g * GROUP_M;
+  const int gsize = min(GROUP_M, tiles_m - first_m);
+  const int tm = first_m + (t % per_group) % gsize;
+  const int tn = (t % per_group) / gsize;
+  const int64_t row0 = (int64_t)tm * WBM, col0 = (int64_t)tn * WBN;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;     // 2 x 4 waves
+  const int fr = lane & 15, fg = lane >> 4;
+
+  // staging: thread tid moves segment tid % 8 of rows tid / 8 + 64 i
+  const int rowb = (int)(Kp * 2);
+  const int voff = (tid / WSEG) * rowb + (tid % WSEG) * 16;
+  const int lofs = (tid / WSEG) * WPITCH + (tid % WSEG) * 16;
+  const __amdgpu_buffer_rsrc_t ra = wide_rsrc(Xp + row0 * Kp, min<int64_t>(rows - row0, WBM) * rowb);
+  const __amdgpu_buffer_rsrc_t rb = wide_rsrc(Wt + col0 * Kp, min<int64_t>(cols - col0, WBN) * rowb);
+
+  v4f acc[TJ][8];   // [feature tile][row tile]
+#pragma unroll
+  for (int j = 0; j < TJ; ++j)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[j][i] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nchunks = Kp / BK;
+  u32x4 sa[WNS], sb[WNS];
+  wide_load(ra, rb, voff, rowb, 0, sa, sb);
+  wide_store(lds[0], lofs, sa, sb);
+  __syncthreads();
+  for (int64_t c = 0; c < nchunks; ++c) {
+    const int buf = (int)(c & 1);
+    const bool more = c + 1 < nchunks;
+    if (more) wide_load(ra, rb, voff, rowb, (int)(c + 1) * WKROW, sa, sb);
+    wide_mfma(lds[buf], wm, wn, fr, fg, acc);
+    if (more) wide_store(lds[buf ^ 1], lofs, sa, sb);
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds features 4 fg .. 4 fg + 3 of tile j for row fr of
+  // tile i; phase + bias -> cos -> two packed BF16 pairs -> one 8-byte store.
+  // Tiles that cross the row or feature edge store element by element.
+  if (row0 + WBM <= rows && col0 + WBN <= cols) {
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int64_t f = col0 + wn * (16 * TJ) + j * 16 + 4 * fg;
+      const float b0 = bias[f], b1 = bias[f + 1], b2 = bias[f + 2], b3 = bias[f + 3];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t row = row0 + wm * 128 + i * 16 + fr;
+        uint2 v;
+        v.x = pack_bf16x2(scale * rff_cos_bf16out(acc[j][i][0] + b0),
+                          scale * rff_cos_bf16out(acc[j][i][1] + b1));
+        v.y = pack_bf16x2(scale * rff_cos_bf16out(acc[j][i][2] + b2),
+                          scale * rff_cos_bf16out(acc[j][i][3] + b3));
+        *reinterpret_cast<uint2*>(Z + row * ldz + f) = v;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) {
+      const int64_t f = col0 + wn * (16 * TJ) + j * 16 + 4 * fg;
+      float bj[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bj[r] = bias[min(f + r, cols - 1)];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t row = row0 + wm * 128 + i * 16 + fr;
+        if (row >= rows) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (f + r < cols) {
+            const float z = scale * rff_cos_bf16out(acc[j][i][r] + bj[r]);
+            Z[row * ldz + f + r] = (uint16_t)(pack_bf16x2(z, 0.f) & 0xffffu);
+          }
+      }
+    }
+  }
+}
+
 inline unsigned grid_1d(int64_t count, int threads, int64_t cap = 65536) {
   int64_t g = (count + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -356,11 +532,22 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
           (const float*)Xp, xps, rows, (const float*)Wt, wps, cols, (const float*)bias, Kp,
           (float)scale, (float*)Z, ldz);
       break;
-    case BS_PREC_BF16:
-      regen_kernel<BS_PREC_BF16, uint16_t><<<g, NTHREADS, 0, st>>>(
-          (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,
-          (float)scale, (uint16_t*)Z, ldz);
+    case BS_PREC_BF16: {
+      // wide tiles: the 8-byte Z stores need ldz and the base 8-byte aligned,
+      // the 32-bit buffer offsets a tile of 256 rows below 2 GiB
+      const int64_t wt = ((rows + WBM - 1) / WBM) * ((cols + WBN - 1) / WBN);
+      if (ldz % 4 == 0 && reinterpret_cast<uintptr_t>(Z) % 8 == 0 && wt <= 0x7fffffff &&
+          Kp <= ((int64_t)1 << 21)) {
+        regen_bf16_wide_kernel<<<dim3((unsigned)wt), WNT, 0, st>>>(
+            (const uint16_t*)Xp, rows, (const uint16_t*)Wt, cols, (const float*)bias, Kp,
+            (float)scale, (uint16_t*)Z, ldz);
+      } else {
+        regen_kernel<BS_PREC_BF16, uint16_t><<<g, NTHREADS, 0, st>>>(
+            (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias,
+            Kp, (float)scale, (uint16_t*)Z, ldz);
+      }
       break;
+    }
     default:
       regen_kernel<BS_PREC_BF16X3, float><<<g, NTHREADS, 0, st>>>(
           (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,

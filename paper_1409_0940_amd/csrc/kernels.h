@@ -38,10 +38,19 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
 // The padded feature index: feature block j occupies [coff_j, coff_j + s_j)
 // with coff_j a multiple of 64; spad is the padded total; pad entries are 0.
 
+// Product operands.  FP64, FP32 and BF16X3 multiply R as [n][mp] and W' as
+// [i][spad][mp] in the operand type (double, float, float).  BF16 multiplies
+// BF16 head and residual planes of both, stored transposed: R as
+// [plane][mp][ldr] with ldr = R * nbpad and row block i in the segment
+// starting at i * nbpad (zero for at least 32 rows past its rows), W' as
+// [i][plane][mp][spad].
+
 // Partial transpose products for one row block:
-// part[sp][f][c] = sum_{r in split sp} Z[r][f] * Rop[r][c], f < spad, c < mp.
+// part[sp][f][c] = sum_{r in split sp} Z[r][f] * R[r][c], f < spad, c < mp.
+// Rop points at the block's rows; ldr is used by BF16 only, whose split_rows
+// must be a multiple of 32.
 hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t spad,
-                       const void* Rop, int64_t mp, int64_t split_rows, void* part,
+                       const void* Rop, int64_t ldr, int64_t mp, int64_t split_rows, void* part,
                        hipStream_t st);
 // For row blocks i in [i0, i1): rhs_i = W-bar - mu'_i + U_i + sum_sp part_i[sp]
 // (part laid out [i][sp < nsplit_max][spad][mp]; the split count of block i
@@ -49,9 +58,13 @@ hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64
 hipError_t reduce_rhs(int prec, const void* part, int64_t nsplit_max, int64_t n, int R, int i0,
                       int i1, int64_t split_rows, int64_t spad, int64_t mp, const double* Wbar,
                       const double* mup, const double* U, double* rhs, hipStream_t st);
-// Pout[r][c] = sum_f Z[r][f] * Wop[f][c] for r < rows, c < mp, f < spad.
-hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t spad, const void* Wop,
-              int64_t mp, double* Pout, hipStream_t st);
+// For the row blocks i in [i0, i1) of the partition of n rows into R blocks:
+// Pout[r][c] = sum_f Z[r][f] * W'_i[f][c], f < spad (a multiple of 64),
+// c < mp.  Z points at row floor(i0 n / R), Pout at row 0; W'_i starts
+// wop_stride operand elements after W'_{i-1} (0: one W' for every block).
+hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t n, int R, int i0, int i1,
+              int64_t spad, const void* Wop, int64_t wop_stride, int64_t mp, double* Pout,
+              hipStream_t st);
 // Gram of one block (rows x [coff, coff + sj)) of Z into slot (ld = S):
 // lower 64 x 64 tiles of I + Z^T Z.
 hipError_t gram(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t coff, int64_t sj,
@@ -67,14 +80,15 @@ hipError_t spd_inverse(double* slots, int batch, int64_t S, double* work, double
                        int* flag, hipStream_t st);
 
 // W'_b = Q_b rhs_b for blocks b in [b0, b0 + nb) (b = i * C + j); U = rhs - W';
-// Wop = W' as operand.  coff / sjs are device arrays of length C.
+// Wop = W' in the operand layout of the precision.  coff / sjs are device
+// arrays of length C.
 hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, const int64_t* coff,
                  const int64_t* sjs, int64_t spad, int64_t mp, const double* rhs, double* Wp,
                  double* U, void* Wop, hipStream_t st);
 
 // Elementwise steps (FP64 state, n x mp / s x mp, only c < m touched).
-hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int64_t m,
-                   int64_t mp, const float* Y, const double* Obar, const double* nu,
+hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int R, int64_t m,
+                   int64_t mp, int64_t nbpad, const float* Y, const double* Obar, const double* nu,
                    const double* Dbar, double* O, void* Rop, hipStream_t st);
 hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, const double* P,
                     double* Obar, double* nu, double* Dbar, hipStream_t st);
@@ -89,6 +103,10 @@ hipError_t pad(const double* src, int64_t rows, int64_t m, int64_t mp, double* d
                hipStream_t st);
 // Operand copy of a padded FP64 array (rows x mp) into op type.
 hipError_t to_op(int prec, const double* src, int64_t count, void* dst, hipStream_t st);
+// Operand copy of nblk blocks of W' ([spad][mp] doubles each) in the layout
+// the forward products of the precision read.
+hipError_t to_wop(int prec, const double* src, int64_t nblk, int64_t spad, int64_t mp, void* dst,
+                  hipStream_t st);
 // Deterministic partial sums (one per workgroup, nblocks <= 65536, summed by
 // the caller in order): sum of V(y_rc, P_rc) over r < n, c < m (loss 0:
 // squared, otherwise hinge), and sum of squares of a.

@@ -283,6 +283,402 @@ gram_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Transpose products from a BF16 Z on the 16x16x16 BF16 instruction, one row
+// block per launch: part[sp][f][c] = sum_{r in split sp} Z[r][f] R[r][c].
+// R comes as BF16 head and residual planes stored transposed, Rt[p][c][r]
+// (plane stride mp * ldr, zero past the block's rows), and both planes are
+// multiplied, so R keeps ~16 significant bits.
+// A lane loads a 4-row x 4-feature block of Z (four 8-byte loads of adjacent
+// rows) and transposes it in registers; instruction q of a step takes feature
+// 4 m + q as its row m and the 16 rows of the step as k.  split_rows is a
+// multiple of 16, so every 16-row step lies in one split.
+// ---------------------------------------------------------------------------
+template <int NTC, int U>
+__global__ void __launch_bounds__(256)
+ztr_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
+                const uint16_t* __restrict__ Rt, int64_t ldr, int64_t mp, int64_t split_rows,
+                float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t f0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int64_t sp = blockIdx.y;
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const int64_t rbeg = sp * split_rows;
+  const int64_t rend = min(rows, rbeg + split_rows);
+  const int64_t rlast = (rows - 1) / 16 * 16;       // start of the block's last step
+  const int64_t fl = f0 + 4 * fr;
+  const int64_t pstride = mp * ldr;
+
+  v4f acc[4][NTC];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  if (f0 < s) {
+    for (int64_t rb = rbeg; rb < rend; rb += 16 * U) {
+      u32x2 z[U][4], rv[U][NTC][2];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r16 = rb + 16 * u;
+        ok[u] = r16 < rend;                 // whole step inside the split, or none of it
+        const int64_t rs = min(r16, rlast);  // in-bounds stand-in for a step past the end
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t r = min(rs + 4 * fg + t, rows - 1);
+          z[u][t] = *reinterpret_cast<const u32x2*>(Z + r * ldz + fl);
+        }
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) {
+          const int nt = min(nc0 + t, ntiles - 1);
+          const uint16_t* rp = Rt + (int64_t)(nt * 16 + fr) * ldr + rs + 4 * fg;
+          rv[u][t][0] = *reinterpret_cast<const u32x2*>(rp);
+          rv[u][t][1] = *reinterpret_cast<const u32x2*>(rp + pstride);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // a[q] = feature fl + q at rows 4 fg .. 4 fg + 3 of the step
+        u32x2 a[4];
+        a[0].x = __builtin_amdgcn_perm(z[u][1].x, z[u][0].x, 0x05040100u);
+        a[0].y = __builtin_amdgcn_perm(z[u][3].x, z[u][2].x, 0x05040100u);
+        a[1].x = __builtin_amdgcn_perm(z[u][1].x, z[u][0].x, 0x07060302u);
+        a[1].y = __builtin_amdgcn_perm(z[u][3].x, z[u][2].x, 0x07060302u);
+        a[2].x = __builtin_amdgcn_perm(z[u][1].y, z[u][0].y, 0x05040100u);
+        a[2].y = __builtin_amdgcn_perm(z[u][3].y, z[u][2].y, 0x05040100u);
+        a[3].x = __builtin_amdgcn_perm(z[u][1].y, z[u][0].y, 0x07060302u);
+        a[3].y = __builtin_amdgcn_perm(z[u][3].y, z[u][2].y, 0x07060302u);
+        const u32x2 zero2 = {0u, 0u};
+#pragma unroll
+        for (int t = 0; t < NTC; ++t) {
+          const u32x2 bh = ok[u] ? rv[u][t][0] : zero2;
+          const u32x2 bl = ok[u] ? rv[u][t][1] : zero2;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc[q][t] = mfma_bf16x4(a[q], bh, acc[q][t]);
+            acc[q][t] = mfma_bf16x4(a[q], bl, acc[q][t]);
+          }
+        }
+      }
+    }
+  }
+  // lane holds D[m = 4 fg + r][n = fr]; feature = f0 + 4 m + q
+#pragma unroll
+  for (int t = 0; t < NTC; ++t) {
+    const int nt = nc0 + t;
+    if (nt >= ntiles) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t f = f0 + 4 * acc_row<float>(fg, r) + q;
+        if (f < s) part[(sp * s + f) * mp + nt * 16 + fr] = acc[q][t][r];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward products from a BF16 Z on the 16x16x32 BF16 instruction, all row
+// blocks of a group in one launch (grid.y = block):
+// P[r][c] = sum_f Z[r][f] W'_i[f][c] for the rows r of block i.
+// W'_i comes as BF16 head and residual planes stored transposed,
+// Wt[p][c][f] (plane stride mp * s), and both planes are multiplied.
+// A lane loads 8 adjacent features of one row of Z and of one column of each
+// plane; a wave owns MT 16-row tiles, a workgroup 4 MT of them.
+// ---------------------------------------------------------------------------
+template <int NTC, int MT, int U>
+__global__ void __launch_bounds__(256)
+zw_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R, int i0, int64_t s,
+               const uint16_t* __restrict__ Wt, int64_t wt_stride, int64_t mp,
+               double* __restrict__ Pout) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int i = i0 + (int)blockIdx.y;
+  const int64_t gi = (int64_t)i * n / R, ni = (int64_t)(i + 1) * n / R - gi;
+  const int64_t zi = gi - (int64_t)i0 * n / R;   // first row of block i in Z
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * MT) + wave * (16 * MT);
+  if (row0 >= ni) return;
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const uint16_t* Wb = Wt + (int64_t)i * wt_stride;
+  const int64_t pstride = mp * s;
+
+  const uint16_t* zp[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+    zp[t] = Z + (zi + min(row0 + 16 * t + fr, ni - 1)) * ldz + 8 * fg;
+  const uint16_t* wp[NTC];
+#pragma unroll
+  for (int t = 0; t < NTC; ++t)
+    wp[t] = Wb + (int64_t)(min(nc0 + t, ntiles - 1) * 16 + fr) * s + 8 * fg;
+
+  v4f acc[MT][NTC];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[a][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t k0 = 0; k0 < s; k0 += 32 * U) {
+    u32x4 a[U][MT], b[U][NTC][2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+        a[u][t] = *reinterpret_cast<const u32x4*>(zp[t] + k0 + 32 * u);
+#pragma unroll
+      for (int t = 0; t < NTC; ++t) {
+        b[u][t][0] = *reinterpret_cast<const u32x4*>(wp[t] + k0 + 32 * u);
+        b[u][t][1] = *reinterpret_cast<const u32x4*>(wp[t] + pstride + k0 + 32 * u);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int t = 0; t < NTC; ++t)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          acc[m][t] = mfma_bf16x8(a[u][m], b[u][t][0], acc[m][t]);
+          acc[m][t] = mfma_bf16x8(a[u][m], b[u][t][1], acc[m][t]);
+        }
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const int nt = nc0 + t;
+      if (nt >= ntiles) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 16 * m + acc_row<float>(fg, r);
+        if (row < ni) Pout[(gi + row) * mp + nt * 16 + fr] = (double)acc[m][t][r];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transpose products from a BF16 Z for many output columns: the R planes of a
+// 16-row step (2 x NC columns x 32 B) are loaded once per workgroup into LDS
+// (row pitch 48 B: the 16 columns a fragment read touches fall in distinct
+// banks) and shared by its 4 waves of 64 features; the next step's R and each
+// wave's next Z block are loaded while the current step's products run.  A
+// lane transposes its 4-row x 4-feature block of Z as in ztr_bf16_kernel.
+// Same grid and output as ztr_bf16_kernel.
+// ---------------------------------------------------------------------------
+template <int NTC>
+__global__ void __launch_bounds__(256, 2)
+ztr_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
+                    const uint16_t* __restrict__ Rt, int64_t ldr, int64_t mp, int64_t split_rows,
+                    float* __restrict__ part) {
+  constexpr int NC = NTC * 16, PITCH = 48;
+  constexpr int SEGS = 2 * NC * 2;                 // 16-byte segments (8 rows) per step
+  constexpr int NSEG = (SEGS + 255) / 256;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2 * NC * PITCH];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t f0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int64_t sp = blockIdx.y;
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const int64_t rbeg = sp * split_rows;
+  const int64_t rend = min(rows, rbeg + split_rows);
+  const int64_t fl = min(f0 + 4 * fr, s - 4);      // waves past s load in bounds, store nothing
+  const int64_t pstride = mp * ldr;
+
+  // staged segment q = tid + 256 u: plane q / (2 NC), column (q / 2) % NC, half q % 2
+  const uint16_t* gsrc[NSEG];
+  int ldst[NSEG];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) {
+    const int q = min(tid + 256 * u, SEGS - 1);
+    const int p = q / (2 * NC), c = (q / 2) % NC, half = q % 2;
+    const int64_t col = min(nc0 * 16 + c, (int)mp - 1);
+    gsrc[u] = Rt + p * pstride + col * ldr + rbeg + half * 8;
+    ldst[u] = tid + 256 * u < SEGS ? (p * NC + c) * PITCH + half * 16 : -1;
+  }
+
+  v4f acc[4][NTC];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  // Z block of the step at row rb: rows rb + 4 fg + 0..3, features fl .. fl + 3
+  u32x2 zc[4], zn[4];
+  u32x4 stg[NSEG];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    zc[t] = *reinterpret_cast<const u32x2*>(Z + min(rbeg + 4 * fg + t, rows - 1) * ldz + fl);
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u]);
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u)
+    if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[0][ldst[u]]) = stg[u];
+  __syncthreads();
+  for (int64_t rb = rbeg; rb < rend; rb += 16) {
+    const int buf = (int)(((rb - rbeg) >> 4) & 1);
+    const bool more = rb + 16 < rend;
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        zn[t] = *reinterpret_cast<const u32x2*>(Z + min(rb + 16 + 4 * fg + t, rows - 1) * ldz + fl);
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u)
+        stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u] + (rb + 16 - rbeg));
+    }
+    u32x2 a[4];
+    a[0].x = __builtin_amdgcn_perm(zc[1].x, zc[0].x, 0x05040100u);
+    a[0].y = __builtin_amdgcn_perm(zc[3].x, zc[2].x, 0x05040100u);
+    a[1].x = __builtin_amdgcn_perm(zc[1].x, zc[0].x, 0x07060302u);
+    a[1].y = __builtin_amdgcn_perm(zc[3].x, zc[2].x, 0x07060302u);
+    a[2].x = __builtin_amdgcn_perm(zc[1].y, zc[0].y, 0x05040100u);
+    a[2].y = __builtin_amdgcn_perm(zc[3].y, zc[2].y, 0x05040100u);
+    a[3].x = __builtin_amdgcn_perm(zc[1].y, zc[0].y, 0x07060302u);
+    a[3].y = __builtin_amdgcn_perm(zc[3].y, zc[2].y, 0x07060302u);
+    const int roff = 8 * fg;                        // rows 4 fg .. 4 fg + 3, 2 bytes each
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const u32x2 bh = *reinterpret_cast<const u32x2*>(&lds[buf][(t * 16 + fr) * PITCH + roff]);
+      const u32x2 bl =
+          *reinterpret_cast<const u32x2*>(&lds[buf][(NC + t * 16 + fr) * PITCH + roff]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[q][t] = mfma_bf16x4(a[q], bh, acc[q][t]);
+        acc[q][t] = mfma_bf16x4(a[q], bl, acc[q][t]);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u)
+        if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[buf ^ 1][ldst[u]]) = stg[u];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) zc[t] = zn[t];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < NTC; ++t) {
+    const int nt = nc0 + t;
+    if (nt >= ntiles) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t f = f0 + 4 * acc_row<float>(fg, r) + q;
+        if (f < s) part[(sp * s + f) * mp + nt * 16 + fr] = acc[q][t][r];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward products from a BF16 Z for many output columns: the W' planes of a
+// 32-feature stage (2 x NC columns x 64 B) are loaded once per workgroup into
+// LDS (row pitch 80 B: the 16 columns a fragment read touches fall in
+// distinct banks) and shared by its 4 waves of 64 rows, so W' moves from L2
+// 1.25 times per byte of Z instead of 10 times.  The next stage's W' and
+// each wave's next Z fragments are loaded while the current stage's products
+// run.  Same grid and output as zw_bf16_kernel.
+// ---------------------------------------------------------------------------
+template <int NTC>
+__global__ void __launch_bounds__(256, 2)
+zw_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R, int i0,
+                   int64_t s, const uint16_t* __restrict__ Wt, int64_t wt_stride, int64_t mp,
+                   double* __restrict__ Pout) {
+  constexpr int MT = 4, NC = NTC * 16, PITCH = 80;
+  constexpr int SEGS = 2 * NC * 4;                 // 16-byte segments per stage
+  constexpr int NSEG = (SEGS + 255) / 256;         // per thread
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2 * NC * PITCH];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int i = i0 + (int)blockIdx.y;
+  const int64_t gi = (int64_t)i * n / R, ni = (int64_t)(i + 1) * n / R - gi;
+  const int64_t zi = gi - (int64_t)i0 * n / R;
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * MT) + wave * (16 * MT);
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const uint16_t* Wb = Wt + (int64_t)i * wt_stride;
+  const int64_t pstride = mp * s;
+
+  // staged segment q = tid + 256 u: plane q / (4 NC), column (q / 4) % NC, part q % 4
+  const uint16_t* gsrc[NSEG];
+  int ldst[NSEG];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) {
+    const int q = min(tid + 256 * u, SEGS - 1);
+    const int p = q / (4 * NC), c = (q / 4) % NC, part = q % 4;
+    const int64_t col = min(nc0 * 16 + c, (int)mp - 1);
+    gsrc[u] = Wb + p * pstride + col * s + part * 8;
+    ldst[u] = tid + 256 * u < SEGS ? (p * NC + c) * PITCH + part * 16 : -1;
+  }
+  const uint16_t* zp[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+    zp[t] = Z + (zi + min(row0 + 16 * t + fr, ni - 1)) * ldz + 8 * fg;
+
+  v4f acc[MT][NTC];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[a][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  u32x4 stg[NSEG], a_cur[MT], a_nxt[MT];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u]);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) a_cur[t] = *reinterpret_cast<const u32x4*>(zp[t]);
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u)
+    if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[0][ldst[u]]) = stg[u];
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < s; k0 += 32) {
+    const int buf = (int)((k0 >> 5) & 1);
+    const bool more = k0 + 32 < s;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u] + k0 + 32);
+#pragma unroll
+      for (int t = 0; t < MT; ++t) a_nxt[t] = *reinterpret_cast<const u32x4*>(zp[t] + k0 + 32);
+    }
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const u32x4 bh = *reinterpret_cast<const u32x4*>(&lds[buf][(t * 16 + fr) * PITCH + 16 * fg]);
+      const u32x4 bl =
+          *reinterpret_cast<const u32x4*>(&lds[buf][(NC + t * 16 + fr) * PITCH + 16 * fg]);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        acc[m][t] = mfma_bf16x8(a_cur[m], bh, acc[m][t]);
+        acc[m][t] = mfma_bf16x8(a_cur[m], bl, acc[m][t]);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u)
+        if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[buf ^ 1][ldst[u]]) = stg[u];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) a_cur[t] = a_nxt[t];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const int nt = nc0 + t;
+      if (nt >= ntiles) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 16 * m + acc_row<float>(fg, r);
+        if (row < ni) Pout[(gi + row) * mp + nt * 16 + fr] = (double)acc[m][t][r];
+      }
+    }
+}
+
 // Loads batched per wave before their MFMAs: more when each load feeds few
 // instructions (few output tiles), fewer when the tile count is large.
 template <int NTC> constexpr int ztr_unroll() { return NTC <= 2 ? 8 : 4; }
@@ -322,15 +718,56 @@ static void ztr_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, co
   }
 }
 
+template <int NTC>
+static void launch_ztr_bf16(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rt,
+                            int64_t ldr, int64_t mp, int64_t split_rows, void* part,
+                            hipStream_t st) {
+  constexpr int U = NTC <= 2 ? 4 : (NTC <= 6 ? 2 : 1);
+  const int ntiles = (int)(mp / 16);
+  const int64_t nsplit = (rows + split_rows - 1) / split_rows;
+  dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
+  ztr_bf16_kernel<NTC, U><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, s,
+                                             (const uint16_t*)Rt, ldr, mp, split_rows,
+                                             (float*)part);
+}
+
+template <int NTC>
+static void launch_ztr_bf16_lds(const void* Z, int64_t ldz, int64_t rows, int64_t s,
+                                const void* Rt, int64_t ldr, int64_t mp, int64_t split_rows,
+                                void* part, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  const int64_t nsplit = (rows + split_rows - 1) / split_rows;
+  dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
+  ztr_bf16_lds_kernel<NTC><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, s,
+                                              (const uint16_t*)Rt, ldr, mp, split_rows,
+                                              (float*)part);
+}
+
+// Up to two output tiles read R directly, more share it through LDS.
+static void ztr_bf16_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rt,
+                              int64_t ldr, int64_t mp, int64_t split_rows, void* part,
+                              hipStream_t st) {
+  const int nt = (int)(mp / 16);
+  if (nt == 1) launch_ztr_bf16<1>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt == 2) launch_ztr_bf16<2>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 4) launch_ztr_bf16_lds<4>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 6) launch_ztr_bf16_lds<6>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 8) launch_ztr_bf16_lds<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 10) launch_ztr_bf16_lds<10>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else launch_ztr_bf16_lds<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+}
+
 }  // namespace
 
 hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s,
-                       const void* Rop, int64_t mp, int64_t split_rows, void* part,
+                       const void* Rop, int64_t ldr, int64_t mp, int64_t split_rows, void* part,
                        hipStream_t st) {
   if (rows <= 0) return hipSuccess;
   if (prec == BS_PREC_F64) ztr_dispatch<double>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-  else if (prec == BS_PREC_BF16) ztr_dispatch<uint16_t>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-  else ztr_dispatch<float>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+  else if (prec == BS_PREC_BF16) {
+    if (split_rows % 32 != 0) return hipErrorInvalidValue;
+    ztr_bf16_dispatch(Z, ldz, rows, s, Rop, ldr, mp, split_rows, part, st);
+  } else ztr_dispatch<float>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
   return hipGetLastError();
 }
 
@@ -380,15 +817,72 @@ static void zw_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s16, c
   }
 }
 
+template <int NTC, int MT, int U>
+static void launch_zw_bf16(const void* Z, int64_t ldz, int64_t n, int R, int i0, int nblk,
+                           int64_t nmax, int64_t s, const void* Wt, int64_t wt_stride, int64_t mp,
+                           double* Pout, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  dim3 g((unsigned)((nmax + 64 * MT - 1) / (64 * MT)), (unsigned)nblk,
+         (unsigned)((ntiles + NTC - 1) / NTC));
+  zw_bf16_kernel<NTC, MT, U><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, n, R, i0, s,
+                                                (const uint16_t*)Wt, wt_stride, mp, Pout);
+}
+
+template <int NTC>
+static void launch_zw_bf16_lds(const void* Z, int64_t ldz, int64_t n, int R, int i0, int nblk,
+                               int64_t nmax, int64_t s, const void* Wt, int64_t wt_stride,
+                               int64_t mp, double* Pout, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  dim3 g((unsigned)((nmax + 255) / 256), (unsigned)nblk, (unsigned)((ntiles + NTC - 1) / NTC));
+  zw_bf16_lds_kernel<NTC><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, n, R, i0, s,
+                                             (const uint16_t*)Wt, wt_stride, mp, Pout);
+}
+
+// One pass over Z for up to 10 output tiles (passes of 8 beyond): up to two
+// tiles read W' directly, more share it through LDS.
+static void zw_bf16_dispatch(const void* Z, int64_t ldz, int64_t n, int R, int i0, int nblk,
+                             int64_t nmax, int64_t s, const void* Wt, int64_t wt_stride,
+                             int64_t mp, double* Pout, hipStream_t st) {
+  const int nt = (int)(mp / 16);
+#define BS_ZWB(NTC, MT, U) \
+  launch_zw_bf16<NTC, MT, U>(Z, ldz, n, R, i0, nblk, nmax, s, Wt, wt_stride, mp, Pout, st)
+#define BS_ZWL(NTC) \
+  launch_zw_bf16_lds<NTC>(Z, ldz, n, R, i0, nblk, nmax, s, Wt, wt_stride, mp, Pout, st)
+  if (nt == 1) BS_ZWB(1, 4, 2);
+  else if (nt == 2) BS_ZWB(2, 4, 2);
+  else if (nt <= 4) BS_ZWL(4);
+  else if (nt <= 6) BS_ZWL(6);
+  else if (nt <= 8) BS_ZWL(8);
+  else if (nt <= 10) BS_ZWL(10);
+  else BS_ZWL(8);
+#undef BS_ZWB
+#undef BS_ZWL
+}
+
 }  // namespace
 
-hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Wop,
-              int64_t mp, double* Pout, hipStream_t st) {
-  if (rows <= 0) return hipSuccess;
-  const int64_t s16 = (s + 63) / 64 * 64;  // multiple of the 4-step unroll (s is 64-aligned)
-  if (prec == BS_PREC_F64) zw_dispatch<double>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-  else if (prec == BS_PREC_BF16) zw_dispatch<uint16_t>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-  else zw_dispatch<float>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t n, int R, int i0, int i1, int64_t s,
+              const void* Wop, int64_t wop_stride, int64_t mp, double* Pout, hipStream_t st) {
+  if (i1 <= i0 || n <= 0) return hipSuccess;
+  if (s % 64 != 0) return hipErrorInvalidValue;
+  if (prec == BS_PREC_BF16) {
+    int64_t nmax = 0;
+    for (int i = i0; i < i1; ++i)
+      nmax = std::max<int64_t>(nmax, (int64_t)(i + 1) * n / R - (int64_t)i * n / R);
+    zw_bf16_dispatch(Z, ldz, n, R, i0, i1 - i0, nmax, s, Wop, wop_stride, mp, Pout, st);
+    return hipGetLastError();
+  }
+  const int64_t r0 = (int64_t)i0 * n / R;
+  const size_t eb = prec == BS_PREC_F64 ? 8 : 4;       // operand element bytes
+  const size_t zb = prec == BS_PREC_F64 ? 8 : 4;       // stored Z element bytes
+  for (int i = i0; i < i1; ++i) {
+    const int64_t gi = (int64_t)i * n / R, rows = (int64_t)(i + 1) * n / R - gi;
+    if (rows <= 0) continue;
+    const void* Zi = (const char*)Z + (size_t)(gi - r0) * ldz * zb;
+    const void* Wi = (const char*)Wop + (size_t)i * wop_stride * eb;
+    if (prec == BS_PREC_F64) zw_dispatch<double>(Zi, ldz, rows, s, Wi, mp, Pout + gi * mp, st);
+    else zw_dispatch<float>(Zi, ldz, rows, s, Wi, mp, Pout + gi * mp, st);
+  }
   return hipGetLastError();
 }
 
