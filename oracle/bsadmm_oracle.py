@@ -32,6 +32,10 @@ design notes of the repository):
 * The returned model is W-bar; predictions are Z(X_test) W-bar.
 * Multiclass hinge is one-vs-all: sum_k max(0, 1 - y_k o_k), y in {-1, +1}.
 * Squared loss is ||y - o||^2 without a 1/2 and r(W) = ||W||_F^2.
+* Penalty adaptation is not in the paper.  ``admm(..., adapt=...)`` follows
+  residual balancing (Boyd et al. 2011, section 3.4.1) with the primal and
+  dual residuals of ``residuals``; the scaled duals nu, mu, mu' are rescaled
+  when rho changes, and the cached factor needs no update (it has no rho).
 """
 
 from __future__ import annotations
@@ -47,7 +51,7 @@ __all__ = [
     "prox_squared", "prox_hinge", "prox_l2", "prox_loss", "loss_sum",
     "objective", "ridge_closed_form", "ridge_push_through",
     "graph_projection", "Problem", "weights", "admm", "admm_reference",
-    "paper_memory_floats", "predict",
+    "paper_memory_floats", "predict", "set_rho", "residuals", "balance_factor",
 ]
 
 
@@ -202,12 +206,14 @@ class Problem:
         return self.Y.shape[1]
 
 
-def weights(p: Problem):
-    """(tau, kappa): weights of the loss prox and the regulariser prox."""
+def weights(p: Problem, rho: float | None = None):
+    """(tau, kappa): weights of the loss prox and the regulariser prox at the
+    penalty ``rho`` (default: the problem's)."""
+    rho = p.rho if rho is None else rho
     if p.rho_convention == "per_example":
-        return 1.0 / p.rho, p.n * p.lam / p.rho
+        return 1.0 / rho, p.n * p.lam / rho
     if p.rho_convention == "literal":
-        return 1.0 / (p.n * p.rho), p.lam / p.rho
+        return 1.0 / (p.n * rho), p.lam / rho
     raise ValueError(p.rho_convention)
 
 
@@ -223,6 +229,55 @@ def _zero_state(p: Problem):
         "Wc": z(s, m), "Wbar": z(s, m), "mu": z(s, m),
         "Wp": z(R, s, m), "mup": z(R, s, m), "U": z(R, s, m),
     }
+
+
+# ---------------------------------------------------------------------------
+# Penalty adaptation (not in the paper; residual balancing of Boyd, Parikh,
+# Chu, Peleato and Eckstein, "Distributed Optimization and Statistical
+# Learning via the Alternating Direction Method of Multipliers", 2011,
+# section 3.4.1).  The cached factor (I + Z^T Z)^{-1} has no rho in it, so a
+# new penalty only rescales the scaled duals and the two prox weights.
+# ---------------------------------------------------------------------------
+
+DUALS = ("nu", "mu", "mup")
+
+
+def set_rho(state: dict, rho_new: float) -> dict:
+    """State with penalty rho_new: the scaled duals u = y / rho are rescaled
+    by rho_old / rho_new so that the unscaled duals y stay the same."""
+    rho_old = float(state["rho"])
+    out = {k: v.copy() for k, v in state.items()}
+    for k in DUALS:
+        out[k] = state[k] * (rho_old / rho_new)
+    out["rho"] = np.array(float(rho_new))
+    return out
+
+
+def residuals(p: Problem, state: dict, Obar_prev, Wbar_prev):
+    """(primal, dual) residual norms after an iteration.
+
+    Primal: the constraint violations the iteration leaves, i.e. the exchange
+    residual O_i - sum_j O'_ij (= Delta-bar) and the consensus residuals
+    W_j - W-bar_j and W'_ij - W-bar_j.  Dual: rho times the change of the
+    averaged variables, each counted once per copy that is averaged into it
+    (C + 1 for O-bar, R + 1 for W-bar).
+    """
+    r2 = (np.sum(state["Dbar"] ** 2) + np.sum((state["Wc"] - state["Wbar"]) ** 2)
+          + np.sum((state["Wp"] - state["Wbar"][None]) ** 2))
+    rho = float(state["rho"])
+    s2 = rho * rho * ((p.C + 1) * np.sum((state["Obar"] - Obar_prev) ** 2)
+                      + (p.R + 1) * np.sum((state["Wbar"] - Wbar_prev) ** 2))
+    return math.sqrt(r2), math.sqrt(s2)
+
+
+def balance_factor(r: float, s: float, mu: float, tau: float) -> float:
+    """Residual balancing: grow rho by tau when the primal residual exceeds
+    mu times the dual one, shrink it by tau in the opposite case."""
+    if r > mu * s:
+        return tau
+    if s > mu * r:
+        return 1.0 / tau
+    return 1.0
 
 
 # ---------------------------------------------------------------------------
@@ -259,20 +314,28 @@ class _BlockCache:
 
 
 def admm(p: Problem, iters: int, state=None, variant: str = "fixed",
-         regenerate: bool = False, cache: _BlockCache | None = None, callback=None):
+         regenerate: bool = False, cache: _BlockCache | None = None, callback=None,
+         adapt=None):
     """Run ``iters`` iterations of the reorganised block-splitting ADMM.
 
     Returns (state, cache).  ``state`` holds O, Obar, nu, Dbar (n x m), the
-    regulariser-prox output Wc, the consensus W-bar, mu (s x m) and the
-    per-row-block W' (local models), mu' and U (R x s x m).
+    regulariser-prox output Wc, the consensus W-bar, mu (s x m), the
+    per-row-block W' (local models), mu' and U (R x s x m), the current
+    penalty ``rho`` and the iteration count ``k``.
+
+    ``adapt = (every, mu, tau)`` balances the residuals: after iteration k
+    with k % every == 0 the penalty is multiplied by balance_factor(...)
+    and the duals rescaled (set_rho).
     """
-    tau, kappa = weights(p)
     st = _zero_state(p) if state is None else {k: v.copy() for k, v in state.items()}
+    st.setdefault("rho", np.array(float(p.rho)))
+    st.setdefault("k", np.array(0))
     cache = cache or _BlockCache(p, regenerate)
     rows, cols = cache.rows, cache.cols
     C, R = p.C, p.R
     Y = np.asarray(p.Y, dtype=np.float64)
     for it in range(iters):
+        tau, kappa = weights(p, float(st["rho"]))
         # step 4: loss prox on the row state
         O = prox_loss(p.loss, st["Obar"] - st["nu"], Y, tau)
         # step 6: regulariser prox on the consensus model
@@ -309,8 +372,15 @@ def admm(p: Problem, iters: int, state=None, variant: str = "fixed",
             raise ValueError(variant)
         # step 33
         nu = st["nu"] + O - Obar
+        prev = st
         st = {"O": O, "Obar": Obar, "nu": nu, "Dbar": Dbar, "Wc": Wc, "Wbar": Wbar_new,
-              "mu": mu, "Wp": Wp, "mup": mup, "U": U}
+              "mu": mu, "Wp": Wp, "mup": mup, "U": U, "rho": prev["rho"],
+              "k": np.array(int(prev["k"]) + 1)}
+        if adapt is not None and adapt[0] > 0 and int(st["k"]) % adapt[0] == 0:
+            r, sd = residuals(p, st, prev["Obar"], prev["Wbar"])
+            f = balance_factor(r, sd, adapt[1], adapt[2])
+            if f != 1.0:
+                st = set_rho(st, float(st["rho"]) * f)
         if callback is not None:
             callback(it + 1, st)
     return st, cache
