@@ -60,6 +60,10 @@ def recorded_traffic(workload, precision):
     return float(vals["traffic_bytes_per_launch"])
 
 
+# residual balancing of the serving solves: check every 10 iterations, mu = 5, tau = 2
+SERVING_ADAPT = (10, 5.0, 2.0)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -141,6 +145,8 @@ def main():
                     help="only run 4 device copies of 1 GiB (HBM counter calibration) and exit")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run after the step timing (0 = skip)")
+    ap.add_argument("--no-serving-compare", action="store_true",
+                    help="skip the second pass of the serving stream at a fixed penalty")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -234,10 +240,18 @@ def main():
     }
     if args.serving:
         from paper_1409_0940_amd.serving import serve_stream
-        log(f"serving stream: {args.serving} requests at 20/s")
-        summ, _ = serve_stream(args.serving)
-        out["serving"] = {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in summ.items()}
+
+        def fmt(summ):
+            return {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in summ.items()}
+        log(f"serving stream: {args.serving} requests at 20/s, penalty adaptation {SERVING_ADAPT}")
+        summ, _, jobs = serve_stream(args.serving, rho_adapt=SERVING_ADAPT)
+        out["serving"] = fmt(summ)
         log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms")
+        if not args.no_serving_compare:
+            # the same requests at the fixed penalty rho = 1
+            summ0, _, _ = serve_stream(args.serving, jobs=jobs)
+            out["serving_fixed_rho"] = fmt(summ0)
+            log(f"serving, fixed rho: p50 {summ0['p50_ms']:.1f} ms, p99 {summ0['p99_ms']:.1f} ms")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, X, Y, Wr, b)
     print(json.dumps(out), flush=True)

@@ -128,6 +128,20 @@ typedef struct bsadmm_problem {
   size_t hbm_budget_bytes;  /* 0 = no limit; else setup fails with ENOMEM
                                when the footprint exceeds it                */
   size_t workspace_bytes;   /* cap on the Z workspace; 0 = automatic        */
+  /* Penalty adaptation (not in the paper): residual balancing of Boyd,
+   * Parikh, Chu, Peleato and Eckstein (2011), section 3.4.1.  After every
+   * rho_adapt_every-th iteration (counted over the handle's life; 0 = fixed
+   * rho) the primal residual r (exchange residual Delta-bar and consensus
+   * residuals W - W-bar, W'_i - W-bar) and the dual residual
+   * s = rho sqrt((C+1) ||O-bar - O-bar_prev||^2 + (R+1) ||W-bar - W-bar_prev||^2)
+   * are compared: rho is multiplied by tau when r > mu s and divided by tau
+   * when s > mu r, and the scaled duals nu, mu, mu' are divided by the same
+   * factor.  The cached factors do not depend on rho.  The check and the
+   * decision run on the device, stream-ordered: no host synchronisation.  */
+  int32_t rho_adapt_every;  /* >= 0                                         */
+  int32_t reserved0;        /* 0                                            */
+  double rho_adapt_mu;      /* > 1; 0 selects 10                            */
+  double rho_adapt_tau;     /* > 1; 0 selects 2                             */
 } bsadmm_problem;
 
 /* Phases timed with HIP events on the handle's stream (bsadmm_stats). */
@@ -149,6 +163,10 @@ typedef struct bsadmm_stats {
                                iteration)                                  */
   double phase_ms[BSADMM_PH_COUNT];  /* out: summed over the call          */
   double iterate_ms;        /* out: whole call, HIP events                 */
+  double rho;               /* out: penalty after the call                 */
+  int32_t rho_changes;      /* out: penalty changes by adaptation over the
+                               handle's life                               */
+  int32_t reserved1;
 } bsadmm_stats;
 
 typedef struct bsadmm_handle bsadmm_handle;
@@ -171,7 +189,9 @@ BSADMM_API int rff_map(const float* X, int64_t n, int64_t d, const float* W, con
  * bsadmm_validate -- host-only argument checks of a problem (no HIP call,
  * no device access): n >= R >= 1, s >= C >= 1, d >= 1, 1 <= m <= 1024,
  * m == 1 for HINGE, lambda >= 0, rho > 0, sigma > 0, known enums, non-null
- * X, Y, W, b, and 16-byte alignment of X, Y, W, b.  Returns OK or EINVAL.
+ * X, Y, W, b, 16-byte alignment of X, Y, W, b, rho_adapt_every >= 0 and
+ * rho_adapt_mu, rho_adapt_tau either 0 or finite and > 1.  Returns OK or
+ * EINVAL.
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_validate(const bsadmm_problem* p);
 
@@ -200,7 +220,9 @@ BSADMM_API int bsadmm_setup(const bsadmm_problem* p, bsadmm_handle** out);
  * graph-projection right-hand side of eq. gpWij (it includes Z_ij^T nu_i)
  * and the dual updates of mu, mu' made with the new consensus W-bar, as in
  * the block-splitting update equations.  Enqueued on the handle's stream;
- * if st != NULL the call synchronises and fills st.
+ * if st != NULL the call synchronises and fills st.  With
+ * rho_adapt_every > 0 the penalty is balanced after every K-th iteration
+ * (see bsadmm_problem), on the device.
  * Errors: EINVAL (iters < 0, null handle), ESTATE, EDEVICE.
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_iterate(bsadmm_handle* h, int32_t iters, bsadmm_stats* st);
@@ -232,16 +254,19 @@ enum {
   BSADMM_ST_WP = 7,    /* R x s x m local models W'                         */
   BSADMM_ST_MUP = 8,   /* R x s x m mu'                                     */
   BSADMM_ST_U = 9,     /* R x s x m U = Z_ij^T Z_ij W'_ij                   */
-  BSADMM_ST_COUNT = 10
+  BSADMM_ST_META = 10, /* 2       penalty rho and iterations done (importing
+                                  them sets both; duals are not rescaled)   */
+  BSADMM_ST_COUNT = 11
 };
 
 /* ----------------------------------------------------------------------
  * bsadmm_state_size -- number of doubles of state array `which`.
  * bsadmm_export_state / bsadmm_import_state -- copy one state array to /
  * from a caller-owned device buffer (checkpoint and resume: exporting all
- * BSADMM_ST_COUNT arrays and the iteration count and importing them into a
- * handle set up from the same inputs continues the run exactly).  Both
- * synchronise.  Errors: EINVAL (bad `which`, null pointer), ESTATE.
+ * BSADMM_ST_COUNT arrays, META included, and importing them into a handle
+ * set up from the same inputs continues the run exactly, also under penalty
+ * adaptation).  Both synchronise.  Errors: EINVAL (bad `which`, null
+ * pointer, an imported META with rho <= 0 or a negative count), ESTATE.
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_state_size(const bsadmm_handle* h, int32_t which, int64_t* count);
 BSADMM_API int bsadmm_export_state(const bsadmm_handle* h, int32_t which, double* dst);
@@ -273,6 +298,18 @@ BSADMM_API int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* 
  * Errors: EINVAL (null argument), ESTATE, EDEVICE.
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_monitor(bsadmm_handle* h, double* out);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_set_rho -- change the ADMM penalty to rho (> 0, finite) for the
+ * following iterations.  The loss-prox weight becomes 1/rho and the
+ * regulariser weight n lambda / rho; with rescale_duals != 0 the scaled
+ * duals nu, mu, mu' are multiplied by rho_old / rho, which keeps the
+ * unscaled duals and hence the fixed point (the usual penalty update);
+ * with 0 they are left as they are.  The factor cache is unchanged: it has
+ * no rho.  Enqueued on the handle's stream.
+ * Errors: EINVAL (null handle, rho <= 0 or not finite), ESTATE, EDEVICE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_set_rho(bsadmm_handle* h, double rho, int32_t rescale_duals);
 
 /* bsadmm_destroy -- free everything the handle owns.  NULL is allowed. */
 BSADMM_API int bsadmm_destroy(bsadmm_handle* h);

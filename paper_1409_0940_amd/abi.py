@@ -20,13 +20,13 @@ Z_MODE = {"auto": 0, "store": 1, "keep": 2}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTPD", 5: "ENONFINITE",
           6: "ESTATE", 7: "ENOTIMPL"}
 STATE = {"O": 0, "Obar": 1, "nu": 2, "Dbar": 3, "Wc": 4, "Wbar": 5, "mu": 6, "Wp": 7,
-         "mup": 8, "U": 9}
+         "mup": 8, "U": 9, "meta": 10}
 PHASES = ["regen", "ztr", "solve", "zw", "row", "col"]
 
 EXPORTED = ["rff_map", "bsadmm_validate", "bsadmm_footprint", "bsadmm_setup", "bsadmm_iterate",
             "bsadmm_predict", "bsadmm_get_coef", "bsadmm_state_size", "bsadmm_export_state",
-            "bsadmm_import_state", "bsadmm_objective", "bsadmm_monitor", "bsadmm_destroy",
-            "bsadmm_last_error"]
+            "bsadmm_import_state", "bsadmm_objective", "bsadmm_monitor", "bsadmm_set_rho",
+            "bsadmm_destroy", "bsadmm_last_error"]
 
 
 class BsadmmProblem(ctypes.Structure):
@@ -38,6 +38,8 @@ class BsadmmProblem(ctypes.Structure):
         ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("W", ctypes.c_void_p),
         ("b", ctypes.c_void_p), ("stream", ctypes.c_void_p),
         ("hbm_budget_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+        ("rho_adapt_every", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("rho_adapt_mu", ctypes.c_double), ("rho_adapt_tau", ctypes.c_double),
     ]
 
 
@@ -45,6 +47,7 @@ class BsadmmStats(ctypes.Structure):
     _fields_ = [
         ("iters_done", ctypes.c_int64), ("timed", ctypes.c_int32), ("launches", ctypes.c_int32),
         ("phase_ms", ctypes.c_double * 8), ("iterate_ms", ctypes.c_double),
+        ("rho", ctypes.c_double), ("rho_changes", ctypes.c_int32), ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -79,6 +82,7 @@ def lib():
         L.bsadmm_import_state.argtypes = [vp, i32, vp]
         L.bsadmm_objective.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.bsadmm_monitor.argtypes = [vp, vp]
+        L.bsadmm_set_rho.argtypes = [vp, ctypes.c_double, i32]
         L.bsadmm_destroy.argtypes = [vp]
         L.bsadmm_last_error.argtypes = []
         L.bsadmm_last_error.restype = ctypes.c_char_p
@@ -141,7 +145,9 @@ def rff_map(X, W, b, precision="fp32", out=None, stream=None):
 
 
 def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
-                 stream=None, hbm_budget_bytes=0, workspace_bytes=0, check=True, z_mode="auto"):
+                 stream=None, hbm_budget_bytes=0, workspace_bytes=0, check=True, z_mode="auto",
+                 rho_adapt=None):
+    """bsadmm_problem for device tensors; rho_adapt = (every, mu, tau) or None."""
     n, d = X.shape
     m = Y.shape[1]
     s = W.shape[1]
@@ -162,6 +168,8 @@ def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="f
     p.stream = _stream(stream).value if check else None
     p.hbm_budget_bytes = hbm_budget_bytes
     p.workspace_bytes = workspace_bytes
+    if rho_adapt is not None:
+        p.rho_adapt_every, p.rho_adapt_mu, p.rho_adapt_tau = rho_adapt
     return p
 
 
@@ -186,7 +194,8 @@ def bsadmm_iterate(h, iters, timed=False):
     st.timed = 1 if timed else 0
     _check("bsadmm_iterate", lib().bsadmm_iterate(h, iters, ctypes.byref(st)))
     return {"iters_done": st.iters_done, "launches": st.launches, "iterate_ms": st.iterate_ms,
-            "phase_ms": {k: st.phase_ms[i] for i, k in enumerate(PHASES)}}
+            "phase_ms": {k: st.phase_ms[i] for i, k in enumerate(PHASES)},
+            "rho": st.rho, "rho_changes": st.rho_changes}
 
 
 def bsadmm_iterate_async(h, iters):
@@ -235,6 +244,10 @@ def bsadmm_monitor(h, out):
     """Enqueue the convergence reductions into out (4 float64 on the device)."""
     _check("bsadmm_monitor", lib().bsadmm_monitor(h, _ptr(out)))
     return out
+
+
+def bsadmm_set_rho(h, rho, rescale_duals=True):
+    _check("bsadmm_set_rho", lib().bsadmm_set_rho(h, float(rho), 1 if rescale_duals else 0))
 
 
 def bsadmm_destroy(h):

@@ -59,12 +59,12 @@ struct Plan {
   int planes = 1;
   // byte counts
   size_t b_xp = 0, b_wt = 0, b_bias = 0, b_q = 0, b_ws = 0, b_row = 0, b_rop = 0, b_col = 0,
-         b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0;
+         b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0, b_prev = 0;
   // operand elements between the W' copies of consecutive row blocks
   int64_t wop_stride() const { return prec == BSADMM_BF16 ? 2 * mp * spad : spad * mp; }
   size_t total() const {
     return b_xp + b_wt + b_bias + b_q + b_ws + 5 * b_row + b_rop + 3 * b_col + 4 * b_colR + b_wop +
-           b_part + b_small + b_fac_tmp;
+           b_part + b_small + b_fac_tmp + b_prev;
   }
 };
 
@@ -86,6 +86,11 @@ int validate(const bsadmm_problem* p) {
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(BSADMM_EINVAL, "need lambda >= 0");
   if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return fail(BSADMM_EINVAL, "need rho > 0");
   if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) return fail(BSADMM_EINVAL, "need sigma > 0");
+  if (p->rho_adapt_every < 0) return fail(BSADMM_EINVAL, "need rho_adapt_every >= 0");
+  if (p->rho_adapt_mu != 0.0 && !(p->rho_adapt_mu > 1.0 && std::isfinite(p->rho_adapt_mu)))
+    return fail(BSADMM_EINVAL, "rho_adapt_mu must be 0 or finite and > 1");
+  if (p->rho_adapt_tau != 0.0 && !(p->rho_adapt_tau > 1.0 && std::isfinite(p->rho_adapt_tau)))
+    return fail(BSADMM_EINVAL, "rho_adapt_tau must be 0 or finite and > 1");
   if (!p->X || !p->Y || !p->W || !p->b) return fail(BSADMM_EINVAL, "X, Y, W, b must be non-NULL");
   const void* ptrs[4] = {p->X, p->Y, p->W, p->b};
   for (const void* q : ptrs)
@@ -157,7 +162,9 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.b_colR = (size_t)L.R * L.spad * L.mp * 8;
   L.b_wop = (size_t)L.R * L.spad * L.mp * L.vb;
   L.b_part = (size_t)L.R * L.nsplit_max * L.spad * L.mp * L.vb;
-  L.b_small = 256 + 2 * (size_t)L.C * 8 + 4 * kMonBlocks * 8;
+  L.b_small = 256 + 2 * (size_t)L.C * 8 + 6 * kMonBlocks * 8 + bs::BS_W_COUNT * 8;
+  // previous O-bar and W-bar for the dual residual of penalty adaptation
+  L.b_prev = p->rho_adapt_every > 0 ? L.b_row + L.b_col : 0;
   L.b_fac_tmp = (size_t)L.fac_batch * (slot + (size_t)L.S * 64 * 8);
   return BSADMM_OK;
 }
@@ -168,7 +175,9 @@ struct bsadmm_handle {
   Plan L;
   bsadmm_problem p{};
   hipStream_t st = nullptr;
-  double tau = 0, kappa = 0, scale = 0;
+  double scale = 0;
+  double* wts = nullptr;  // device penalty block (bs::BS_W_*)
+  double *Obar_prev = nullptr, *Wbar_prev = nullptr;
   std::vector<void*> allocs;
   void *Xp = nullptr, *Wt = nullptr, *bias = nullptr, *Z = nullptr, *Rop = nullptr,
        *Wop = nullptr, *part = nullptr;
@@ -249,6 +258,24 @@ struct PhaseTimer {
   }
 };
 
+// Multiply the scaled duals nu, mu, mu' by the device factor wts[BS_W_DUAL].
+hipError_t rescale_duals(bsadmm_handle* h) {
+  const Plan& L = h->L;
+  const double* f = h->wts + bs::BS_W_DUAL;
+  hipError_t e = bs::scale(h->nu, L.n * L.mp, f, h->st);
+  if (e == hipSuccess) e = bs::scale(h->mu, L.spad * L.mp, f, h->st);
+  if (e == hipSuccess) e = bs::scale(h->mup, (int64_t)L.R * L.spad * L.mp, f, h->st);
+  return e;
+}
+
+// New penalty (stream-ordered); with rescale the scaled duals are multiplied
+// by rho_old / rho.
+hipError_t apply_rho(bsadmm_handle* h, double rho, bool rescale) {
+  hipError_t e = bs::set_rho(h->wts, rho, (double)h->L.n * h->p.lambda, rescale ? 1 : 0, h->st);
+  if (e == hipSuccess && rescale) e = rescale_duals(h);
+  return e;
+}
+
 int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
   const Plan& L = h->L;
   PhaseTimer tm{h, st && st->timed != 0};
@@ -260,13 +287,21 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
   }
   int launches = 0;
   const double cfac = 1.0 / (double)(L.C + 1);
+  const int every = h->p.rho_adapt_every;
+  const double amu = h->p.rho_adapt_mu > 0.0 ? h->p.rho_adapt_mu : 10.0;
+  const double atau = h->p.rho_adapt_tau > 0.0 ? h->p.rho_adapt_tau : 2.0;
   for (int it = 0; it < iters; ++it) {
+    const bool check = every > 0 && (h->iters + it + 1) % every == 0;
+    if (check) {  // O-bar and W-bar before this iteration, for the dual residual
+      HCHK(hipMemcpyAsync(h->Obar_prev, h->Obar, L.b_row, hipMemcpyDeviceToDevice, h->st));
+      HCHK(hipMemcpyAsync(h->Wbar_prev, h->Wbar, L.b_col, hipMemcpyDeviceToDevice, h->st));
+    }
     tm.begin();
-    HCHK(bs::row_pre(L.prec, h->p.loss == BSADMM_SQUARED ? 0 : 1, h->tau, cfac, L.n, L.R, L.m,
+    HCHK(bs::row_pre(L.prec, h->p.loss == BSADMM_SQUARED ? 0 : 1, h->wts, cfac, L.n, L.R, L.m,
                      L.mp, L.nbpad, h->p.Y, h->Obar, h->nu, h->Dbar, h->O, h->Rop, h->st));
     tm.end(BSADMM_PH_ROW);
     tm.begin();
-    HCHK(bs::col_pre(h->kappa, L.spad, L.m, L.mp, h->Wbar, h->mu, h->Wc, h->st));
+    HCHK(bs::col_pre(h->wts, L.spad, L.m, L.mp, h->Wbar, h->mu, h->Wc, h->st));
     tm.end(BSADMM_PH_COL);
     for (const auto& g : L.groups) {
       const int i0 = g.first, i1 = g.second;
@@ -306,6 +341,13 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
     tm.begin();
     HCHK(bs::col_post(L.R, L.spad, L.m, L.mp, h->Wc, h->Wp, h->Wbar, h->mu, h->mup, h->st));
     tm.end(BSADMM_PH_COL);
+    if (check) {  // residual balancing, decided on the device (no read-back)
+      double* sums = h->mon_part + 5 * kMonBlocks;
+      HCHK(bs::residuals(h->Dbar, h->Wc, h->Wp, h->Wbar, h->Obar, h->Obar_prev, h->Wbar_prev, L.R,
+                         L.n, L.spad, L.m, L.mp, h->mon_part, kMonBlocks, sums, h->st));
+      HCHK(bs::adapt(sums, h->wts, L.R, L.C, (double)L.n * h->p.lambda, amu, atau, h->st));
+      HCHK(rescale_duals(h));
+    }
   }
   h->iters += iters;
   if (st) {
@@ -321,6 +363,10 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
     if (all0 && all1) HCHK(hipEventElapsedTime(&all, all0, all1));
     st->iterate_ms = all;
     st->launches = launches;
+    double w[bs::BS_W_COUNT];
+    HCHK(hipMemcpy(w, h->wts, sizeof w, hipMemcpyDeviceToHost));
+    st->rho = w[bs::BS_W_RHO];
+    st->rho_changes = (int32_t)w[bs::BS_W_CHANGES];
     st->iters_done = h->iters;
   }
   return BSADMM_OK;
@@ -331,9 +377,7 @@ int do_setup(bsadmm_handle* h) {
   const bsadmm_problem& p = h->p;
   h->st = (hipStream_t)p.stream;
   h->scale = std::sqrt(2.0 / (double)L.s);
-  // n F(W) scaling of the penalty: loss prox weight 1/rho, regulariser n lambda / rho
-  h->tau = 1.0 / p.rho;
-  h->kappa = (double)L.n * p.lambda / p.rho;
+
   void* tmp = nullptr;
 #define ALLOC(ptr, bytes)                                                         \
   do {                                                                            \
@@ -360,15 +404,23 @@ int do_setup(bsadmm_handle* h) {
   ALLOC(h->rhs, L.b_colR);
   ALLOC(h->Wop, L.b_wop);
   ALLOC(h->part, L.b_part);
+  if (L.b_prev) {
+    ALLOC(h->Obar_prev, L.b_row);
+    ALLOC(h->Wbar_prev, L.b_col);
+  }
   ALLOC(tmp, L.b_small);
   h->dflag = (int*)tmp;
   h->d_coff = (int64_t*)((char*)tmp + 256);
   h->d_sj = h->d_coff + L.C;
   h->mon_part = (double*)(h->d_sj + L.C);
+  h->wts = h->mon_part + 6 * kMonBlocks;
   hipStream_t st = h->st;
   HCHK(hipMemcpyAsync(h->d_coff, L.coff.data(), L.C * 8, hipMemcpyHostToDevice, st));
   HCHK(hipMemcpyAsync(h->d_sj, L.sj.data(), L.C * 8, hipMemcpyHostToDevice, st));
   HCHK(hipMemsetAsync(h->dflag, 0, 256, st));
+  HCHK(hipMemsetAsync(h->wts, 0, bs::BS_W_COUNT * 8, st));
+  // n F(W) scaling of the penalty: loss prox weight 1/rho, regulariser n lambda / rho
+  HCHK(apply_rho(h, p.rho, false));
   for (void* z : {(void*)h->O, (void*)h->Obar, (void*)h->nu, (void*)h->Dbar, (void*)h->P})
     HCHK(hipMemsetAsync(z, 0, L.b_row, st));
   HCHK(hipMemsetAsync(h->Rop, 0, L.b_rop, st));
@@ -436,7 +488,7 @@ int do_setup(bsadmm_handle* h) {
 // per-row-block column-side (R x s).
 struct StateRef {
   double* ptr;
-  int kind;  // 0: n x m, 1: s x m, 2: R x s x m
+  int kind;  // 0: n x m, 1: s x m, 2: R x s x m, 3: {rho, iterations} on the host
 };
 
 StateRef state_ref(const bsadmm_handle* h, int which) {
@@ -451,6 +503,7 @@ StateRef state_ref(const bsadmm_handle* h, int which) {
     case BSADMM_ST_WP: return {h->Wp, 2};
     case BSADMM_ST_MUP: return {h->mup, 2};
     case BSADMM_ST_U: return {h->U, 2};
+    case BSADMM_ST_META: return {h->wts, 3};
     default: return {nullptr, -1};
   }
 }
@@ -460,6 +513,25 @@ int copy_state(const bsadmm_handle* h, int which, double* dense, bool to_dense) 
   StateRef s = state_ref(h, which);
   if (!s.ptr) return fail(BSADMM_EINVAL, "unknown state array");
   hipStream_t st = h->st;
+  if (s.kind == 3) {  // {rho, iterations}: small synchronous copies
+    double meta[2];
+    HCHK(hipStreamSynchronize(st));
+    if (to_dense) {
+      HCHK(hipMemcpy(meta, h->wts + bs::BS_W_RHO, 8, hipMemcpyDeviceToHost));
+      meta[1] = (double)h->iters;
+      HCHK(hipMemcpy(dense, meta, sizeof meta, hipMemcpyHostToDevice));
+      return BSADMM_OK;
+    }
+    HCHK(hipMemcpy(meta, dense, sizeof meta, hipMemcpyDeviceToHost));
+    if (!(meta[0] > 0.0) || !std::isfinite(meta[0]) || !(meta[1] >= 0.0) ||
+        meta[1] != std::floor(meta[1]))
+      return fail(BSADMM_EINVAL, "META needs rho > 0 and a whole iteration count >= 0");
+    bsadmm_handle* hm = const_cast<bsadmm_handle*>(h);
+    HCHK(apply_rho(hm, meta[0], false));
+    HCHK(hipStreamSynchronize(st));
+    hm->iters = (int64_t)meta[1];
+    return BSADMM_OK;
+  }
   auto mv = [&](double* padded, int64_t rows, double* dn) -> hipError_t {
     return to_dense ? bs::unpad(padded, rows, L.m, L.mp, dn, st)
                     : bs::pad(dn, rows, L.m, L.mp, padded, st);
@@ -538,6 +610,19 @@ int bsadmm_iterate(bsadmm_handle* h, int32_t iters, bsadmm_stats* st) {
   return rc;
 }
 
+int bsadmm_set_rho(bsadmm_handle* h, double rho, int32_t rescale_duals) {
+  g_err.clear();
+  if (!h) return fail(BSADMM_EINVAL, "handle is NULL");
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(BSADMM_EINVAL, "need rho > 0 and finite");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  hipError_t e = apply_rho(h, rho, rescale_duals != 0);
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "set_rho");
+  }
+  return BSADMM_OK;
+}
+
 int bsadmm_get_coef(const bsadmm_handle* h, double* Wbar) {
   g_err.clear();
   if (!h || !Wbar) return fail(BSADMM_EINVAL, "NULL argument");
@@ -551,7 +636,8 @@ int bsadmm_state_size(const bsadmm_handle* h, int32_t which, int64_t* count) {
   StateRef s = state_ref(h, which);
   if (!s.ptr) return fail(BSADMM_EINVAL, "unknown state array");
   const Plan& L = h->L;
-  *count = s.kind == 0 ? L.n * L.m : (s.kind == 1 ? L.s * L.m : (int64_t)L.R * L.s * L.m);
+  *count = s.kind == 0 ? L.n * L.m
+                       : (s.kind == 1 ? L.s * L.m : (s.kind == 2 ? (int64_t)L.R * L.s * L.m : 2));
   return BSADMM_OK;
 }
 

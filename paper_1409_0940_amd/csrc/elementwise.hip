@@ -38,10 +38,12 @@ __device__ __forceinline__ double prox_loss(int loss, double v, double y, double
 }
 
 template <typename OP>
-__global__ void row_pre_kernel(int loss, double tau, double cfac, int64_t n, int64_t m, int64_t mp,
+__global__ void row_pre_kernel(int loss, const double* __restrict__ wts, double cfac, int64_t n,
+                               int64_t m, int64_t mp,
                                const float* __restrict__ Y, const double* __restrict__ Obar,
                                const double* __restrict__ nu, const double* __restrict__ Dbar,
                                double* __restrict__ O, OP* __restrict__ Rop) {
+  const double tau = wts[BS_W_TAU];
   GRID_STRIDE(e, n * m) {
     const int64_t r = e / m, c = e - r * m;
     const int64_t o = r * mp + c;
@@ -53,11 +55,13 @@ __global__ void row_pre_kernel(int loss, double tau, double cfac, int64_t n, int
 
 // BF16 products: R as BF16 head and residual planes stored transposed,
 // Rt[plane][c][i * nbpad + (r - first row of block i)].
-__global__ void row_pre_bf16_kernel(int loss, double tau, double cfac, int64_t n, int R,
+__global__ void row_pre_bf16_kernel(int loss, const double* __restrict__ wts, double cfac,
+                                    int64_t n, int R,
                                     int64_t m, int64_t mp, int64_t nbpad,
                                     const float* __restrict__ Y, const double* __restrict__ Obar,
                                     const double* __restrict__ nu, const double* __restrict__ Dbar,
                                     double* __restrict__ O, uint16_t* __restrict__ Rt) {
+  const double tau = wts[BS_W_TAU];
   const int64_t ldr = (int64_t)R * nbpad;
   GRID_STRIDE(e, n * m) {
     const int64_t r = e / m, c = e - r * m;
@@ -91,10 +95,10 @@ __global__ void row_post_kernel(int64_t n, int64_t m, int64_t mp, double a, doub
   }
 }
 
-__global__ void col_pre_kernel(double kappa, int64_t rows, int64_t m, int64_t mp,
+__global__ void col_pre_kernel(const double* __restrict__ wts, int64_t rows, int64_t m, int64_t mp,
                                const double* __restrict__ Wbar, const double* __restrict__ mu,
                                double* __restrict__ Wc) {
-  const double den = 1.0 / (1.0 + 2.0 * kappa);
+  const double den = 1.0 / (1.0 + 2.0 * wts[BS_W_KAPPA]);
   GRID_STRIDE(e, rows * m) {
     const int64_t r = e / m, c = e - r * m;
     const int64_t o = r * mp + c;
@@ -216,7 +220,45 @@ __global__ void diffsq_partial_kernel(const double* __restrict__ Wp, const doubl
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// out[q] = scale[q] * sum_k part[q * nb + k], one workgroup per quantity.
+__global__ void scale_kernel(double* __restrict__ a, int64_t count, const double* __restrict__ f) {
+  const double v = *f;
+  if (v == 1.0) return;
+  GRID_STRIDE(e, count) a[e] *= v;
+}
+
+// Residual balancing step on the device (one thread): compares the primal
+// residual sqrt(q0 + q1 + q2) with the dual one rho sqrt((C+1) q3 + (R+1) q4)
+// and updates the penalty block; wts[BS_W_DUAL] gets the factor the scaled
+// duals must be multiplied by (1 when rho stays).
+__global__ void adapt_kernel(const double* __restrict__ q, double* __restrict__ wts, int R, int C,
+                             double n_lambda, double mu, double tau_f) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double rho = wts[BS_W_RHO];
+  const double r = sqrt(q[0] + q[1] + q[2]);
+  const double sd = rho * sqrt((double)(C + 1) * q[3] + (double)(R + 1) * q[4]);
+  const double f = r > mu * sd ? tau_f : (sd > mu * r ? 1.0 / tau_f : 1.0);
+  wts[BS_W_DUAL] = 1.0 / f;
+  if (f != 1.0) {
+    const double nr = rho * f;
+    wts[BS_W_RHO] = nr;
+    wts[BS_W_TAU] = 1.0 / nr;
+    wts[BS_W_KAPPA] = n_lambda / nr;
+    wts[BS_W_CHANGES] += 1.0;
+  }
+}
+
+// Penalty set from the host: rho, the two prox weights and the dual factor
+// rho_old / rho (or 1 without rescaling).
+__global__ void set_rho_kernel(double* __restrict__ wts, double rho, double n_lambda, int rescale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  wts[BS_W_DUAL] = rescale ? wts[BS_W_RHO] / rho : 1.0;
+  wts[BS_W_RHO] = rho;
+  wts[BS_W_TAU] = 1.0 / rho;
+  wts[BS_W_KAPPA] = n_lambda / rho;
+}
+
+// out[q] = scale[q] * sum_k part[q * nb + k], one workgroup per quantity
+// (quantities past the fourth take the fourth scale).
 __global__ void final_reduce_kernel(const double* __restrict__ part, int nb, double s0, double s1,
                                     double s2, double s3, double* __restrict__ out) {
   __shared__ double red[256];
@@ -241,6 +283,36 @@ hipError_t monitor(int loss, const double* P, const float* Y, const double* Wp,
   return hipGetLastError();
 }
 
+hipError_t residuals(const double* Dbar, const double* Wc, const double* Wp, const double* Wbar,
+                     const double* Obar, const double* Obar_prev, const double* Wbar_prev, int R,
+                     int64_t n, int64_t spad, int64_t m, int64_t mp, double* part, int nb,
+                     double* out, hipStream_t st) {
+  sumsq_partial_kernel<<<nb, 256, 0, st>>>(Dbar, n * mp, part);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Wc, Wbar, 1, spad, m, mp, part + nb);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Wp, Wbar, R, spad, m, mp, part + 2 * nb);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Obar, Obar_prev, 1, n, m, mp, part + 3 * nb);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Wbar, Wbar_prev, 1, spad, m, mp, part + 4 * nb);
+  final_reduce_kernel<<<5, 256, 0, st>>>(part, nb, 1.0, 1.0, 1.0, 1.0, out);
+  return hipGetLastError();
+}
+
+hipError_t scale(double* a, int64_t count, const double* f, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  scale_kernel<<<grid_for(count), 256, 0, st>>>(a, count, f);
+  return hipGetLastError();
+}
+
+hipError_t adapt(const double* sums, double* wts, int R, int C, double n_lambda, double mu,
+                 double tau_f, hipStream_t st) {
+  adapt_kernel<<<1, 64, 0, st>>>(sums, wts, R, C, n_lambda, mu, tau_f);
+  return hipGetLastError();
+}
+
+hipError_t set_rho(double* wts, double rho, double n_lambda, int rescale, hipStream_t st) {
+  set_rho_kernel<<<1, 64, 0, st>>>(wts, rho, n_lambda, rescale);
+  return hipGetLastError();
+}
+
 hipError_t loss_partial(int loss, const double* P, const float* Y, int64_t n, int64_t m,
                         int64_t mp, double* part, int nblocks, hipStream_t st) {
   loss_partial_kernel<<<nblocks, 256, 0, st>>>(loss, P, Y, n, m, mp, part);
@@ -253,18 +325,18 @@ hipError_t sumsq_partial(const double* a, int64_t count, double* part, int nbloc
   return hipGetLastError();
 }
 
-hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int R, int64_t m,
+hipError_t row_pre(int prec, int loss, const double* wts, double cfac, int64_t n, int R, int64_t m,
                    int64_t mp, int64_t nbpad, const float* Y, const double* Obar, const double* nu,
                    const double* Dbar, double* O, void* Rop, hipStream_t st) {
   unsigned g = grid_for(n * m);
   if (prec == BS_PREC_BF16)
-    row_pre_bf16_kernel<<<g, 256, 0, st>>>(loss, tau, cfac, n, R, m, mp, nbpad, Y, Obar, nu, Dbar,
+    row_pre_bf16_kernel<<<g, 256, 0, st>>>(loss, wts, cfac, n, R, m, mp, nbpad, Y, Obar, nu, Dbar,
                                            O, (uint16_t*)Rop);
   else if (prec == BS_PREC_F64)
-    row_pre_kernel<double><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
+    row_pre_kernel<double><<<g, 256, 0, st>>>(loss, wts, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
                                                (double*)Rop);
   else
-    row_pre_kernel<float><<<g, 256, 0, st>>>(loss, tau, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
+    row_pre_kernel<float><<<g, 256, 0, st>>>(loss, wts, cfac, n, m, mp, Y, Obar, nu, Dbar, O,
                                               (float*)Rop);
   return hipGetLastError();
 }
@@ -276,9 +348,9 @@ hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, co
   return hipGetLastError();
 }
 
-hipError_t col_pre(double kappa, int64_t s, int64_t m, int64_t mp, const double* Wbar,
+hipError_t col_pre(const double* wts, int64_t s, int64_t m, int64_t mp, const double* Wbar,
                    const double* mu, double* Wc, hipStream_t st) {
-  col_pre_kernel<<<grid_for(s * m), 256, 0, st>>>(kappa, s, m, mp, Wbar, mu, Wc);
+  col_pre_kernel<<<grid_for(s * m), 256, 0, st>>>(wts, s, m, mp, Wbar, mu, Wc);
   return hipGetLastError();
 }
 

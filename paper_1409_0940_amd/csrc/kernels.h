@@ -87,12 +87,12 @@ hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, co
                  double* U, void* Wop, hipStream_t st);
 
 // Elementwise steps (FP64 state, n x mp / s x mp, only c < m touched).
-hipError_t row_pre(int prec, int loss, double tau, double cfac, int64_t n, int R, int64_t m,
+hipError_t row_pre(int prec, int loss, const double* wts, double cfac, int64_t n, int R, int64_t m,
                    int64_t mp, int64_t nbpad, const float* Y, const double* Obar, const double* nu,
                    const double* Dbar, double* O, void* Rop, hipStream_t st);
 hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, const double* P,
                     double* Obar, double* nu, double* Dbar, hipStream_t st);
-hipError_t col_pre(double kappa, int64_t s, int64_t m, int64_t mp, const double* Wbar,
+hipError_t col_pre(const double* wts, int64_t s, int64_t m, int64_t mp, const double* Wbar,
                    const double* mu, double* Wc, hipStream_t st);
 hipError_t col_post(int R, int64_t s, int64_t m, int64_t mp, const double* Wc, const double* Wp,
                     double* Wbar, double* mu, double* mup, hipStream_t st);
@@ -103,6 +103,24 @@ hipError_t pad(const double* src, int64_t rows, int64_t m, int64_t mp, double* d
                hipStream_t st);
 // Operand copy of a padded FP64 array (rows x mp) into op type.
 hipError_t to_op(int prec, const double* src, int64_t count, void* dst, hipStream_t st);
+// Penalty adaptation: out[0..4] = ||Dbar||^2, ||Wc - Wbar||^2,
+// sum_i ||Wp_i - Wbar||^2, ||Obar - Obar_prev||^2, ||Wbar - Wbar_prev||^2
+// (fixed-order sums; part holds 5 nb partials).
+hipError_t residuals(const double* Dbar, const double* Wc, const double* Wp, const double* Wbar,
+                     const double* Obar, const double* Obar_prev, const double* Wbar_prev, int R,
+                     int64_t n, int64_t spad, int64_t m, int64_t mp, double* part, int nb,
+                     double* out, hipStream_t st);
+// a[e] *= *f for e < count (nothing when *f == 1).
+hipError_t scale(double* a, int64_t count, const double* f, hipStream_t st);
+// Penalty block on the device (doubles): rho, the loss-prox weight 1/rho, the
+// regulariser weight n lambda / rho, the factor for the scaled duals from the
+// last change, and the number of changes made by adapt.
+enum { BS_W_RHO = 0, BS_W_TAU = 1, BS_W_KAPPA = 2, BS_W_DUAL = 3, BS_W_CHANGES = 4, BS_W_COUNT = 8 };
+// Residual balancing from the five sums of residuals(): updates wts.
+hipError_t adapt(const double* sums, double* wts, int R, int C, double n_lambda, double mu,
+                 double tau_f, hipStream_t st);
+// wts <- penalty rho (dual factor rho_old / rho when rescale, else 1).
+hipError_t set_rho(double* wts, double rho, double n_lambda, int rescale, hipStream_t st);
 // Operand copy of nblk blocks of W' ([spad][mp] doubles each) in the layout
 // the forward products of the precision read.
 hipError_t to_wop(int prec, const double* src, int64_t nblk, int64_t spad, int64_t mp, void* dst,

@@ -189,12 +189,13 @@ class GpuExecutor:
     """
 
     def __init__(self, precision="bf16x3", max_streams=8, device="cuda:0", setup_workers=2,
-                 z_mode="keep"):
+                 z_mode="keep", rho_adapt=None):
         import torch
         from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
         self.precision = precision
         self.z_mode = z_mode
+        self.rho_adapt = rho_adapt        # (every, mu, tau): residual balancing per solve
         self.device = torch.device(device)
         self.free_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_streams)]
         self.pool = ThreadPoolExecutor(max_workers=setup_workers)
@@ -205,7 +206,7 @@ class GpuExecutor:
         r = job.spec
         C = max(1, -(-r.s // 4096))
         p = abi.make_problem(X, Y, W, b, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision,
-                             check=False, z_mode=self.z_mode)
+                             check=False, z_mode=self.z_mode, rho_adapt=self.rho_adapt)
         p.X = p.Y = p.W = p.b = 256       # sizes only: footprint never touches memory
         inputs = sum(a.nbytes for a in job.inputs)
         return abi.bsadmm_footprint(p) + inputs
@@ -220,7 +221,7 @@ class GpuExecutor:
             dev = [torch.from_numpy(a).to(self.device) for a in (X, Y, W, b)]
             mon = torch.zeros(4, dtype=torch.float64, device=self.device)
         S = Solver(*dev, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision, stream=stream,
-                   z_mode=self.z_mode)
+                   z_mode=self.z_mode, rho_adapt=self.rho_adapt)
         return S, dev, mon
 
     def start(self, job):
@@ -300,25 +301,26 @@ def _request_inputs(r):
 
 def serve_stream(count=256, rate_per_s=20.0, precision="bf16x3", budget_gb=160.0, max_active=8,
                  max_iters=300, check_every=10, rtol=2e-6, workers=8, n_range=(2000, 200000),
-                 z_mode="keep"):
+                 z_mode="keep", rho_adapt=None, jobs=None):
     """Run the request stream of the serving workload end to end; returns (summary, results)."""
     import workloads as wl
-    reqs = wl.serving_stream(count, rate_per_s, n_range=n_range)
     t = time.perf_counter()
-    jobs = make_jobs(reqs, workers)
+    if jobs is None:   # a caller comparing settings passes the same jobs again
+        jobs = make_jobs(wl.serving_stream(count, rate_per_s, n_range=n_range), workers)
     gen_s = time.perf_counter() - t
-    ex = GpuExecutor(precision, max_active, z_mode=z_mode)
+    ex = GpuExecutor(precision, max_active, z_mode=z_mode, rho_adapt=rho_adapt)
     sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active, check_every, max_iters, rtol)
     t = time.perf_counter()
     res = sch.run(jobs)
     wall = time.perf_counter() - t
     summ = latency_summary(res, wall)
     summ.update({"precision": precision, "z_mode": z_mode, "max_active": max_active,
+                 "rho_adapt": list(rho_adapt) if rho_adapt else None,
                  "budget_gb": budget_gb,
                  "peak_active": sch.peak_active, "peak_used_gb": sch.peak_used / (1 << 30),
                  "input_generation_s": gen_s, "rate_per_s": rate_per_s,
                  "check_every": check_every, "max_iters": max_iters, "rtol": rtol})
-    return summ, res
+    return summ, res, jobs
 
 
 if __name__ == "__main__":
@@ -333,7 +335,11 @@ if __name__ == "__main__":
     ap.add_argument("--precision", default="bf16x3")
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--z-mode", default="keep", choices=["keep", "store"])
+    ap.add_argument("--rho-adapt", default="10,5,2",
+                    help="every,mu,tau of residual balancing; 'off' keeps rho = 1")
     args = ap.parse_args()
-    summ, _ = serve_stream(args.requests, args.rate, args.precision, max_active=args.max_active,
-                           z_mode=args.z_mode)
+    adapt = None if args.rho_adapt == "off" else tuple(
+        t(v) for t, v in zip((int, float, float), args.rho_adapt.split(",")))
+    summ, _, _ = serve_stream(args.requests, args.rate, args.precision,
+                              max_active=args.max_active, z_mode=args.z_mode, rho_adapt=adapt)
     print(json.dumps(summ))

@@ -12,7 +12,8 @@ class Solver:
     """Block-splitting ADMM solve on one GPU (Algorithm 1 over an R x C grid)."""
 
     def __init__(self, X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
-                 stream=None, hbm_budget_bytes=0, workspace_bytes=0, z_mode="auto"):
+                 stream=None, hbm_budget_bytes=0, workspace_bytes=0, z_mode="auto",
+                 rho_adapt=None):
         self._keep = (X, Y, W, b)
         self.n, self.d = X.shape
         self.m = Y.shape[1]
@@ -21,7 +22,8 @@ class Solver:
         self.device = X.device
         self.stream = stream
         self.problem = abi.make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss, precision,
-                                        stream, hbm_budget_bytes, workspace_bytes, z_mode=z_mode)
+                                        stream, hbm_budget_bytes, workspace_bytes, z_mode=z_mode,
+                                        rho_adapt=rho_adapt)
         self.h = abi.bsadmm_setup(self.problem)
 
     def iterate(self, iters, timed=False):
@@ -38,7 +40,17 @@ class Solver:
             return out.view(self.n, self.m)
         if name in ("Wc", "Wbar", "mu"):
             return out.view(self.s, self.m)
+        if name == "meta":
+            return out                        # [rho, iterations done]
         return out.view(self.R, self.s, self.m)
+
+    def set_rho(self, rho, rescale_duals=True):
+        """New ADMM penalty; the duals are rescaled to keep the fixed point."""
+        abi.bsadmm_set_rho(self.h, rho, rescale_duals)
+
+    @property
+    def rho(self):
+        return float(self.state("meta")[0])
 
     def set_state(self, name, value):
         abi.bsadmm_import_state(self.h, name, value.contiguous().to(torch.float64))

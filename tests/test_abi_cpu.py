@@ -47,6 +47,7 @@ def _problem(**kw):
     p.X, p.Y, p.W, p.b = base.get("ptrs", (0x10000, 0x20000, 0x30000, 0x40000))
     p.hbm_budget_bytes = base.get("budget", 0)
     p.workspace_bytes = base.get("ws", 0)
+    p.rho_adapt_every, p.rho_adapt_mu, p.rho_adapt_tau = base.get("adapt", (0, 0.0, 0.0))
     return p
 
 
@@ -62,6 +63,9 @@ def test_valid_problem_passes():
     (dict(lam=-1.0), "lambda"), (dict(rho=0.0), "rho"), (dict(sigma=0.0), "sigma"),
     (dict(lam=float("nan")), "lambda"), (dict(ptrs=(0, 0x20000, 0x30000, 0x40000)), "non-NULL"),
     (dict(ptrs=(0x10004, 0x20000, 0x30000, 0x40000)), "aligned"),
+    (dict(adapt=(-1, 0.0, 0.0)), "rho_adapt_every"), (dict(adapt=(10, 0.5, 2.0)), "rho_adapt_mu"),
+    (dict(adapt=(10, 10.0, 1.0)), "rho_adapt_tau"),
+    (dict(adapt=(10, float("inf"), 2.0)), "rho_adapt_mu"),
 ])
 def test_validation_errors(kw, frag):
     p = _problem(**kw)
@@ -148,3 +152,18 @@ def test_last_error_is_thread_local():
     t.join()
     assert seen["msg"] == ""
     assert "R and C" in pkg.lib().bsadmm_last_error().decode()
+
+
+def test_adaptation_settings_validate_and_add_buffers():
+    assert abi.bsadmm_validate(_problem(adapt=(10, 0.0, 0.0))) == 0
+    assert abi.bsadmm_validate(_problem(adapt=(5, 5.0, 2.0))) == 0
+    fixed = abi.bsadmm_footprint(_problem())
+    adapt = abi.bsadmm_footprint(_problem(adapt=(10, 0.0, 0.0)))
+    n, m, s = 1000, 1, 512
+    assert adapt - fixed == n * 16 * 8 + (s // 2 // 64 * 64 * 2) * 16 * 8
+
+
+def test_set_rho_rejects_bad_arguments_without_device():
+    L = pkg.lib()
+    assert L.bsadmm_set_rho(None, 1.0, 1) == 1
+    assert "NULL" in L.bsadmm_last_error().decode()

@@ -36,12 +36,13 @@ def test_same_result_alone_and_in_the_mix():
         assert np.array_equal(a.coef, m.coef), j.rid
 
 
-def test_served_ridge_solves_reach_the_optimum():
+@pytest.mark.parametrize("rho_adapt", [None, (10, 5.0, 2.0)], ids=["fixed_rho", "adaptive_rho"])
+def test_served_ridge_solves_reach_the_optimum(rho_adapt):
     from paper_1409_0940_amd.serving import GpuExecutor, Scheduler
     jobs = [j for j in _jobs() if j.spec.loss == "squared"]
     assert jobs
-    res = Scheduler(GpuExecutor("bf16x3", 4), 64 << 30, max_active=4, max_iters=300).run(
-        jobs, time_scale=0.0)
+    res = Scheduler(GpuExecutor("bf16x3", 4, rho_adapt=rho_adapt), 64 << 30, max_active=4,
+                    max_iters=300).run(jobs, time_scale=0.0)
     for j in jobs:
         X, Y, W, b = j.inputs
         Z = o.rff(X, W, b)
