@@ -49,6 +49,7 @@ import scipy.linalg as sla
 __all__ = [
     "partition", "rff", "rff_block", "gaussian_kernel",
     "prox_squared", "prox_hinge", "prox_l2", "prox_loss", "loss_sum",
+    "prox_l1", "project_simplex", "prox_cs_hinge", "prox_softmax",
     "objective", "ridge_closed_form", "ridge_push_through",
     "graph_projection", "Problem", "weights", "admm", "admm_reference",
     "paper_memory_floats", "predict", "set_rho", "residuals", "balance_factor",
@@ -118,11 +119,106 @@ def prox_l2(v, kappa):
     return v / (1.0 + 2.0 * kappa)
 
 
+# ---------------------------------------------------------------------------
+# Losses beyond the paper's experiments that still enter only through a prox
+# of the row state (the paper notes any loss with a cheap prox fits step 4):
+# l1 regression loss, Crammer-Singer multiclass hinge, multinomial logistic.
+# Targets of the two multiclass losses are one-hot rows (1 at the class).
+# ---------------------------------------------------------------------------
+
+def prox_l1(v, y, tau):
+    """f(o) = sum_k |y_k - o_k|: v - y soft-thresholded at tau, shifted back by y."""
+    d = v - y
+    return y + np.sign(d) * np.maximum(np.abs(d) - tau, 0.0)
+
+
+def project_simplex(w):
+    """Euclidean projection of each row of w onto {q >= 0, sum q = 1}
+    (sort the row in decreasing order; the threshold is set by the largest
+    count k whose k leading entries all stay positive after the shift)."""
+    w = np.atleast_2d(w)
+    u = -np.sort(-w, axis=1)
+    css = np.cumsum(u, axis=1) - 1.0
+    k = np.arange(1, w.shape[1] + 1)
+    keep = u - css / k > 0.0
+    last = w.shape[1] - 1 - np.argmax(keep[:, ::-1], axis=1)
+    theta = css[np.arange(w.shape[0]), last] / (last + 1.0)
+    return np.maximum(w - theta[:, None], 0.0)
+
+
+def prox_cs_hinge(v, Y, tau):
+    """f(o) = max_k (o_k + delta_k) - o_y with delta_k = [k != y] (Crammer-Singer).
+
+    With e_y the one-hot row, f(o) = g(o + delta) - e_y^T o where g = max is
+    the support function of the probability simplex; the linear term shifts
+    the point: prox_{tau f}(v) = prox_{tau g}(v + tau e_y + delta) - delta,
+    and by the Moreau decomposition prox_{tau g}(w) = w - tau P(w / tau) with
+    P the projection onto the simplex.
+    """
+    E = (np.asarray(Y, dtype=np.float64) > 0.5).astype(np.float64)
+    delta = 1.0 - E
+    w = v + tau * E + delta
+    return w - tau * project_simplex(w / tau) - delta
+
+
+def _softmax(o):
+    e = np.exp(o - o.max(axis=1, keepdims=True))
+    return e / e.sum(axis=1, keepdims=True)
+
+
+def prox_softmax(v, Y, tau, max_newton=100):
+    """f(o) = log sum_k exp(o_k) - y^T o (multinomial logistic).
+
+    Newton's method on h(o) = tau f(o) + 1/2 ||o - v||^2 for every row at
+    once, with the dense Hessians I + tau (diag(p) - p p^T), p = softmax(o),
+    halving a row's step until its gradient norm drops, and stopping a row
+    once its gradient tau (p - y) + o - v no longer decreases (rounding
+    level).
+    """
+    Yd = np.asarray(Y, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    n, m = v.shape
+    grad = lambda x: tau * (_softmax(x) - Yd) + x - v
+    O = v.copy()
+    g = grad(O)
+    live = np.ones(n, dtype=bool)
+    eye = np.eye(m)
+    for _ in range(max_newton):
+        if not live.any():
+            break
+        p = _softmax(O)
+        H = eye[None] + tau * (p[:, :, None] * eye[None] - p[:, :, None] * p[:, None, :])
+        step = np.linalg.solve(H, g[:, :, None])[:, :, 0]
+        gn = np.abs(g).max(axis=1)
+        t = np.ones(n)
+        done = ~live
+        newO, newg = O.copy(), g.copy()
+        for _ in range(45):
+            cand = O - t[:, None] * step
+            gc = grad(cand)
+            ok = (np.abs(gc).max(axis=1) < gn) & ~done
+            newO[ok], newg[ok] = cand[ok], gc[ok]
+            done |= ok
+            if done.all():
+                break
+            t = np.where(done, t, 0.5 * t)
+        improved = live & (np.abs(newg).max(axis=1) < gn)
+        live = improved
+        O, g = newO, newg
+    return O
+
+
 def prox_loss(kind, v, y, tau):
     if kind == "squared":
         return prox_squared(v, y, tau)
     if kind in ("hinge", "mc_hinge"):
         return prox_hinge(v, y, tau)
+    if kind == "l1":
+        return prox_l1(v, y, tau)
+    if kind == "cs_hinge":
+        return prox_cs_hinge(v, y, tau)
+    if kind == "softmax":
+        return prox_softmax(v, y, tau)
     raise ValueError(kind)
 
 
@@ -133,6 +229,15 @@ def loss_sum(kind, Y, O):
         return float(((Y - O) ** 2).sum())
     if kind in ("hinge", "mc_hinge"):
         return float(np.maximum(0.0, 1.0 - Y * O).sum())
+    if kind == "l1":
+        return float(np.abs(Y - O).sum())
+    if kind == "cs_hinge":
+        E = Y > 0.5
+        return float(((O + (~E)).max(axis=1) - (O * E).sum(axis=1)).sum())
+    if kind == "softmax":
+        mx = O.max(axis=1)
+        lse = mx + np.log(np.exp(O - mx[:, None]).sum(axis=1))
+        return float((lse - (Y * O).sum(axis=1)).sum())
     raise ValueError(kind)
 
 
