@@ -76,8 +76,22 @@ enum { BSADMM_FP64 = 0, BSADMM_FP32 = 1, BSADMM_BF16 = 2, BSADMM_BF16X3 = 3 };
  * "Modularity").
  *   SQUARED : ||y - o||^2 (no 1/2), any m.
  *   HINGE   : max(0, 1 - y o), m = 1, y in {-1, +1}.
- *   MC_HINGE: one-vs-all sum_k max(0, 1 - y_k o_k), y in {-1, +1}^m.      */
-enum { BSADMM_SQUARED = 0, BSADMM_HINGE = 1, BSADMM_MC_HINGE = 2 };
+ *   MC_HINGE: one-vs-all sum_k max(0, 1 - y_k o_k), y in {-1, +1}^m.
+ * Further losses with cheap proxes (not in the paper's experiments):
+ *   L1      : sum_k |y_k - o_k|, any m (soft-thresholding prox).
+ *   CS_HINGE: Crammer-Singer multiclass hinge max_k (o_k + [k != c]) - o_c,
+ *             m >= 2, y one-hot (1 at class c, 0 elsewhere); row-wise prox
+ *             through a projection onto the probability simplex.
+ *   SOFTMAX : multinomial logistic log sum_k exp(o_k) - o_c, m >= 2, y
+ *             one-hot; row-wise prox by Newton's method.                   */
+enum {
+  BSADMM_SQUARED = 0,
+  BSADMM_HINGE = 1,
+  BSADMM_MC_HINGE = 2,
+  BSADMM_L1 = 3,
+  BSADMM_CS_HINGE = 4,
+  BSADMM_SOFTMAX = 5
+};
 
 /* ----------------------------------------------------------- regulariser */
 /* r(W) = ||W||_F^2, separable over feature blocks (l2 case of the block
@@ -188,7 +202,8 @@ BSADMM_API int rff_map(const float* X, int64_t n, int64_t d, const float* W, con
 /* ----------------------------------------------------------------------
  * bsadmm_validate -- host-only argument checks of a problem (no HIP call,
  * no device access): n >= R >= 1, s >= C >= 1, d >= 1, 1 <= m <= 1024,
- * m == 1 for HINGE, lambda >= 0, rho > 0, sigma > 0, known enums, non-null
+ * m == 1 for HINGE, m >= 2 for CS_HINGE and SOFTMAX, lambda >= 0, rho > 0,
+ * sigma > 0, known enums, non-null
  * X, Y, W, b, 16-byte alignment of X, Y, W, b, rho_adapt_every >= 0 and
  * rho_adapt_mu, rho_adapt_tau either 0 or finite and > 1.  Returns OK or
  * EINVAL.
@@ -210,8 +225,9 @@ BSADMM_API int bsadmm_footprint(const bsadmm_problem* p, size_t* bytes);
  * cache of eq. cache: for every block, Q_ij = (I + Z_ij^T Z_ij)^{-1} in
  * FP64 through a Cholesky factorisation (the paper builds it in the first
  * iteration, step 16).  Synchronises the stream.
- * Errors: EINVAL, ENONFINITE (NaN/Inf in X, Y, W or b), ENOMEM, EDEVICE,
- * ENOTPD.  On error *out is NULL and nothing stays allocated.
+ * Errors: EINVAL (also targets that are not +-1 for HINGE / MC_HINGE or
+ * not one-hot rows for CS_HINGE / SOFTMAX), ENONFINITE (NaN/Inf in X, Y, W
+ * or b), ENOMEM, EDEVICE, ENOTPD.  On error *out is NULL and nothing stays allocated.
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_setup(const bsadmm_problem* p, bsadmm_handle** out);
 

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbsadmm.so")
 
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
-LOSS = {"squared": 0, "hinge": 1, "mc_hinge": 2}
+LOSS = {"squared": 0, "hinge": 1, "mc_hinge": 2, "l1": 3, "cs_hinge": 4, "softmax": 5}
 Z_MODE = {"auto": 0, "store": 1, "keep": 2}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTPD", 5: "ENONFINITE",
           6: "ESTATE", 7: "ENOTIMPL"}

@@ -41,6 +41,18 @@ int hip_fail(hipError_t e, const char* what) {
 
 inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// Loss code of the elementwise kernels: 0 squared, 1 hinge (one-vs-all
+// included), 2 l1, 3 Crammer-Singer, 4 multinomial logistic.
+inline int kernel_loss(int loss) {
+  switch (loss) {
+    case BSADMM_SQUARED: return 0;
+    case BSADMM_L1: return 2;
+    case BSADMM_CS_HINGE: return 3;
+    case BSADMM_SOFTMAX: return 4;
+    default: return 1;
+  }
+}
+
 constexpr int kMonBlocks = 256;  // partial sums per monitored quantity
 
 // Sizes and layout derived from a problem; computed on the host only.
@@ -75,9 +87,10 @@ int validate(const bsadmm_problem* p) {
   if (p->s < p->C) return fail(BSADMM_EINVAL, "need s >= C");
   if (p->d < 1) return fail(BSADMM_EINVAL, "need d >= 1");
   if (p->m < 1 || p->m > 1024) return fail(BSADMM_EINVAL, "need 1 <= m <= 1024");
-  if (p->loss != BSADMM_SQUARED && p->loss != BSADMM_HINGE && p->loss != BSADMM_MC_HINGE)
-    return fail(BSADMM_EINVAL, "unknown loss");
+  if (p->loss < BSADMM_SQUARED || p->loss > BSADMM_SOFTMAX) return fail(BSADMM_EINVAL, "unknown loss");
   if (p->loss == BSADMM_HINGE && p->m != 1) return fail(BSADMM_EINVAL, "HINGE needs m == 1");
+  if ((p->loss == BSADMM_CS_HINGE || p->loss == BSADMM_SOFTMAX) && p->m < 2)
+    return fail(BSADMM_EINVAL, "CS_HINGE and SOFTMAX need m >= 2");
   if (p->reg != BSADMM_L2) return fail(BSADMM_EINVAL, "unknown regulariser");
   if (p->precision < BSADMM_FP64 || p->precision > BSADMM_BF16X3)
     return fail(BSADMM_EINVAL, "unknown precision");
@@ -297,7 +310,7 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
       HCHK(hipMemcpyAsync(h->Wbar_prev, h->Wbar, L.b_col, hipMemcpyDeviceToDevice, h->st));
     }
     tm.begin();
-    HCHK(bs::row_pre(L.prec, h->p.loss == BSADMM_SQUARED ? 0 : 1, h->wts, cfac, L.n, L.R, L.m,
+    HCHK(bs::row_pre(L.prec, kernel_loss(h->p.loss), h->wts, cfac, L.n, L.R, L.m,
                      L.mp, L.nbpad, h->p.Y, h->Obar, h->nu, h->Dbar, h->O, h->Rop, h->st));
     tm.end(BSADMM_PH_ROW);
     tm.begin();
@@ -438,13 +451,27 @@ int do_setup(bsadmm_handle* h) {
   HCHK(hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
   HCHK(hipStreamSynchronize(st));
   if (flag & 1) return fail(BSADMM_ENONFINITE, "X, Y, W or b holds NaN or Inf");
-  if (p.loss != BSADMM_SQUARED) {
-    // hinge targets must be exactly +-1: checked on a host copy of Y
+  if (p.loss != BSADMM_SQUARED && p.loss != BSADMM_L1) {
+    // target encodings, checked on a host copy of Y: +-1 for the hinge
+    // losses, one-hot rows for the two multiclass losses with a class index
     std::vector<float> y((size_t)L.n * L.m);
     HCHK(hipMemcpyAsync(y.data(), p.Y, y.size() * 4, hipMemcpyDeviceToHost, st));
     HCHK(hipStreamSynchronize(st));
-    for (float v : y)
-      if (v != 1.0f && v != -1.0f) return fail(BSADMM_EINVAL, "hinge targets must be +1 or -1");
+    if (p.loss == BSADMM_HINGE || p.loss == BSADMM_MC_HINGE) {
+      for (float v : y)
+        if (v != 1.0f && v != -1.0f) return fail(BSADMM_EINVAL, "hinge targets must be +1 or -1");
+    } else {
+      for (int64_t r = 0; r < L.n; ++r) {
+        int ones = 0;
+        for (int64_t k = 0; k < L.m; ++k) {
+          const float v = y[(size_t)r * L.m + k];
+          if (v == 1.0f) ++ones;
+          else if (v != 0.0f) ones = 2;
+        }
+        if (ones != 1)
+          return fail(BSADMM_EINVAL, "CS_HINGE / SOFTMAX targets must be one-hot rows");
+      }
+    }
   }
   // Gram blocks and the FP64 inverse cache (eq. cache)
   const size_t slot = (size_t)L.S * L.S;
@@ -716,7 +743,7 @@ int bsadmm_monitor(bsadmm_handle* h, double* out) {
   if (!h || !out) return fail(BSADMM_EINVAL, "NULL argument");
   if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
   const Plan& L = h->L;
-  hipError_t e = bs::monitor(h->p.loss == BSADMM_SQUARED ? 0 : 1, h->P, h->p.Y, h->Wp, h->Wbar,
+  hipError_t e = bs::monitor(kernel_loss(h->p.loss), h->P, h->p.Y, h->Wp, h->Wbar,
                              h->Dbar, L.R, L.n, L.spad, L.m, L.mp, h->mon_part, kMonBlocks, out,
                              h->st);
   if (e != hipSuccess) {
@@ -764,7 +791,7 @@ int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F) {
       e = bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, wop, 0, L.mp, h->P, st);
   }
   if (e == hipSuccess)
-    e = bs::loss_partial(h->p.loss == BSADMM_SQUARED ? 0 : 1, h->P, h->p.Y, L.n, L.m, L.mp, part,
+    e = bs::loss_partial(kernel_loss(h->p.loss), h->P, h->p.Y, L.n, L.m, L.mp, part,
                          NB, st);
   if (e == hipSuccess) e = bs::sumsq_partial(wpad, L.spad * L.mp, part + NB, NB, st);
   std::vector<double> hp(2 * NB);

@@ -29,12 +29,151 @@ inline unsigned grid_for(int64_t count) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (total); \
        e += (int64_t)gridDim.x * blockDim.x)
 
+// Kernel loss codes: 0 squared ||y - o||^2, 1 hinge max(0, 1 - y o) (also
+// one-vs-all), 2 l1 |y - o|: elementwise proxes; 3 Crammer-Singer hinge and
+// 4 multinomial logistic: row-wise proxes (row_prox_kernel).
 __device__ __forceinline__ double prox_loss(int loss, double v, double y, double tau) {
   if (loss == 0) return (v + 2.0 * tau * y) / (1.0 + 2.0 * tau);  // ||y - o||^2
+  if (loss == 2) {  // |y - o|: soft-threshold v - y at tau
+    const double d = v - y, a = fabs(d) - tau;
+    return a > 0.0 ? y + (d > 0.0 ? a : -a) : y;
+  }
   // max(0, 1 - y o): move by y * clamp(1 - y v, 0, tau)
   double g = 1.0 - y * v;
   g = g < 0.0 ? 0.0 : (g > tau ? tau : g);
   return v + y * g;
+}
+
+// Row-wise proxes, one thread per row r of the padded n x mp state; the
+// argument of the prox is v_k = O-bar[r][k] - nu[r][k] and the result goes to
+// O[r][k], which also holds the iterate while it is being computed.
+//
+// Crammer-Singer, f(o) = max_k (o_k + delta_k) - o_y with delta_k = [k != y]:
+// prox_{tau f}(v) = w - tau P(w / tau) - delta with w = v + tau e_y + delta and
+// P the projection onto the probability simplex, P(u)_k = max(u_k - theta, 0).
+// theta is found by support shrinking: starting from all k, theta = (sum of
+// u over the support - 1) / (support size), and entries not above theta leave
+// the support until it is stable (at most m passes; exact).
+//
+// Multinomial logistic, f(o) = log sum_k exp(o_k) - y^T o: Newton's method on
+// h(o) = tau f(o) + 1/2 ||o - v||^2.  Its Hessian is D - tau p p^T with
+// D = diag(1 + tau p), p = softmax(o), so by Sherman-Morrison the step is
+// H^{-1} g = g / d + tau (p / d) (sum p g / d) / (1 - tau sum p^2 / d).  A step
+// is halved until the gradient norm drops; the iteration stops when it no
+// longer does (rounding level) or after 100 steps.
+__device__ __forceinline__ double row_v(const double* Obar, const double* nu, int64_t o) {
+  return Obar[o] - nu[o];
+}
+
+__global__ void row_prox_kernel(int loss, const double* __restrict__ wts, int64_t n, int64_t m,
+                                int64_t mp, const float* __restrict__ Y,
+                                const double* __restrict__ Obar, const double* __restrict__ nu,
+                                double* __restrict__ O) {
+  const double tau = wts[BS_W_TAU];
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = r * mp;
+    const float* y = Y + r * m;
+    if (loss == 3) {
+      // w into O; the support test runs on u = w / tau
+      for (int64_t k = 0; k < m; ++k) {
+        const double e = y[k] > 0.5f ? 1.0 : 0.0;
+        O[b + k] = row_v(Obar, nu, b + k) + tau * e + (1.0 - e);
+      }
+      double theta = -__builtin_inf();
+      int64_t cnt = -1;
+      for (int pass = 0; pass <= m; ++pass) {
+        double sum = 0.0;
+        int64_t c = 0;
+        for (int64_t k = 0; k < m; ++k) {
+          const double u = O[b + k] / tau;
+          if (u > theta) {
+            sum += u;
+            ++c;
+          }
+        }
+        const double th = (sum - 1.0) / (double)c;
+        if (c == cnt) break;  // support unchanged: theta is final
+        cnt = c;
+        theta = th;
+      }
+      for (int64_t k = 0; k < m; ++k) {
+        const double w = O[b + k], u = w / tau;
+        const double q = u > theta ? u - theta : 0.0;
+        O[b + k] = w - tau * q - (y[k] > 0.5f ? 0.0 : 1.0);
+      }
+    } else {  // loss == 4
+      for (int64_t k = 0; k < m; ++k) O[b + k] = row_v(Obar, nu, b + k);
+      // softmax normaliser and gradient norm of the current iterate
+      auto stats = [&](double t, double mx0, double se0, double a, double c, double& mx,
+                       double& se, double& gmax) {
+        // iterate o - t * step (t = 0: o itself), step from (mx0, se0, a, c)
+        mx = -__builtin_inf();
+        for (int64_t k = 0; k < m; ++k) {
+          double x = O[b + k];
+          if (t != 0.0) {
+            const double p = exp(x - mx0) / se0, d = 1.0 + tau * p;
+            const double g = tau * (p - (double)y[k]) + x - row_v(Obar, nu, b + k);
+            x -= t * (g / d + tau * (p / d) * a / (1.0 - tau * c));
+          }
+          mx = x > mx ? x : mx;
+        }
+        se = 0.0;
+        for (int64_t k = 0; k < m; ++k) {
+          double x = O[b + k];
+          if (t != 0.0) {
+            const double p = exp(x - mx0) / se0, d = 1.0 + tau * p;
+            const double g = tau * (p - (double)y[k]) + x - row_v(Obar, nu, b + k);
+            x -= t * (g / d + tau * (p / d) * a / (1.0 - tau * c));
+          }
+          se += exp(x - mx);
+        }
+        gmax = 0.0;
+        for (int64_t k = 0; k < m; ++k) {
+          double x = O[b + k];
+          if (t != 0.0) {
+            const double p = exp(x - mx0) / se0, d = 1.0 + tau * p;
+            const double g = tau * (p - (double)y[k]) + x - row_v(Obar, nu, b + k);
+            x -= t * (g / d + tau * (p / d) * a / (1.0 - tau * c));
+          }
+          const double g = tau * (exp(x - mx) / se - (double)y[k]) + x - row_v(Obar, nu, b + k);
+          gmax = fabs(g) > gmax ? fabs(g) : gmax;
+        }
+      };
+      double mx, se, gn;
+      stats(0.0, 0.0, 1.0, 0.0, 0.0, mx, se, gn);
+      for (int it = 0; it < 100; ++it) {
+        // Sherman-Morrison sums at the current iterate
+        double a = 0.0, c = 0.0;
+        for (int64_t k = 0; k < m; ++k) {
+          const double x = O[b + k];
+          const double p = exp(x - mx) / se, d = 1.0 + tau * p;
+          const double g = tau * (p - (double)y[k]) + x - row_v(Obar, nu, b + k);
+          a += p * g / d;
+          c += p * p / d;
+        }
+        double t = 1.0, mxc = 0.0, sec = 0.0, gc = 0.0;
+        bool ok = false;
+        for (int h = 0; h < 45; ++h, t *= 0.5) {
+          stats(t, mx, se, a, c, mxc, sec, gc);
+          if (gc < gn) {
+            ok = true;
+            break;
+          }
+        }
+        if (!ok) break;  // no further decrease: at rounding level
+        for (int64_t k = 0; k < m; ++k) {
+          const double x = O[b + k];
+          const double p = exp(x - mx) / se, d = 1.0 + tau * p;
+          const double g = tau * (p - (double)y[k]) + x - row_v(Obar, nu, b + k);
+          O[b + k] = x - t * (g / d + tau * (p / d) * a / (1.0 - tau * c));
+        }
+        mx = mxc;
+        se = sec;
+        gn = gc;
+      }
+    }
+  }
 }
 
 template <typename OP>
@@ -48,7 +187,7 @@ __global__ void row_pre_kernel(int loss, const double* __restrict__ wts, double 
     const int64_t r = e / m, c = e - r * m;
     const int64_t o = r * mp + c;
     const double nv = nu[o];
-    O[o] = prox_loss(loss, Obar[o] - nv, (double)Y[e], tau);
+    if (loss < 3) O[o] = prox_loss(loss, Obar[o] - nv, (double)Y[e], tau);
     Rop[o] = cvt_from_double<OP>(Dbar[o] * cfac + nv);
   }
 }
@@ -67,7 +206,7 @@ __global__ void row_pre_bf16_kernel(int loss, const double* __restrict__ wts, do
     const int64_t r = e / m, c = e - r * m;
     const int64_t o = r * mp + c;
     const double nv = nu[o];
-    O[o] = prox_loss(loss, Obar[o] - nv, (double)Y[e], tau);
+    if (loss < 3) O[o] = prox_loss(loss, Obar[o] - nv, (double)Y[e], tau);
     // row block of r: the largest i with floor(i n / R) <= r
     int64_t i = r * R / n;
     while (i + 1 < R && (i + 1) * n / R <= r) ++i;
@@ -175,15 +314,38 @@ __global__ void loss_partial_kernel(int loss, const double* __restrict__ P,
                                     double* __restrict__ part) {
   __shared__ double red[256];
   double acc = 0.0;
-  GRID_STRIDE(e, n * m) {
-    const int64_t r = e / m, c = e - r * m;
-    const double o = P[r * mp + c], y = (double)Y[e];
-    if (loss == 0) {
-      const double d = y - o;
-      acc += d * d;
-    } else {
-      const double h = 1.0 - y * o;
-      acc += h > 0.0 ? h : 0.0;
+  if (loss < 3) {
+    GRID_STRIDE(e, n * m) {
+      const int64_t r = e / m, c = e - r * m;
+      const double o = P[r * mp + c], y = (double)Y[e];
+      if (loss == 0) {
+        const double d = y - o;
+        acc += d * d;
+      } else if (loss == 2) {
+        acc += fabs(y - o);
+      } else {
+        const double h = 1.0 - y * o;
+        acc += h > 0.0 ? h : 0.0;
+      }
+    }
+  } else {  // row-wise: Crammer-Singer max_k (o_k + delta_k) - o_y, or log sum exp(o) - o_y
+    GRID_STRIDE(r, n) {
+      const double* o = P + r * mp;
+      const float* y = Y + r * m;
+      double mx = -__builtin_inf(), oy = 0.0;
+      for (int64_t k = 0; k < m; ++k) {
+        const bool cls = y[k] > 0.5f;
+        const double v = o[k] + (loss == 3 && !cls ? 1.0 : 0.0);
+        mx = v > mx ? v : mx;
+        if (cls) oy = o[k];
+      }
+      if (loss == 3) {
+        acc += mx - oy;
+      } else {
+        double se = 0.0;
+        for (int64_t k = 0; k < m; ++k) se += exp(o[k] - mx);
+        acc += mx + log(se) - oy;
+      }
     }
   }
   const double t = block_sum(acc, red);
@@ -329,6 +491,8 @@ hipError_t row_pre(int prec, int loss, const double* wts, double cfac, int64_t n
                    int64_t mp, int64_t nbpad, const float* Y, const double* Obar, const double* nu,
                    const double* Dbar, double* O, void* Rop, hipStream_t st) {
   unsigned g = grid_for(n * m);
+  if (loss >= 3)
+    row_prox_kernel<<<grid_for(n), 256, 0, st>>>(loss, wts, n, m, mp, Y, Obar, nu, O);
   if (prec == BS_PREC_BF16)
     row_pre_bf16_kernel<<<g, 256, 0, st>>>(loss, wts, cfac, n, R, m, mp, nbpad, Y, Obar, nu, Dbar,
                                            O, (uint16_t*)Rop);

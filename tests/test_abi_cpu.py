@@ -63,6 +63,8 @@ def test_valid_problem_passes():
     (dict(lam=-1.0), "lambda"), (dict(rho=0.0), "rho"), (dict(sigma=0.0), "sigma"),
     (dict(lam=float("nan")), "lambda"), (dict(ptrs=(0, 0x20000, 0x30000, 0x40000)), "non-NULL"),
     (dict(ptrs=(0x10004, 0x20000, 0x30000, 0x40000)), "aligned"),
+    (dict(loss="cs_hinge", m=1), "m >= 2"), (dict(loss="softmax", m=1), "m >= 2"),
+    (dict(loss=6), "loss"),
     (dict(adapt=(-1, 0.0, 0.0)), "rho_adapt_every"), (dict(adapt=(10, 0.5, 2.0)), "rho_adapt_mu"),
     (dict(adapt=(10, 10.0, 1.0)), "rho_adapt_tau"),
     (dict(adapt=(10, float("inf"), 2.0)), "rho_adapt_mu"),

@@ -24,6 +24,11 @@ CASES = [
     ("mc_hinge_2x2", "digits_pm1", 600, 784, 256, 5, 2, 2, "mc_hinge", 10.0, 1e-3, 1.0),
     ("multi_sq_4x3", "digits", 2000, 784, 700, 10, 4, 3, "squared", 10.0, 1e-4, 1.0),
     ("speech_1x4", "speech_pm1", 900, 440, 512, 20, 1, 4, "mc_hinge", 8.0, 1e-3, 1.0),
+    # losses beyond the paper's experiments (prox step only)
+    ("l1_2x3", "sine", 1000, 20, 300, 1, 2, 3, "l1", 4.0, 1e-3, 1.0),
+    ("cs_hinge_2x2", "digits", 800, 784, 256, 10, 2, 2, "cs_hinge", 10.0, 1e-3, 1.0),
+    ("cs_hinge_m40_1x2", "digits", 700, 64, 200, 40, 1, 2, "cs_hinge", 10.0, 1e-3, 1.0),
+    ("softmax_3x2", "digits", 900, 784, 320, 10, 3, 2, "softmax", 10.0, 1e-3, 1.0),
 ]
 
 
