@@ -322,6 +322,145 @@ solve_kernel(const double* __restrict__ Q, int64_t S, int C, int b0, const int64
   }
 }
 
+// ---------------------------------------------------------------------------
+// Projection solve for many output columns (ntiles > 2): one pass over Q for
+// all column tiles.  A workgroup owns 128 rows of W'_b (each wave two 16-row
+// tiles) and every column; per 16-value k-step the rows k0 .. k0 + 15 of
+// rhs_b (16 x mp doubles) are staged once in LDS, double-buffered, and read by
+// all 4 waves, so rhs moves from L2 once per 128 rows instead of once per 16.
+// A lane loads 4 adjacent doubles of a row of Q, which feed instructions
+// q = 0..3 with the matching rhs rows (the k-permutation of solve_kernel).
+// ---------------------------------------------------------------------------
+template <typename OUT, int NTC>
+__global__ void __launch_bounds__(256, 2)
+solve_wide_kernel(const double* __restrict__ Q, int64_t S, int C, int b0,
+                  const int64_t* __restrict__ coff, const int64_t* __restrict__ sjs, int64_t spad,
+                  int64_t mp, const double* __restrict__ rhs, double* __restrict__ Wp,
+                  double* __restrict__ U, OUT* __restrict__ Wop) {
+  constexpr int NC = NTC * 16;
+  constexpr int PITCH = NC + 4;  // doubles per staged row: rows 4 apart 32 banks apart
+  constexpr int NSEG = NTC / 2;                    // 16-byte segments per thread per stage
+  static_assert(NTC % 2 == 0, "a stage is 8 NC segments, NTC / 2 per thread");
+  __shared__ __attribute__((aligned(16))) double stage[2][16 * PITCH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int b = b0 + (int)blockIdx.y;
+  const int i = b / C, j = b - i * C;
+  const int64_t sj = sjs[j];
+  if ((int64_t)blockIdx.x * 128 >= sj) return;  // uniform over the workgroup
+  const int64_t row0 = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const double* Qb = Q + (int64_t)b * S * S;
+  const int64_t base = ((int64_t)i * spad + coff[j]) * mp;
+  const double* rb = rhs + base;
+  const int64_t k16 = (sj + 15) / 16 * 16;          // Q pad columns are zero off the diagonal
+  // rows past sj read row sj - 1 of Q (in bounds) and store nothing
+  const double* qrow0 = Qb + min(row0 + fr, sj - 1) * S + 4 * fg;
+  const double* qrow1 = Qb + min(row0 + 16 + fr, sj - 1) * S + 4 * fg;
+
+  // staged segment q = tid + 256 u: rhs row q / (NC / 2) of the step, columns
+  // 2 (q % (NC / 2)) + 0..1 of the workgroup's NC (clamped into rhs past mp;
+  // those staged values feed accumulators that are never stored)
+  int soff[NSEG], goff[NSEG];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) {
+    const int q = tid + 256 * u;
+    const int r = q / (NC / 2), c2 = 2 * (q % (NC / 2));
+    goff[u] = r * (int)mp + min(nc0 * 16 + c2, (int)mp - 2);
+    soff[u] = r * PITCH + c2;
+  }
+
+  v4d acc[2][NTC];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[m][t][r] = 0.0;
+
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2 stg[NSEG];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const d2*>(rb + goff[u]);
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) *reinterpret_cast<d2*>(&stage[0][soff[u]]) = stg[u];
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < k16; k0 += 16) {
+    const int buf = (int)((k0 >> 4) & 1);
+    const bool more = k0 + 16 < k16;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u)
+        stg[u] = *reinterpret_cast<const d2*>(rb + (k0 + 16) * mp + goff[u]);
+    }
+    const Frag<BS_PREC_F64> a0 = load_frag<BS_PREC_F64>(qrow0 + k0);
+    const Frag<BS_PREC_F64> a1 = load_frag<BS_PREC_F64>(qrow1 + k0);
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      Frag<BS_PREC_F64> bb;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bb.v[q] = stage[buf][(4 * fg + q) * PITCH + t * 16 + fr];
+      mfma_step(acc[0][t], a0, bb);
+      mfma_step(acc[1][t], a1, bb);
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u) *reinterpret_cast<d2*>(&stage[buf ^ 1][soff[u]]) = stg[u];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const int nt = nc0 + t;
+      if (nt >= ntiles) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 16 * m + acc_row<double>(fg, r);
+        if (row < sj) {
+          const int64_t o = base + row * mp + nt * 16 + fr;
+          const double w = acc[m][t][r];
+          Wp[o] = w;
+          U[o] = rhs[o] - w;
+          if constexpr (sizeof(OUT) == 2) {
+            uint16_t hi, lo;
+            split_bf16(w, hi, lo);
+            const int64_t tcol = ((int64_t)i * 2 * mp + nt * 16 + fr) * spad + coff[j] + row;
+            Wop[tcol] = hi;
+            Wop[tcol + mp * spad] = lo;
+          } else {
+            Wop[o] = (OUT)w;
+          }
+        }
+      }
+    }
+}
+
+template <typename OUT>
+void launch_solve(const double* Q, int64_t S, int C, int b0, int nb, const int64_t* coff,
+                  const int64_t* sjs, int64_t spad, int64_t mp, const double* rhs, double* Wp,
+                  double* U, OUT* Wop, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  if (ntiles <= 2) {  // few columns: Q is streamed once by 16-row waves
+    constexpr int NTC = 4;
+    dim3 g((unsigned)(S / 64), (unsigned)nb, (unsigned)((ntiles + NTC - 1) / NTC));
+    solve_kernel<OUT, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U, Wop);
+    return;
+  }
+#define BS_SOLVE_WIDE(NTC)                                                                 \
+  solve_wide_kernel<OUT, NTC><<<dim3((unsigned)((S + 127) / 128), (unsigned)nb,            \
+                                     (unsigned)((ntiles + NTC - 1) / NTC)), 256, 0, st>>>( \
+      Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U, Wop)
+  if (ntiles <= 4) BS_SOLVE_WIDE(4);
+  else if (ntiles <= 6) BS_SOLVE_WIDE(6);
+  else if (ntiles <= 8) BS_SOLVE_WIDE(8);
+  else if (ntiles <= 10) BS_SOLVE_WIDE(10);
+  else BS_SOLVE_WIDE(8);
+#undef BS_SOLVE_WIDE
+}
+
 }  // namespace
 
 hipError_t identity_pad(double* slots, int batch, int64_t S, const int64_t* sj_host,
@@ -354,19 +493,13 @@ hipError_t spd_inverse(double* slots, int batch, int64_t S, double* work, double
 hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, const int64_t* coff,
                  const int64_t* sjs, int64_t spad, int64_t mp, const double* rhs, double* Wp,
                  double* U, void* Wop, hipStream_t st) {
-  constexpr int NTC = 4;
-  const int ntiles = (int)(mp / 16);
   if (nb <= 0) return hipSuccess;
-  dim3 g((unsigned)(S / 64), (unsigned)nb, (unsigned)((ntiles + NTC - 1) / NTC));
   if (prec == BS_PREC_F64)
-    solve_kernel<double, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
-                                                 (double*)Wop);
+    launch_solve<double>(Q, S, C, b0, nb, coff, sjs, spad, mp, rhs, Wp, U, (double*)Wop, st);
   else if (prec == BS_PREC_BF16)
-    solve_kernel<uint16_t, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
-                                                   (uint16_t*)Wop);
+    launch_solve<uint16_t>(Q, S, C, b0, nb, coff, sjs, spad, mp, rhs, Wp, U, (uint16_t*)Wop, st);
   else  // FP32 and BF16X3 multiply FP32 operands
-    solve_kernel<float, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
-                                                (float*)Wop);
+    launch_solve<float>(Q, S, C, b0, nb, coff, sjs, spad, mp, rhs, Wp, U, (float*)Wop, st);
   return hipGetLastError();
 }
 

@@ -29,6 +29,12 @@ CASES = [
     ("cs_hinge_2x2", "digits", 800, 784, 256, 10, 2, 2, "cs_hinge", 10.0, 1e-3, 1.0),
     ("cs_hinge_m40_1x2", "digits", 700, 64, 200, 40, 1, 2, "cs_hinge", 10.0, 1e-3, 1.0),
     ("softmax_3x2", "digits", 900, 784, 320, 10, 3, 2, "softmax", 10.0, 1e-3, 1.0),
+    # many output columns: the projection solve covers 5, 10 and 13 column
+    # tiles (one pass with a dead tile; one pass; two passes); s_j = 176 / 177
+    # spans a full and a partial 128-row workgroup and a ragged k tail
+    ("wide_m70_2x3", "digits", 800, 64, 530, 70, 2, 3, "squared", 10.0, 1e-4, 1.0),
+    ("wide_m147_2x3", "speech_pm1", 700, 440, 530, 147, 2, 3, "mc_hinge", 8.0, 1e-3, 1.0),
+    ("wide_m200_1x2", "digits", 600, 64, 280, 200, 1, 2, "squared", 10.0, 1e-4, 1.0),
 ]
 
 
