@@ -101,6 +101,7 @@ __global__ void check_finite_kernel(const float* __restrict__ p, int64_t count, 
 // ~2^-16 of the product), so the phase keeps ~16 significant bits instead of
 // the ~8 of a single BF16 product.
 // ---------------------------------------------------------------------------
+template <int V> struct Tag { static constexpr int value = V; };
 template <int P> constexpr int planes() { return P == BS_PREC_BF16X3 ? 2 : 1; }
 template <int P> constexpr int krow_bytes() { return P == BS_PREC_BF16X3 ? 64 : 128; }
 
@@ -155,7 +156,10 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
   }
   const int64_t xpb = xps * (int64_t)sizeof(op_t), wpb = wps * (int64_t)sizeof(op_t);
   const int64_t nchunks = Kp / BK;
-  u32x4 sa[NPL][NS], sb[NPL][NS];
+  // Global loads run DEPTH chunks ahead of the MFMAs through DEPTH register
+  // sets (the FP64 variant has no registers to spare for a second set).
+  constexpr int DEPTH = P == BS_PREC_F64 ? 1 : 2;
+  u32x4 sa[DEPTH][NPL][NS], sb[DEPTH][NPL][NS];
 
   accv acc[4][4];
 #pragma unroll
@@ -165,36 +169,32 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  // prologue: chunk 0 into LDS buffer 0
-#pragma unroll
-  for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      sa[pl][i] = *reinterpret_cast<const u32x4*>(gA[i] + pl * xpb);
-      sb[pl][i] = *reinterpret_cast<const u32x4*>(gB[i] + pl * wpb);
-    }
-#pragma unroll
-  for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {
-      *reinterpret_cast<u32x4*>(&lds[0][0][pl][ldsoff[i]]) = sa[pl][i];
-      *reinterpret_cast<u32x4*>(&lds[0][1][pl][ldsoff[i]]) = sb[pl][i];
-    }
-  __syncthreads();
   const int fr = lane & 15, fg = lane >> 4;
-  for (int64_t c = 0; c < nchunks; ++c) {
-    const int buf = (int)(c & 1);
-    const bool more = c + 1 < nchunks;
-    if (more) {
-      const int64_t off = (c + 1) * KROW;
+  // register set SET <- chunk `chunk` of the X and W tiles
+  auto gload = [&](auto set, int64_t chunk) {
+    constexpr int S = decltype(set)::value;
+    const int64_t off = chunk * KROW;
 #pragma unroll
-      for (int pl = 0; pl < NPL; ++pl)
+    for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
-        for (int i = 0; i < NS; ++i) {
-          sa[pl][i] = *reinterpret_cast<const u32x4*>(gA[i] + pl * xpb + off);
-          sb[pl][i] = *reinterpret_cast<const u32x4*>(gB[i] + pl * wpb + off);
-        }
-    }
+      for (int i = 0; i < NS; ++i) {
+        sa[S][pl][i] = *reinterpret_cast<const u32x4*>(gA[i] + pl * xpb + off);
+        sb[S][pl][i] = *reinterpret_cast<const u32x4*>(gB[i] + pl * wpb + off);
+      }
+  };
+  // LDS buffer BUF <- register set SET
+  auto lstore = [&](auto set, auto buf) {
+    constexpr int S = decltype(set)::value, B = decltype(buf)::value;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        *reinterpret_cast<u32x4*>(&lds[B][0][pl][ldsoff[i]]) = sa[S][pl][i];
+        *reinterpret_cast<u32x4*>(&lds[B][1][pl][ldsoff[i]]) = sb[S][pl][i];
+      }
+  };
+  // the MFMAs of the chunk staged in LDS buffer `buf`
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < STEPS; ++ks) {
       const int kbyte = (ks * KC + VEC * fg) * (int)sizeof(op_t);
@@ -219,16 +219,53 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
           }
         }
     }
-    if (more) {
-#pragma unroll
-      for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-        for (int i = 0; i < NS; ++i) {
-          *reinterpret_cast<u32x4*>(&lds[buf ^ 1][0][pl][ldsoff[i]]) = sa[pl][i];
-          *reinterpret_cast<u32x4*>(&lds[buf ^ 1][1][pl][ldsoff[i]]) = sb[pl][i];
-        }
-    }
+  };
+  constexpr Tag<0> T0{};
+  constexpr Tag<1> T1{};
+
+  if constexpr (DEPTH == 2) {
+    // Chunk k travels in register set k % 2 and LDS buffer k % 2.  Loads are
+    // issued unconditionally, past the last chunk as repeats of it, so that
+    // no branch separates a load from the wait for it.
+    // The loop runs over whole pairs of chunks so that no exit test sits
+    // between a load and the store that consumes it (the compiler would sink
+    // the load past the test), and the scheduling barriers keep each step's
+    // loads ahead of its MFMAs and its LDS stores after them.
+    const int64_t last = nchunks - 1;
+    gload(T0, 0);
+    gload(T1, min((int64_t)1, last));
+    lstore(T0, T0);
     __syncthreads();
+    for (int64_t c = 0; c + 1 < nchunks; c += 2) {
+      gload(T0, min(c + 2, last));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      __builtin_amdgcn_sched_barrier(0);
+      lstore(T1, T1);  // chunk c + 1
+      __syncthreads();
+      gload(T1, min(c + 3, last));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      __builtin_amdgcn_sched_barrier(0);
+      lstore(T0, T0);  // chunk c + 2
+      __syncthreads();
+    }
+    if (nchunks & 1) compute(0);  // the last chunk, staged in buffer 0
+  } else {
+    gload(T0, 0);
+    lstore(T0, T0);
+    __syncthreads();
+    for (int64_t c = 0; c < nchunks; ++c) {
+      const int buf = (int)(c & 1);
+      const bool more = c + 1 < nchunks;
+      if (more) gload(T0, c + 1);
+      compute(buf);
+      if (more) {
+        if (buf) lstore(T0, T0);
+        else lstore(T0, T1);
+      }
+      __syncthreads();
+    }
   }
 
   // Epilogue: lane holds D[acc_row(lane / 16, r)][lane % 16] of each 16 x 16 tile.
