@@ -283,11 +283,6 @@ __global__ void pad_kernel(const double* __restrict__ src, int64_t rows, int64_t
   }
 }
 
-template <typename OP>
-__global__ void to_op_kernel(const double* __restrict__ src, int64_t count, OP* __restrict__ dst) {
-  GRID_STRIDE(e, count) dst[e] = cvt_from_double<OP>(src[e]);
-}
-
 __global__ void scores_kernel(const double* __restrict__ P, int64_t rows, int64_t m, int64_t mp,
                               float* __restrict__ out) {
   GRID_STRIDE(e, rows * m) {
@@ -554,24 +549,29 @@ __global__ void to_wop_bf16_kernel(const double* __restrict__ src, int64_t nblk,
     dst[t + mp * spad] = lo;
   }
 }
+template <typename T>
+__global__ void to_wop_kernel(const double* __restrict__ src, int64_t nblk, int64_t spad,
+                              int64_t mp, T* __restrict__ dst) {
+  const int64_t per = spad * mp;
+  GRID_STRIDE(e, nblk * per) {
+    const int64_t b = e / per, rem = e - b * per;
+    const int64_t f = rem / mp, c = rem - f * mp;
+    dst[(b * mp + c) * spad + f] = (T)src[e];
+  }
+}
 }  // namespace
 
 hipError_t to_wop(int prec, const double* src, int64_t nblk, int64_t spad, int64_t mp, void* dst,
                   hipStream_t st) {
-  if (prec != BS_PREC_BF16) return to_op(prec, src, nblk * spad * mp, dst, st);
-  if (nblk * spad * mp == 0) return hipSuccess;
-  to_wop_bf16_kernel<<<grid_for(nblk * spad * mp), 256, 0, st>>>(src, nblk, spad, mp,
-                                                                 (uint16_t*)dst);
-  return hipGetLastError();
-}
-
-hipError_t to_op(int prec, const double* src, int64_t count, void* dst, hipStream_t st) {
+  const int64_t count = nblk * spad * mp;
   if (count == 0) return hipSuccess;
-  unsigned g = grid_for(count);
-  if (prec == BS_PREC_F64)
-    to_op_kernel<double><<<g, 256, 0, st>>>(src, count, (double*)dst);
+  const unsigned g = grid_for(count);
+  if (prec == BS_PREC_BF16)
+    to_wop_bf16_kernel<<<g, 256, 0, st>>>(src, nblk, spad, mp, (uint16_t*)dst);
+  else if (prec == BS_PREC_F64)
+    to_wop_kernel<double><<<g, 256, 0, st>>>(src, nblk, spad, mp, (double*)dst);
   else
-    to_op_kernel<float><<<g, 256, 0, st>>>(src, count, (float*)dst);
+    to_wop_kernel<float><<<g, 256, 0, st>>>(src, nblk, spad, mp, (float*)dst);
   return hipGetLastError();
 }
 

@@ -314,8 +314,8 @@ solve_kernel(const double* __restrict__ Q, int64_t S, int C, int b0, const int64
           const int64_t tcol = ((int64_t)i * 2 * mp + nt * 16 + fr) * spad + coff[j] + row;
           Wop[tcol] = hi;
           Wop[tcol + mp * spad] = lo;
-        } else {
-          Wop[o] = (OUT)w;
+        } else {  // [i][mp][spad], like the BF16 planes
+          Wop[((int64_t)i * mp + nt * 16 + fr) * spad + coff[j] + row] = (OUT)w;
         }
       }
     }
@@ -430,8 +430,8 @@ solve_wide_kernel(const double* __restrict__ Q, int64_t S, int C, int b0,
             const int64_t tcol = ((int64_t)i * 2 * mp + nt * 16 + fr) * spad + coff[j] + row;
             Wop[tcol] = hi;
             Wop[tcol + mp * spad] = lo;
-          } else {
-            Wop[o] = (OUT)w;
+          } else {  // [i][mp][spad], like the BF16 planes
+            Wop[((int64_t)i * mp + nt * 16 + fr) * spad + coff[j] + row] = (OUT)w;
           }
         }
       }

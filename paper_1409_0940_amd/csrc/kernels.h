@@ -38,10 +38,10 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
 // The padded feature index: feature block j occupies [coff_j, coff_j + s_j)
 // with coff_j a multiple of 64; spad is the padded total; pad entries are 0.
 
-// Product operands.  FP64, FP32 and BF16X3 multiply R as [n][mp] and W' as
-// [i][spad][mp] in the operand type (double, float, float).  BF16 multiplies
-// BF16 head and residual planes of both, stored transposed: R as
-// [plane][mp][ldr] with ldr = R * nbpad and row block i in the segment
+// Product operands.  FP64, FP32 and BF16X3 multiply R as [n][mp] and W'
+// transposed, [i][mp][spad], in the operand type (double, float, float).
+// BF16 multiplies BF16 head and residual planes of both, stored transposed:
+// R as [plane][mp][ldr] with ldr = R * nbpad and row block i in the segment
 // starting at i * nbpad (zero for at least 32 rows past its rows), W' as
 // [i][plane][mp][spad].
 
@@ -60,8 +60,9 @@ hipError_t reduce_rhs(int prec, const void* part, int64_t nsplit_max, int64_t n,
                       const double* mup, const double* U, double* rhs, hipStream_t st);
 // For the row blocks i in [i0, i1) of the partition of n rows into R blocks:
 // Pout[r][c] = sum_f Z[r][f] * W'_i[f][c], f < spad (a multiple of 64),
-// c < mp.  Z points at row floor(i0 n / R), Pout at row 0; W'_i starts
-// wop_stride operand elements after W'_{i-1} (0: one W' for every block).
+// c < mp, W'_i in the transposed operand layout with row stride spad.  Z
+// points at row floor(i0 n / R), Pout at row 0; W'_i starts wop_stride
+// operand elements after W'_{i-1} (0: one W' for every block).
 hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t n, int R, int i0, int i1,
               int64_t spad, const void* Wop, int64_t wop_stride, int64_t mp, double* Pout,
               hipStream_t st);
@@ -101,8 +102,6 @@ hipError_t unpad(const double* src, int64_t rows, int64_t m, int64_t mp, double*
                  hipStream_t st);
 hipError_t pad(const double* src, int64_t rows, int64_t m, int64_t mp, double* dst,
                hipStream_t st);
-// Operand copy of a padded FP64 array (rows x mp) into op type.
-hipError_t to_op(int prec, const double* src, int64_t count, void* dst, hipStream_t st);
 // Penalty adaptation: out[0..4] = ||Dbar||^2, ||Wc - Wbar||^2,
 // sum_i ||Wp_i - Wbar||^2, ||Obar - Obar_prev||^2, ||Wbar - Wbar_prev||^2
 // (fixed-order sums; part holds 5 nb partials).

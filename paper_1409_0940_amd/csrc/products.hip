@@ -123,12 +123,13 @@ __global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max
 }
 
 // ---------------------------------------------------------------------------
-// Forward product for one row block: P[r][c] = sum_f Z[r][f] Wop[f][c].
-// MFMA view: M = rows, N = outputs, K = features.  A lane loads 4 adjacent
-// features of its row; instruction t of a step pairs feature 4 g + t with
-// row t of the matching Wop slice.  Each wave owns 32 rows (two M tiles
-// sharing every Wop value), a workgroup 128; U fragment steps are loaded
-// before they are consumed.  Pad columns of Z and pad rows of Wop are zero.
+// Forward product for one row block: P[r][c] = sum_f Z[r][f] W'[f][c], with
+// W' stored transposed, Wt[c][f] (row stride s16).  MFMA view: M = rows,
+// N = outputs, K = features.  A lane loads 4 adjacent features of its row of
+// Z and the same 4 features of its column of Wt; instruction t of a step
+// pairs feature 4 g + t of both.  Each wave owns 32 rows (two M tiles sharing
+// every W' value), a workgroup 128; U fragment steps are loaded before they
+// are consumed.  Pad columns of Z and pad features of W' are zero.
 // ---------------------------------------------------------------------------
 template <typename ZT, int NTC, int U>
 __global__ void __launch_bounds__(256)
@@ -160,12 +161,11 @@ zw_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const auto* wb = Wop + (f0 + 16 * u + 4 * fg) * mp + fr;
+        const auto* wb = Wop + (int64_t)fr * s16 + f0 + 16 * u + 4 * fg;
 #pragma unroll
         for (int t = 0; t < NTC; ++t) {
           const int nt = min(nc0 + t, ntiles - 1);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) b[u][t][q] = wb[q * mp + nt * 16];
+          load_z4<op_t>(wb + (int64_t)nt * 16 * s16, b[u][t]);
         }
       }
       __builtin_amdgcn_sched_barrier(0);
