@@ -128,18 +128,25 @@ __global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max
 // N = outputs, K = features.  A lane loads 4 adjacent features of its row of
 // Z and the same 4 features of its column of Wt; instruction t of a step
 // pairs feature 4 g + t of both.  Each wave owns 32 rows (two M tiles sharing
-// every W' value), a workgroup 128; U fragment steps are loaded before they
-// are consumed.  Pad columns of Z and pad features of W' are zero.
+// every W' value); U fragment steps of 16 features are loaded before they are
+// consumed.  Pad columns of Z and pad features of W' are zero.
+// KS = 1: a workgroup owns 128 rows, each wave all features of its 32.
+// KS = 4: the 4 waves share 32 rows and take every fourth group of 16 U
+// features, so each round reads 4 x 16 U adjacent features of every row (the
+// DRAM locality of the transpose product) instead of 16 U features of 128
+// rows; their partial sums are added in wave order through LDS.
 // ---------------------------------------------------------------------------
-template <typename ZT, int NTC, int U>
+template <typename ZT, int NTC, int U, int KS>
 __global__ void __launch_bounds__(256)
 zw_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
           const typename ZAcc<ZT>::type* __restrict__ Wop, int64_t mp, double* __restrict__ Pout) {
   using op_t = typename ZAcc<ZT>::type;
   using accv = typename V4<op_t>::type;
+  static_assert(KS == 1 || KS == 4, "K split over 1 or 4 waves");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int64_t r0 = KS == 1 ? (int64_t)blockIdx.x * 128 + wave * 32 : (int64_t)blockIdx.x * 32;
+  const int64_t fbeg = KS == 1 ? 0 : (int64_t)wave * 16 * U;
   const int nc0 = blockIdx.y * NTC;
   const int ntiles = (int)(mp / 16);
   accv acc[2][NTC];
@@ -152,7 +159,7 @@ zw_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
   if (r0 < rows) {
     const auto* z0 = Z + min(r0 + fr, rows - 1) * ldz + 4 * fg;
     const auto* z1 = Z + min(r0 + 16 + fr, rows - 1) * ldz + 4 * fg;
-    for (int64_t f0 = 0; f0 < s16; f0 += 16 * U) {
+    for (int64_t f0 = fbeg; f0 < s16; f0 += KS * 16 * U) {
       op_t a0[U][4], a1[U][4], b[U][NTC][4];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -179,6 +186,27 @@ zw_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
             acc[1][t] = mfma4(a1[u][q], b[u][t][q], acc[1][t]);
           }
     }
+  }
+  if constexpr (KS > 1) {  // r0 is uniform over the workgroup: every wave gets here
+    __shared__ op_t red[KS - 1][2 * NTC * 4][64];
+    if (wave > 0) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < NTC; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[wave - 1][(h * NTC + t) * 4 + r][lane] = acc[h][t][r];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < KS - 1; ++w)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < NTC; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[h][t][r] += red[w][(h * NTC + t) * 4 + r][lane];
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -388,20 +416,26 @@ ztr_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64
 // W'_i comes as BF16 head and residual planes stored transposed,
 // Wt[p][c][f] (plane stride mp * s), and both planes are multiplied.
 // A lane loads 8 adjacent features of one row of Z and of one column of each
-// plane; a wave owns MT 16-row tiles, a workgroup 4 MT of them.
+// plane; a wave owns MT 16-row tiles.  KS = 1: a workgroup owns 4 MT tiles,
+// each wave all features of its own.  KS = 4: the 4 waves share MT tiles and
+// take every fourth group of 32 U features (4 x 32 U adjacent features of
+// each row per round, as in zw_kernel), partial sums added in wave order.
 // ---------------------------------------------------------------------------
-template <int NTC, int MT, int U>
+template <int NTC, int MT, int U, int KS>
 __global__ void __launch_bounds__(256)
 zw_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R, int i0, int64_t s,
                const uint16_t* __restrict__ Wt, int64_t wt_stride, int64_t mp,
                double* __restrict__ Pout) {
+  static_assert(KS == 1 || KS == 4, "K split over 1 or 4 waves");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
   const int i = i0 + (int)blockIdx.y;
   const int64_t gi = (int64_t)i * n / R, ni = (int64_t)(i + 1) * n / R - gi;
   const int64_t zi = gi - (int64_t)i0 * n / R;   // first row of block i in Z
-  const int64_t row0 = (int64_t)blockIdx.x * (64 * MT) + wave * (16 * MT);
-  if (row0 >= ni) return;
+  const int64_t row0 = KS == 1 ? (int64_t)blockIdx.x * (64 * MT) + wave * (16 * MT)
+                               : (int64_t)blockIdx.x * (16 * MT);
+  if (row0 >= ni) return;  // with KS = 4 uniform over the workgroup
+  const int64_t kbeg = KS == 1 ? 0 : (int64_t)wave * 32 * U;
   const int nc0 = blockIdx.z * NTC;
   const int ntiles = (int)(mp / 16);
   const uint16_t* Wb = Wt + (int64_t)i * wt_stride;
@@ -422,7 +456,7 @@ zw_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R, in
 #pragma unroll
     for (int t = 0; t < NTC; ++t) acc[a][t] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t k0 = 0; k0 < s; k0 += 32 * U) {
+  for (int64_t k0 = kbeg; k0 < s; k0 += KS * 32 * U) {
     u32x4 a[U][MT], b[U][NTC][2];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -445,6 +479,27 @@ zw_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R, in
           acc[m][t] = mfma_bf16x8(a[u][m], b[u][t][0], acc[m][t]);
           acc[m][t] = mfma_bf16x8(a[u][m], b[u][t][1], acc[m][t]);
         }
+  }
+  if constexpr (KS > 1) {
+    __shared__ float red[KS - 1][MT * NTC * 4][64];
+    if (wave > 0) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NTC; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[wave - 1][(m * NTC + t) * 4 + r][lane] = acc[m][t][r];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < KS - 1; ++w)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NTC; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[m][t][r] += red[w][(m * NTC + t) * 4 + r][lane];
   }
 #pragma unroll
   for (int m = 0; m < MT; ++m)
@@ -793,9 +848,12 @@ static void launch_zw(const void* Z, int64_t ldz, int64_t rows, int64_t s16, con
                       int64_t mp, double* Pout, hipStream_t st) {
   using op_t = typename ZAcc<ZT>::type;
   const int ntiles = (int)(mp / 16);
-  dim3 g((unsigned)((rows + 127) / 128), (unsigned)((ntiles + NTC - 1) / NTC));
-  zw_kernel<ZT, NTC, zw_unroll<NTC>()><<<g, 256, 0, st>>>((const ZT*)Z, ldz, rows, s16,
-                                                         (const op_t*)Wop, mp, Pout);
+  // up to two output tiles: HBM-bound, K split over the waves for locality
+  constexpr int KS = NTC <= 2 ? 4 : 1;
+  const int64_t wrows = KS == 1 ? 128 : 32;
+  dim3 g((unsigned)((rows + wrows - 1) / wrows), (unsigned)((ntiles + NTC - 1) / NTC));
+  zw_kernel<ZT, NTC, zw_unroll<NTC>(), KS><<<g, 256, 0, st>>>((const ZT*)Z, ldz, rows, s16,
+                                                             (const op_t*)Wop, mp, Pout);
 }
 
 template <typename ZT>
@@ -822,10 +880,12 @@ static void launch_zw_bf16(const void* Z, int64_t ldz, int64_t n, int R, int i0,
                            int64_t nmax, int64_t s, const void* Wt, int64_t wt_stride, int64_t mp,
                            double* Pout, hipStream_t st) {
   const int ntiles = (int)(mp / 16);
-  dim3 g((unsigned)((nmax + 64 * MT - 1) / (64 * MT)), (unsigned)nblk,
+  constexpr int KS = NTC <= 2 ? 4 : 1;  // K split over the waves for DRAM locality
+  const int64_t wrows = (KS == 1 ? 64 : 16) * MT;
+  dim3 g((unsigned)((nmax + wrows - 1) / wrows), (unsigned)nblk,
          (unsigned)((ntiles + NTC - 1) / NTC));
-  zw_bf16_kernel<NTC, MT, U><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, n, R, i0, s,
-                                                (const uint16_t*)Wt, wt_stride, mp, Pout);
+  zw_bf16_kernel<NTC, MT, U, KS><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, n, R, i0, s,
+                                                    (const uint16_t*)Wt, wt_stride, mp, Pout);
 }
 
 template <int NTC>
