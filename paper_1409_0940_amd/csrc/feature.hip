@@ -103,10 +103,17 @@ __global__ void check_finite_kernel(const float* __restrict__ p, int64_t count, 
 // ---------------------------------------------------------------------------
 template <int V> struct Tag { static constexpr int value = V; };
 template <int P> constexpr int planes() { return P == BS_PREC_BF16X3 ? 2 : 1; }
-template <int P> constexpr int krow_bytes() { return P == BS_PREC_BF16X3 ? 64 : 128; }
+// Bytes of one staged k-chunk per row (per plane).  FP32 stages 16 values so
+// that four 40 KB workgroups fill the LDS of a CU (4 waves per SIMD to cover
+// each other's barrier and load waits); FP64 needs 128 bytes for one step.
+template <int P> constexpr int krow_bytes() {
+  return (P == BS_PREC_BF16X3 || P == BS_PREC_F32) ? 64 : 128;
+}
+// Workgroups per CU the register budget is sized for.
+template <int P> constexpr int regen_wgs() { return P == BS_PREC_F32 ? 4 : 2; }
 
 template <int P, typename ZT>
-__global__ void __launch_bounds__(NTHREADS, 2)
+__global__ void __launch_bounds__(NTHREADS, regen_wgs<P>())
 regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t rows,
              const typename Prec<P>::op_t* __restrict__ Wt, int64_t wps, int64_t cols,
              const typename Prec<P>::acc_t* __restrict__ bias, int64_t Kp,
@@ -157,8 +164,9 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
   const int64_t xpb = xps * (int64_t)sizeof(op_t), wpb = wps * (int64_t)sizeof(op_t);
   const int64_t nchunks = Kp / BK;
   // Global loads run DEPTH chunks ahead of the MFMAs through DEPTH register
-  // sets (the FP64 variant has no registers to spare for a second set).
-  constexpr int DEPTH = P == BS_PREC_F64 ? 1 : 2;
+  // sets (FP64 has no registers to spare for a second set; FP32 spends its
+  // registers on occupancy instead).
+  constexpr int DEPTH = (P == BS_PREC_F64 || P == BS_PREC_F32) ? 1 : 2;
   u32x4 sa[DEPTH][NPL][NS], sb[DEPTH][NPL][NS];
 
   accv acc[4][4];
