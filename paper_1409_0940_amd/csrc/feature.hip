@@ -492,7 +492,12 @@ inline unsigned grid_1d(int64_t count, int threads, int64_t cap = 65536) {
 }  // namespace
 
 int64_t padded_k(int prec, int64_t d) {
-  const int64_t bk = (prec == BS_PREC_BF16X3 ? 64 : 128) / (int64_t)op_bytes(prec);
+  // a whole number of the regeneration's k-chunks (the wide BF16 kernel's
+  // chunk is 128 bytes, as regen_kernel's BF16 one)
+  int krow = 128;
+  if (prec == BS_PREC_F32) krow = krow_bytes<BS_PREC_F32>();
+  else if (prec == BS_PREC_BF16X3) krow = krow_bytes<BS_PREC_BF16X3>();
+  const int64_t bk = krow / (int64_t)op_bytes(prec);
   return ((d + bk - 1) / bk) * bk;
 }
 
