@@ -328,7 +328,9 @@ constexpr int WTJ = 4;                           // feature tiles per wave
 // Raw buffer descriptor over [p, p + bytes): loads past the end return zero.
 // p and bytes are wave-uniform; rebuilding them from readfirstlane halves
 // keeps the descriptor in scalar registers even where their arithmetic was
-// done in vector registers.
+// done in vector registers.  wide_load builds it at every call: a descriptor
+// kept live across the k-loop was given vector registers, which wraps each
+// load in a readfirstlane loop (about 90 instructions and 8 branches a chunk).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t wide_rsrc(const void* p, int64_t bytes) {
   const uint64_t a = reinterpret_cast<uint64_t>(p);
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
@@ -338,9 +340,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t wide_rsrc(const void* p, int64
   return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, nb, 0x00020000);
 }
 
-__device__ __forceinline__ void wide_load(__amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb,
+__device__ __forceinline__ void wide_load(const void* pa, int64_t na, const void* pb, int64_t nbb,
                                           int voff, int rowb, int koff, u32x4 (&sa)[WNS],
                                           u32x4 (&sb)[WNS]) {
+  const __amdgpu_buffer_rsrc_t ra = wide_rsrc(pa, na), rb = wide_rsrc(pb, nbb);
 #pragma unroll
   for (int i = 0; i < WNS; ++i)
     sa[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
@@ -418,8 +421,10 @@ regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
   const int rowb = (int)(Kp * 2);
   const int voff = (tid / WSEG) * rowb + (tid % WSEG) * 16;
   const int lofs = (tid / WSEG) * WPITCH + (tid % WSEG) * 16;
-  const __amdgpu_buffer_rsrc_t ra = wide_rsrc(Xp + row0 * Kp, min<int64_t>(rows - row0, WBM) * rowb);
-  const __amdgpu_buffer_rsrc_t rb = wide_rsrc(Wt + col0 * Kp, min<int64_t>(cols - col0, WBN) * rowb);
+  const void* pa = Xp + row0 * Kp;
+  const int64_t na = min<int64_t>(rows - row0, WBM) * rowb;
+  const void* pb = Wt + col0 * Kp;
+  const int64_t nbb = min<int64_t>(cols - col0, WBN) * rowb;
 
   v4f acc[TJ][8];   // [feature tile][row tile]
 #pragma unroll
@@ -429,13 +434,13 @@ regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
 
   const int64_t nchunks = Kp / BK;
   u32x4 sa[WNS], sb[WNS];
-  wide_load(ra, rb, voff, rowb, 0, sa, sb);
+  wide_load(pa, na, pb, nbb, voff, rowb, 0, sa, sb);
   wide_store(lds[0], lofs, sa, sb);
   __syncthreads();
   for (int64_t c = 0; c < nchunks; ++c) {
     const int buf = (int)(c & 1);
     const bool more = c + 1 < nchunks;
-    if (more) wide_load(ra, rb, voff, rowb, (int)(c + 1) * WKROW, sa, sb);
+    if (more) wide_load(pa, na, pb, nbb, voff, rowb, (int)(c + 1) * WKROW, sa, sb);
     wide_mfma(lds[buf], wm, wn, fr, fg, acc);
     if (more) wide_store(lds[buf ^ 1], lofs, sa, sb);
     __syncthreads();
