@@ -367,30 +367,44 @@ __device__ __forceinline__ void wide_store(unsigned char* buf, int lofs, const u
 // The MFMA work of one staged chunk (64 k values, two 16x16x32 steps).
 __device__ __forceinline__ void wide_mfma(const unsigned char* buf, int wm, int wn, int fr, int fg,
                                           v4f (&acc)[WTJ][8]) {
-#pragma unroll
-  for (int ks = 0; ks < WKROW / 64; ++ks) {
-    const int kbyte = ks * 64 + 16 * fg;
-    Frag<BS_PREC_BF16> fw[WTJ];
+  // quarter q = (k-step ks, row half h) of the chunk's two k-steps; its
+  // fragments are read while the previous quarter's 16 products run
+  static_assert(WKROW == 128, "two 32-value k-steps per chunk");
+  auto load_w = [&](int ks, Frag<BS_PREC_BF16> (&fw)[WTJ]) {
 #pragma unroll
     for (int j = 0; j < WTJ; ++j)
       fw[j] = load_frag<BS_PREC_BF16>(reinterpret_cast<const uint16_t*>(
-          buf + (WBM + wn * (16 * WTJ) + j * 16 + fr) * WPITCH + kbyte));
-    // row tiles in two halves of 4: fewer fragments live at once
+          buf + (WBM + wn * (16 * WTJ) + j * 16 + fr) * WPITCH + ks * 64 + 16 * fg));
+  };
+  auto load_x = [&](int ks, int h, Frag<BS_PREC_BF16> (&fx)[4]) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      Frag<BS_PREC_BF16> fx[4];
+    for (int i = 0; i < 4; ++i)
+      fx[i] = load_frag<BS_PREC_BF16>(reinterpret_cast<const uint16_t*>(
+          buf + (wm * 128 + (4 * h + i) * 16 + fr) * WPITCH + ks * 64 + 16 * fg));
+  };
+  auto prod = [&](int h, const Frag<BS_PREC_BF16> (&fw)[WTJ], const Frag<BS_PREC_BF16> (&fx)[4]) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        fx[i] = load_frag<BS_PREC_BF16>(reinterpret_cast<const uint16_t*>(
-            buf + (wm * 128 + (4 * h + i) * 16 + fr) * WPITCH + kbyte));
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < WTJ; ++j) mfma_step(acc[j][4 * h + i], fw[j], fx[i]);
-      // keep the next fragment loads behind these products (registers)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
+      for (int j = 0; j < WTJ; ++j) mfma_step(acc[j][4 * h + i], fw[j], fx[i]);
+  };
+  Frag<BS_PREC_BF16> fw0[WTJ], fw1[WTJ], xa[4], xb[4];
+  load_w(0, fw0);
+  load_x(0, 0, xa);
+  load_x(0, 1, xb);
+  __builtin_amdgcn_sched_barrier(0);
+  prod(0, fw0, xa);
+  __builtin_amdgcn_sched_barrier(0);
+  load_w(1, fw1);
+  load_x(1, 0, xa);
+  __builtin_amdgcn_sched_barrier(0);
+  prod(1, fw0, xb);
+  __builtin_amdgcn_sched_barrier(0);
+  load_x(1, 1, xb);
+  __builtin_amdgcn_sched_barrier(0);
+  prod(0, fw1, xa);
+  __builtin_amdgcn_sched_barrier(0);
+  prod(1, fw1, xb);
 }
 
 __global__ void __launch_bounds__(WNT, 1)
