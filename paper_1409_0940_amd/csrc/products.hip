@@ -563,12 +563,18 @@ ztr_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, i
 #pragma unroll
     for (int t = 0; t < NTC; ++t) acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  // Z block of the step at row rb: rows rb + 4 fg + 0..3, features fl .. fl + 3
-  u32x2 zc[4], zn[4];
+  // One 16x16x32 product per output tile and feature takes k = 32 as the 16
+  // rows of the step against R's head plane (k < 16) and against its residual
+  // plane (k >= 16): lane group fg holds k = 8 fg .. 8 fg + 7, i.e. rows
+  // 8 (fg & 1) .. + 7 of plane fg / 2.  Z block of the step at row rb: rows
+  // rb + 8 (fg & 1) + 0..7, features fl .. fl + 3 (groups fg and fg ^ 2 load
+  // the same rows).
+  const int rsub = 8 * (fg & 1);
+  u32x2 zc[8], zn[8];
   u32x4 stg[NSEG];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
-    zc[t] = *reinterpret_cast<const u32x2*>(Z + min(rbeg + 4 * fg + t, rows - 1) * ldz + fl);
+  for (int t = 0; t < 8; ++t)
+    zc[t] = *reinterpret_cast<const u32x2*>(Z + min(rbeg + rsub + t, rows - 1) * ldz + fl);
 #pragma unroll
   for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u]);
 #pragma unroll
@@ -580,39 +586,35 @@ ztr_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, i
     const bool more = rb + 16 < rend;
     if (more) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        zn[t] = *reinterpret_cast<const u32x2*>(Z + min(rb + 16 + 4 * fg + t, rows - 1) * ldz + fl);
+      for (int t = 0; t < 8; ++t)
+        zn[t] = *reinterpret_cast<const u32x2*>(Z + min(rb + 16 + rsub + t, rows - 1) * ldz + fl);
 #pragma unroll
       for (int u = 0; u < NSEG; ++u)
         stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u] + (rb + 16 - rbeg));
     }
-    u32x2 a[4];
-    a[0].x = __builtin_amdgcn_perm(zc[1].x, zc[0].x, 0x05040100u);
-    a[0].y = __builtin_amdgcn_perm(zc[3].x, zc[2].x, 0x05040100u);
-    a[1].x = __builtin_amdgcn_perm(zc[1].x, zc[0].x, 0x07060302u);
-    a[1].y = __builtin_amdgcn_perm(zc[3].x, zc[2].x, 0x07060302u);
-    a[2].x = __builtin_amdgcn_perm(zc[1].y, zc[0].y, 0x05040100u);
-    a[2].y = __builtin_amdgcn_perm(zc[3].y, zc[2].y, 0x05040100u);
-    a[3].x = __builtin_amdgcn_perm(zc[1].y, zc[0].y, 0x07060302u);
-    a[3].y = __builtin_amdgcn_perm(zc[3].y, zc[2].y, 0x07060302u);
-    const int roff = 8 * fg;                        // rows 4 fg .. 4 fg + 3, 2 bytes each
+    // a[q] = feature fl + q at the lane's 8 rows (pairs of rows per dword)
+    u32x4 a[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      a[0][h] = __builtin_amdgcn_perm(zc[2 * h + 1].x, zc[2 * h].x, 0x05040100u);
+      a[1][h] = __builtin_amdgcn_perm(zc[2 * h + 1].x, zc[2 * h].x, 0x07060302u);
+      a[2][h] = __builtin_amdgcn_perm(zc[2 * h + 1].y, zc[2 * h].y, 0x05040100u);
+      a[3][h] = __builtin_amdgcn_perm(zc[2 * h + 1].y, zc[2 * h].y, 0x07060302u);
+    }
+    // R fragment: plane fg / 2, rows 8 (fg & 1) .. + 7 of the stage (16 bytes)
+    const int boff = (fg >> 1) * NC * PITCH + 2 * rsub;
 #pragma unroll
     for (int t = 0; t < NTC; ++t) {
-      const u32x2 bh = *reinterpret_cast<const u32x2*>(&lds[buf][(t * 16 + fr) * PITCH + roff]);
-      const u32x2 bl =
-          *reinterpret_cast<const u32x2*>(&lds[buf][(NC + t * 16 + fr) * PITCH + roff]);
+      const u32x4 bv = *reinterpret_cast<const u32x4*>(&lds[buf][boff + (t * 16 + fr) * PITCH]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        acc[q][t] = mfma_bf16x4(a[q], bh, acc[q][t]);
-        acc[q][t] = mfma_bf16x4(a[q], bl, acc[q][t]);
-      }
+      for (int q = 0; q < 4; ++q) acc[q][t] = mfma_bf16x8(a[q], bv, acc[q][t]);
     }
     if (more) {
 #pragma unroll
       for (int u = 0; u < NSEG; ++u)
         if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[buf ^ 1][ldst[u]]) = stg[u];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) zc[t] = zn[t];
+      for (int t = 0; t < 8; ++t) zc[t] = zn[t];
     }
     __syncthreads();
   }
