@@ -407,6 +407,11 @@ __device__ __forceinline__ void wide_mfma(const unsigned char* buf, int wm, int 
   prod(1, fw1, xb);
 }
 
+// Persistent: the grid holds one workgroup per CU and each walks a list of
+// tiles.  Workgroups are dealt round-robin over the 8 XCDs; workgroup b takes
+// every (grid / 8)-th tile of XCD b % 8's contiguous tile range, so the tiles
+// an XCD runs at once are neighbours that share its L2.  The next tile's
+// first chunk is loaded during the current tile's last chunk and epilogue.
 __global__ void __launch_bounds__(WNT, 1)
 regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
                        const uint16_t* __restrict__ Wt, int64_t cols,
@@ -418,87 +423,130 @@ regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
 
   const int tiles_m = (int)((rows + WBM - 1) / WBM);
   const int tiles_n = (int)((cols + WBN - 1) / WBN);
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  const int per_group = GROUP_M * tiles_n;
-  const int g = t / per_group;
-  const int first_m = g * GROUP_M;
-  const int gsize = min(GROUP_M, tiles_m - first_m);
-  const int tm = first_m + (t % per_group) % gsize;
-  const int tn = (t % per_group) / gsize;
-  const int64_t row0 = (int64_t)tm * WBM, col0 = (int64_t)tn * WBN;
+  const int T = tiles_m * tiles_n;
+  // this XCD's tile range [tbeg, tend), split as in xcd_remap
+  const int x = (int)(blockIdx.x % 8), wpx = (int)(gridDim.x / 8);
+  const int per = (T + 7) / 8, full = T - (per - 1) * 8;
+  const int tbeg = x < full ? x * per : full * per + (x - full) * (per - 1);
+  const int tend = tbeg + (x < full ? per : per - 1);
+  int t = tbeg + (int)(blockIdx.x / 8);
+  if (t >= tend) return;  // uniform over the workgroup
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 2, wn = wave & 3;     // 2 x 4 waves
   const int fr = lane & 15, fg = lane >> 4;
-
   // staging: thread tid moves segment tid % 8 of rows tid / 8 + 64 i
   const int rowb = (int)(Kp * 2);
   const int voff = (tid / WSEG) * rowb + (tid % WSEG) * 16;
   const int lofs = (tid / WSEG) * WPITCH + (tid % WSEG) * 16;
-  const void* pa = Xp + row0 * Kp;
-  const int64_t na = min<int64_t>(rows - row0, WBM) * rowb;
-  const void* pb = Wt + col0 * Kp;
-  const int64_t nbb = min<int64_t>(cols - col0, WBN) * rowb;
-
-  v4f acc[TJ][8];   // [feature tile][row tile]
-#pragma unroll
-  for (int j = 0; j < TJ; ++j)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc[j][i] = v4f{0.f, 0.f, 0.f, 0.f};
-
+  const int per_group = GROUP_M * tiles_n;
+  auto origin = [&](int tt, int64_t& r0, int64_t& c0) {
+    const int g = tt / per_group;
+    const int first_m = g * GROUP_M;
+    const int gsize = min(GROUP_M, tiles_m - first_m);
+    r0 = (int64_t)(first_m + (tt % per_group) % gsize) * WBM;
+    c0 = (int64_t)((tt % per_group) / gsize) * WBN;
+  };
+  int64_t row0, col0;
+  origin(t, row0, col0);
   const int64_t nchunks = Kp / BK;
   u32x4 sa[WNS], sb[WNS];
-  wide_load(pa, na, pb, nbb, voff, rowb, 0, sa, sb);
+  wide_load(Xp + row0 * Kp, min<int64_t>(rows - row0, WBM) * rowb, Wt + col0 * Kp,
+            min<int64_t>(cols - col0, WBN) * rowb, voff, rowb, 0, sa, sb);
   wide_store(lds[0], lofs, sa, sb);
   __syncthreads();
-  for (int64_t c = 0; c < nchunks; ++c) {
-    const int buf = (int)(c & 1);
-    const bool more = c + 1 < nchunks;
-    if (more) wide_load(pa, na, pb, nbb, voff, rowb, (int)(c + 1) * WKROW, sa, sb);
-    wide_mfma(lds[buf], wm, wn, fr, fg, acc);
-    if (more) wide_store(lds[buf ^ 1], lofs, sa, sb);
-    __syncthreads();
-  }
 
-  // Epilogue: lane holds features 4 fg .. 4 fg + 3 of tile j for row fr of
-  // tile i; phase + bias -> cos -> two packed BF16 pairs -> one 8-byte store.
-  // Tiles that cross the row or feature edge store element by element.
-  if (row0 + WBM <= rows && col0 + WBN <= cols) {
+  for (;;) {
+    const void* pa = Xp + row0 * Kp;
+    const int64_t na = min<int64_t>(rows - row0, WBM) * rowb;
+    const void* pb = Wt + col0 * Kp;
+    const int64_t nbb = min<int64_t>(cols - col0, WBN) * rowb;
+    const int tnext = t + wpx;
+    const bool has_next = tnext < tend;
+    int64_t nrow0 = 0, ncol0 = 0;
+    if (has_next) origin(tnext, nrow0, ncol0);
+
+    v4f acc[TJ][8];   // [feature tile][row tile]
 #pragma unroll
-    for (int j = 0; j < TJ; ++j) {
-      const int64_t f = col0 + wn * (16 * TJ) + j * 16 + 4 * fg;
-      const float b0 = bias[f], b1 = bias[f + 1], b2 = bias[f + 2], b3 = bias[f + 3];
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t row = row0 + wm * 128 + i * 16 + fr;
-        uint2 v;
-        v.x = pack_bf16x2(scale * rff_cos_bf16out(acc[j][i][0] + b0),
-                          scale * rff_cos_bf16out(acc[j][i][1] + b1));
-        v.y = pack_bf16x2(scale * rff_cos_bf16out(acc[j][i][2] + b2),
-                          scale * rff_cos_bf16out(acc[j][i][3] + b3));
-        *reinterpret_cast<uint2*>(Z + row * ldz + f) = v;
+      for (int i = 0; i < 8; ++i) acc[j][i] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t c = 0; c < nchunks; ++c) {
+      const int buf = (int)(c & 1);
+      const bool more = c + 1 < nchunks;
+      if (more)
+        wide_load(pa, na, pb, nbb, voff, rowb, (int)(c + 1) * WKROW, sa, sb);
+      else if (has_next)
+        wide_load(Xp + nrow0 * Kp, min<int64_t>(rows - nrow0, WBM) * rowb, Wt + ncol0 * Kp,
+                  min<int64_t>(cols - ncol0, WBN) * rowb, voff, rowb, 0, sa, sb);
+      wide_mfma(lds[buf], wm, wn, fr, fg, acc);
+      if (more) wide_store(lds[buf ^ 1], lofs, sa, sb);
+      __syncthreads();
+    }
+
+    // Epilogue: lane holds features 4 fg .. 4 fg + 3 of tile j for row fr of
+    // tile i; phase + bias -> cos -> two packed BF16 pairs -> one 8-byte store.
+    // Tiles that cross the row or feature edge store element by element.
+    if (row0 + WBM <= rows && col0 + WBN <= cols) {
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        const int64_t f = col0 + wn * (16 * TJ) + j * 16 + 4 * fg;
+        const float b0 = bias[f], b1 = bias[f + 1], b2 = bias[f + 2], b3 = bias[f + 3];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int64_t row = row0 + wm * 128 + i * 16 + fr;
+          uint2 v;
+          v.x = pack_bf16x2(scale * rff_cos_bf16out(acc[j][i][0] + b0),
+                            scale * rff_cos_bf16out(acc[j][i][1] + b1));
+          v.y = pack_bf16x2(scale * rff_cos_bf16out(acc[j][i][2] + b2),
+                            scale * rff_cos_bf16out(acc[j][i][3] + b3));
+          *reinterpret_cast<uint2*>(Z + row * ldz + f) = v;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) {
+        const int64_t f = col0 + wn * (16 * TJ) + j * 16 + 4 * fg;
+        float bj[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bj[r] = bias[min(f + r, cols - 1)];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int64_t row = row0 + wm * 128 + i * 16 + fr;
+          if (row >= rows) continue;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (f + r < cols) {
+              const float z = scale * rff_cos_bf16out(acc[j][i][r] + bj[r]);
+              Z[row * ldz + f + r] = (uint16_t)(pack_bf16x2(z, 0.f) & 0xffffu);
+            }
+        }
       }
     }
-  } else {
-#pragma unroll
-    for (int j = 0; j < TJ; ++j) {
-      const int64_t f = col0 + wn * (16 * TJ) + j * 16 + 4 * fg;
-      float bj[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) bj[r] = bias[min(f + r, cols - 1)];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t row = row0 + wm * 128 + i * 16 + fr;
-        if (row >= rows) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (f + r < cols) {
-            const float z = scale * rff_cos_bf16out(acc[j][i][r] + bj[r]);
-            Z[row * ldz + f + r] = (uint16_t)(pack_bf16x2(z, 0.f) & 0xffffu);
-          }
-      }
-    }
+    if (!has_next) break;
+    // every wave passed the last chunk's barrier: no one reads LDS any more
+    wide_store(lds[0], lofs, sa, sb);
+    __syncthreads();
+    t = tnext;
+    row0 = nrow0;
+    col0 = ncol0;
   }
+}
+
+// Compute units of the current device (queried once per device).
+int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
 }
 
 inline unsigned grid_1d(int64_t count, int threads, int64_t cap = 65536) {
@@ -607,7 +655,9 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
       const int64_t wt = ((rows + WBM - 1) / WBM) * ((cols + WBN - 1) / WBN);
       if (ldz % 4 == 0 && reinterpret_cast<uintptr_t>(Z) % 8 == 0 && wt <= 0x7fffffff &&
           Kp <= ((int64_t)1 << 21)) {
-        regen_bf16_wide_kernel<<<dim3((unsigned)wt), WNT, 0, st>>>(
+        // persistent: one workgroup per CU (a multiple of the 8 XCDs)
+        const int64_t nwg = std::min<int64_t>(std::max(8, cu_count() / 8 * 8), (wt + 7) / 8 * 8);
+        regen_bf16_wide_kernel<<<dim3((unsigned)nwg), WNT, 0, st>>>(
             (const uint16_t*)Xp, rows, (const uint16_t*)Wt, cols, (const float*)bias, Kp,
             (float)scale, (uint16_t*)Z, ldz);
       } else {
