@@ -149,7 +149,7 @@ def main():
                     help="skip the second pass of the serving stream at a fixed penalty")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "runs on a single GPU: --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -30,7 +30,7 @@ def test_prox_l1_brute_force_and_kinks():
 
 def _slsqp(fun, x0, cons):
     # at ftol 1e-15 SLSQP may stop on "positive directional derivative" once
-    # rounding blocks progress; the comparisons below judge the point
+    # rounding blocks progress; the comparisons below check the point
     r = minimize(fun, x0, method="SLSQP", constraints=cons,
                  options={"ftol": 1e-15, "maxiter": 500})
     assert r.status in (0, 8), r.message
