@@ -223,6 +223,101 @@ zw_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
 }
 
 // ---------------------------------------------------------------------------
+// Forward product from an FP32 Z for many output columns.  The transposed W'
+// of a 16-feature step (NC columns x 64 B) is staged once per workgroup into
+// LDS (row pitch 80 B: the 16 columns a fragment read touches fall in
+// distinct banks), double-buffered, and shared by the 4 waves of 32 rows, so
+// W' moves from L2 once per workgroup instead of once per wave; each wave's
+// next Z fragments and the next stage are loaded while the current step's
+// products run.  Same grid, k-permutation and output as zw_kernel (KS = 1).
+// ---------------------------------------------------------------------------
+template <int NTC>
+__global__ void __launch_bounds__(256, 2)
+zw_f32_lds_kernel(const float* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
+                  const float* __restrict__ Wt, int64_t mp, double* __restrict__ Pout) {
+  constexpr int NC = NTC * 16, PITCH = 80;
+  constexpr int SEGS = NC * 4;                     // 16-byte segments per stage
+  constexpr int NSEG = (SEGS + 255) / 256;         // per thread
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][NC * PITCH];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int nc0 = blockIdx.y * NTC;
+  const int ntiles = (int)(mp / 16);
+
+  // staged segment q = tid + 256 u: column q / 4 of the workgroup's NC,
+  // features 4 (q % 4) .. 4 (q % 4) + 3 of the step
+  const float* gsrc[NSEG];
+  int ldst[NSEG];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) {
+    const int q = min(tid + 256 * u, SEGS - 1);
+    const int c = q / 4, part = q % 4;
+    const int64_t col = min(nc0 * 16 + c, (int)mp - 1);
+    gsrc[u] = Wt + col * s16 + part * 4;
+    ldst[u] = tid + 256 * u < SEGS ? c * PITCH + part * 16 : -1;
+  }
+  // rows past the block read its last row (in bounds) and store nothing
+  const float* z0 = Z + min(r0 + fr, rows - 1) * ldz + 4 * fg;
+  const float* z1 = Z + min(r0 + 16 + fr, rows - 1) * ldz + 4 * fg;
+
+  v4f acc[2][NTC];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[h][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  v4f stg[NSEG], a0 = *reinterpret_cast<const v4f*>(z0), a1 = *reinterpret_cast<const v4f*>(z1);
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const v4f*>(gsrc[u]);
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u)
+    if (ldst[u] >= 0) *reinterpret_cast<v4f*>(&lds[0][ldst[u]]) = stg[u];
+  __syncthreads();
+  for (int64_t f0 = 0; f0 < s16; f0 += 16) {
+    const int buf = (int)((f0 >> 4) & 1);
+    const bool more = f0 + 16 < s16;
+    v4f n0 = a0, n1 = a1;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const v4f*>(gsrc[u] + f0 + 16);
+      n0 = *reinterpret_cast<const v4f*>(z0 + f0 + 16);
+      n1 = *reinterpret_cast<const v4f*>(z1 + f0 + 16);
+    }
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const v4f b = *reinterpret_cast<const v4f*>(&lds[buf][(t * 16 + fr) * PITCH + 16 * fg]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[0][t] = mfma4(a0[q], b[q], acc[0][t]);
+        acc[1][t] = mfma4(a1[q], b[q], acc[1][t]);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u)
+        if (ldst[u] >= 0) *reinterpret_cast<v4f*>(&lds[buf ^ 1][ldst[u]]) = stg[u];
+      a0 = n0;
+      a1 = n1;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const int nt = nc0 + t;
+      if (nt >= ntiles) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + 16 * h + acc_row<float>(fg, r);
+        if (row < rows) Pout[row * mp + nt * 16 + fr] = (double)acc[h][t][r];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Gram tile of one block: slot[a][b] tile = I + Z_b^T Z_b restricted to the
 // 64 x 64 tile (ta, tb), ta >= tb.  The 4 waves take interleaved groups of 4
 // rows and their partial sums are added in wave order through LDS.
@@ -858,6 +953,15 @@ static void launch_zw(const void* Z, int64_t ldz, int64_t rows, int64_t s16, con
                                                              (const op_t*)Wop, mp, Pout);
 }
 
+template <int NTC>
+static void launch_zw_lds(const void* Z, int64_t ldz, int64_t rows, int64_t s16, const void* Wop,
+                          int64_t mp, double* Pout, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  dim3 g((unsigned)((rows + 127) / 128), (unsigned)((ntiles + NTC - 1) / NTC));
+  zw_f32_lds_kernel<NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, s16, (const float*)Wop,
+                                            mp, Pout);
+}
+
 template <typename ZT>
 static void zw_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s16, const void* Wop,
                         int64_t mp, double* Pout, hipStream_t st) {
@@ -865,15 +969,14 @@ static void zw_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s16, c
   if constexpr (sizeof(ZT) == 8) {
     if (nt == 1) launch_zw<ZT, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
     else launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-  } else {
+  } else {  // FP32 operands: more than two tiles share W' through LDS
     if (nt == 1) launch_zw<ZT, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
     else if (nt == 2) launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 4) launch_zw<ZT, 4>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 6) launch_zw<ZT, 6>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 8) launch_zw<ZT, 8>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 10) launch_zw<ZT, 10>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 12) launch_zw<ZT, 12>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else launch_zw<ZT, 8>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 4) launch_zw_lds<4>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 6) launch_zw_lds<6>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 8) launch_zw_lds<8>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else if (nt <= 10) launch_zw_lds<10>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else launch_zw_lds<8>(Z, ldz, rows, s16, Wop, mp, Pout, st);
   }
 }
 
