@@ -100,6 +100,119 @@ ztr_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Transpose products from an FP32 Z for many output columns.  R of a 16-row
+// step (NC columns) is staged once per workgroup into LDS, transposed to
+// [column][16 rows] (row pitch 80 B), double-buffered, and shared by the 4
+// waves; rows past the split are staged as zeros.  Lane group g takes rows
+// 4 g .. 4 g + 3 of the step: four 16-byte loads give its 4 x 4 block of Z,
+// one 16-byte LDS read gives the matching 4 rows of an R column, and
+// instruction j of the step pairs row 4 g + j of both.  Same grid and output
+// as ztr_kernel.
+// ---------------------------------------------------------------------------
+template <int NTC>
+__global__ void __launch_bounds__(256, 2)
+ztr_f32_lds_kernel(const float* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
+                   const float* __restrict__ Rop, int64_t mp, int64_t split_rows,
+                   float* __restrict__ part) {
+  constexpr int NC = NTC * 16, PITCH = 80;
+  constexpr int SEGS = 16 * NC / 4;                // 16-byte segments of R per step
+  constexpr int NSEG = (SEGS + 255) / 256;         // per thread
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][NC * PITCH];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t f0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int64_t sp = blockIdx.y;
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const int64_t rbeg = sp * split_rows;
+  const int64_t rend = min(rows, rbeg + split_rows);
+  const int64_t fl = min(f0 + 4 * fr, s - 4);      // waves past s load in bounds, store nothing
+
+  // staged segment q = tid + 256 u: row q % 16 of the step, columns
+  // 4 (q / 16) .. + 3 of the workgroup's NC (clamped into R past mp)
+  int srow[NSEG], scol[NSEG];
+  bool sval[NSEG];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) {
+    const int q = min(tid + 256 * u, SEGS - 1);
+    srow[u] = q % 16;
+    scol[u] = 4 * (q / 16);
+    sval[u] = tid + 256 * u < SEGS;
+  }
+  auto stage_load = [&](int64_t rb, v4f (&stg)[NSEG]) {
+#pragma unroll
+    for (int u = 0; u < NSEG; ++u) {
+      const int64_t r = rb + srow[u];
+      const int64_t col = min(nc0 * 16 + scol[u], (int)mp - 4);
+      stg[u] = r < rend ? *reinterpret_cast<const v4f*>(Rop + r * mp + col)
+                        : v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto stage_store = [&](unsigned char* buf, const v4f (&stg)[NSEG]) {
+#pragma unroll
+    for (int u = 0; u < NSEG; ++u)
+      if (sval[u]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          *reinterpret_cast<float*>(buf + (scol[u] + i) * PITCH + srow[u] * 4) = stg[u][i];
+      }
+  };
+  auto z_load = [&](int64_t rb, v4f (&a)[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      a[j] = *reinterpret_cast<const v4f*>(Z + min(rb + 4 * fg + j, rows - 1) * ldz + fl);
+  };
+
+  v4f acc[4][NTC];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  v4f stg[NSEG], a[4], an[4];
+  stage_load(rbeg, stg);
+  z_load(rbeg, a);
+  stage_store(lds[0], stg);
+  __syncthreads();
+  for (int64_t rb = rbeg; rb < rend; rb += 16) {
+    const int buf = (int)(((rb - rbeg) >> 4) & 1);
+    const bool more = rb + 16 < rend;
+    if (more) {
+      stage_load(rb + 16, stg);
+      z_load(rb + 16, an);
+    }
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const v4f b = *reinterpret_cast<const v4f*>(&lds[buf][(t * 16 + fr) * PITCH + 16 * fg]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q][t] = mfma4(a[j][q], b[j], acc[q][t]);
+    }
+    if (more) {
+      stage_store(lds[buf ^ 1], stg);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[j] = an[j];
+    }
+    __syncthreads();
+  }
+  // lane holds D[m = acc_row(fg, r)][n = fr]; feature = f0 + 4 m + q
+#pragma unroll
+  for (int t = 0; t < NTC; ++t) {
+    const int nt = nc0 + t;
+    if (nt >= ntiles) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t f = f0 + 4 * acc_row<float>(fg, r) + q;
+        if (f < s) part[(sp * s + f) * mp + nt * 16 + fr] = acc[q][t][r];
+      }
+  }
+}
+
 // rhs = W-bar - mu' + U + sum over splits (fixed order), per row block.
 template <typename A>
 __global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max, int64_t n,
@@ -847,8 +960,19 @@ static void launch_ztr(const void* Z, int64_t ldz, int64_t rows, int64_t s, cons
       (const ZT*)Z, ldz, rows, s, (const op_t*)Rop, mp, split_rows, (op_t*)part);
 }
 
-// One pass over Z covers all output tiles when there are at most 12 (FP32
-// operands) or 2 (FP64); beyond that, passes of 8 (FP32) or 2 (FP64) tiles.
+template <int NTC>
+static void launch_ztr_lds(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rop,
+                           int64_t mp, int64_t split_rows, void* part, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  const int64_t nsplit = (rows + split_rows - 1) / split_rows;
+  dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
+  ztr_f32_lds_kernel<NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, s, (const float*)Rop,
+                                             mp, split_rows, (float*)part);
+}
+
+// One pass over Z covers all output tiles when there are at most 10 (FP32
+// operands; more than two share R through LDS) or 2 (FP64); beyond that,
+// passes of 8 (FP32) or 2 (FP64) tiles.
 // The FP64 branch is resolved at compile time so its wide variants are never
 // instantiated.
 template <typename ZT>
@@ -861,12 +985,11 @@ static void ztr_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, co
   } else {
     if (nt == 1) launch_ztr<ZT, 1>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
     else if (nt == 2) launch_ztr<ZT, 2>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else if (nt <= 4) launch_ztr<ZT, 4>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else if (nt <= 6) launch_ztr<ZT, 6>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else if (nt <= 8) launch_ztr<ZT, 8>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else if (nt <= 10) launch_ztr<ZT, 10>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else if (nt <= 12) launch_ztr<ZT, 12>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
-    else launch_ztr<ZT, 8>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 4) launch_ztr_lds<4>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 6) launch_ztr_lds<6>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 8) launch_ztr_lds<8>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else if (nt <= 10) launch_ztr_lds<10>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
+    else launch_ztr_lds<8>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
   }
 }
 
