@@ -94,3 +94,18 @@ def test_digits_2m_two_row_blocks_bf16x3():
     m=10, 2x8 grid (s_j = 8192 as in the full 16x8 problem)."""
     w = wl.digits_2m()
     _run_checks(w, w.n // 8, "bf16x3", block=(1, 6), tol_proj=2e-4, tol_rows=2e-4, rows_sample=8)
+
+
+def test_speech_one_row_block_bf16():
+    """The speech workload's BF16 run (BF16 feature GEMM and products, FP32
+    accumulation, FP64 factors) at one of its 4 row blocks; the tolerances
+    cover BF16 rounding of Z against the oracle's FP64 Z."""
+    w = wl.speech_100k()
+    _run_checks(w, w.n // 4, "bf16", block=(0, 2), tol_proj=3e-2, tol_rows=3e-2, rows_sample=8)
+
+
+def test_digits_2m_two_row_blocks_bf16():
+    """The 2M-row workload in its own precision (BF16) at 2 of its 16 row
+    blocks: n=250000, s=65536 in 8 column blocks of 8192."""
+    w = wl.digits_2m()
+    _run_checks(w, w.n // 8, "bf16", block=(0, 3), tol_proj=3e-2, tol_rows=3e-2, rows_sample=8)
