@@ -724,46 +724,111 @@ zw_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R, in
 }
 
 // ---------------------------------------------------------------------------
-// Transpose products from a BF16 Z for many output columns: the R planes of a
-// 16-row step (2 x NC columns x 32 B) are loaded once per workgroup into LDS
-// (row pitch 48 B: the 16 columns a fragment read touches fall in distinct
-// banks) and shared by its 4 waves of 64 features; the next step's R and each
-// wave's next Z block are loaded while the current step's products run.  A
-// lane transposes its 4-row x 4-feature block of Z as in ztr_bf16_kernel.
+// Wait until at most N (0..15) of this wave's vector memory
+// operations are outstanding and all of its LDS accesses have completed
+// (expcnt unconstrained).  The compiler-level memory clobbers keep LDS
+// accesses from moving across.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0x0070 | N);
+  asm volatile("" ::: "memory");
+}
+// Workgroup barrier without the memory fence of __syncthreads (which would
+// wait for every outstanding load, including the prefetched stages); callers
+// precede it with wait_vm, which also drains the wave's LDS accesses.
+__device__ __forceinline__ void bare_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+#define BS_LDS __attribute__((address_space(3)))
+
+// ---------------------------------------------------------------------------
+// Transpose products from a BF16 Z for many output columns, fed by direct
+// global-to-LDS loads.  Each 16-row step of the workgroup (Z: 16 rows x 256
+// features; R: 2 planes x NC columns x 16 rows) goes into one of 4 LDS
+// stages, loaded three steps ahead without passing through registers, so
+// that about 55 KB per workgroup are in flight against HBM latency.  Every
+// wave waits for its own loads of the step, then one barrier makes the whole
+// stage visible; the barrier also orders the reads of the stage refilled
+// next (the previous step's) before its refill.  A lane reads its 8-row x
+// 4-feature block of Z from the stage and transposes it with byte permutes
+// as in ztr_bf16_kernel; one 16x16x32 MFMA per output tile and feature takes
+// k = 32 as the step's 16 rows against R's head plane (k < 16) and against
+// its residual plane (k >= 16): lane group fg holds k = 8 fg .. 8 fg + 7,
+// i.e. rows 8 (fg & 1) .. + 7 of plane fg / 2.
+// Stage layouts, chosen so that fragment reads touch distinct banks with 32
+// banks (8 lanes per cycle) or 64 banks (16 lanes per cycle):
+// * Z row r (512 B) holds its 16-byte segment g at (g + 8 (r / 8)) mod 32;
+// * R: 16-byte segment (plane p, column c, half h: rows 8h .. 8h + 7) at
+//   index (p NC + c) 2 + (h ^ (((c >> 2) ^ (c >> 3)) & 1)).
 // Same grid and output as ztr_bf16_kernel.
 // ---------------------------------------------------------------------------
 template <int NTC>
 __global__ void __launch_bounds__(256, 2)
-ztr_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
+ztr_bf16_dma_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
                     const uint16_t* __restrict__ Rt, int64_t ldr, int64_t mp, int64_t split_rows,
                     float* __restrict__ part) {
-  constexpr int NC = NTC * 16, PITCH = 48;
-  constexpr int SEGS = 2 * NC * 2;                 // 16-byte segments (8 rows) per step
-  constexpr int NSEG = (SEGS + 255) / 256;
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2 * NC * PITCH];
+  constexpr int NC = NTC * 16;
+  constexpr int ZB = 16 * 512;                     // Z bytes of a stage
+  constexpr int RB = 2 * NC * 32;                  // R bytes of a stage (NTC loads of 1 KB)
+  __shared__ __attribute__((aligned(16))) unsigned char z0[ZB], z1[ZB], z2[ZB], z3[ZB];
+  __shared__ __attribute__((aligned(16))) unsigned char q0[RB], q1[RB], q2[RB], q3[RB];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches
   const int fr = lane & 15, fg = lane >> 4;
-  const int64_t f0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int64_t fwg = (int64_t)blockIdx.x * 256;
+  const int64_t f0 = fwg + wave * 64;
   const int64_t sp = blockIdx.y;
   const int nc0 = blockIdx.z * NTC;
   const int ntiles = (int)(mp / 16);
   const int64_t rbeg = sp * split_rows;
   const int64_t rend = min(rows, rbeg + split_rows);
-  const int64_t fl = min(f0 + 4 * fr, s - 4);      // waves past s load in bounds, store nothing
   const int64_t pstride = mp * ldr;
+  const int nsteps = (int)((rend - rbeg + 15) / 16);
 
-  // staged segment q = tid + 256 u: plane q / (2 NC), column (q / 2) % NC, half q % 2
-  const uint16_t* gsrc[NSEG];
-  int ldst[NSEG];
+  // Z: load k = 2 wave + u writes stage rows 2k, 2k + 1; lane -> (row, slot)
+  int64_t zrow[2], zcol[2];
 #pragma unroll
-  for (int u = 0; u < NSEG; ++u) {
-    const int q = min(tid + 256 * u, SEGS - 1);
-    const int p = q / (2 * NC), c = (q / 2) % NC, half = q % 2;
-    const int64_t col = min(nc0 * 16 + c, (int)mp - 1);
-    gsrc[u] = Rt + p * pstride + col * ldr + rbeg + half * 8;
-    ldst[u] = tid + 256 * u < SEGS ? (p * NC + c) * PITCH + half * 16 : -1;
+  for (int u = 0; u < 2; ++u) {
+    const int k = 2 * wave + u;
+    const int pr = 2 * k + (lane >> 5), ps = lane & 31;
+    const int g = (ps - 8 * (pr >> 3)) & 31;
+    zrow[u] = pr;
+    zcol[u] = min(fwg + 8 * g, s - 8);
   }
+  // R: load k = wave + 4 u writes stage segments 64 k + lane; every wave
+  // issues NRU loads per stage, those with k >= NTC repeating load NTC - 1
+  // (same bytes to the same place), so that all waves count the same loads
+  constexpr int NRU = (NTC + 3) / 4;
+  constexpr int NLOAD = 2 + NRU;                   // loads per stage and wave
+  int64_t roff[NRU];
+#pragma unroll
+  for (int u = 0; u < NRU; ++u) {
+    const int k = min(wave + 4 * u, NTC - 1);
+    const int q = 64 * k + lane;
+    const int p = q / (2 * NC), c = (q >> 1) % NC;
+    const int h = (q & 1) ^ (((c >> 2) ^ (c >> 3)) & 1);
+    const int64_t col = min(nc0 * 16 + c, (int)mp - 1);
+    roff[u] = p * pstride + col * ldr + 8 * h;
+  }
+  auto issue = [&](int64_t rb, unsigned char* zs, unsigned char* qs) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(Z + min(rb + zrow[u], rows - 1) * ldz + zcol[u]),
+          (BS_LDS void*)(zs + (2 * wave + u) * 1024), 16, 0, 0);
+#pragma unroll
+    for (int u = 0; u < NRU; ++u)
+      __builtin_amdgcn_global_load_lds((const void*)(Rt + roff[u] + rb),
+                                       (BS_LDS void*)(qs + min(wave + 4 * u, NTC - 1) * 1024),
+                                       16, 0, 0);
+  };
 
   v4f acc[4][NTC];
 #pragma unroll
@@ -771,36 +836,15 @@ ztr_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, i
 #pragma unroll
     for (int t = 0; t < NTC; ++t) acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  // One 16x16x32 product per output tile and feature takes k = 32 as the 16
-  // rows of the step against R's head plane (k < 16) and against its residual
-  // plane (k >= 16): lane group fg holds k = 8 fg .. 8 fg + 7, i.e. rows
-  // 8 (fg & 1) .. + 7 of plane fg / 2.  Z block of the step at row rb: rows
-  // rb + 8 (fg & 1) + 0..7, features fl .. fl + 3 (groups fg and fg ^ 2 load
-  // the same rows).
+  // fragment offsets: Z rows 8 (fg & 1) + t, features wave * 64 + 4 fr .. + 3;
+  // R plane fg / 2, column t * 16 + fr, half fg & 1
   const int rsub = 8 * (fg & 1);
-  u32x2 zc[8], zn[8];
-  u32x4 stg[NSEG];
+  const int zoff = rsub * 512 + ((wave * 8 + (fr >> 1) + rsub) & 31) * 16 + 8 * (fr & 1);
+  const int boff = (((fg >> 1) * NC + fr) * 2 + ((fg & 1) ^ (((fr >> 2) ^ (fr >> 3)) & 1))) * 16;
+  auto compute = [&](const unsigned char* zs, const unsigned char* qs) {
+    u32x2 zc[8];
 #pragma unroll
-  for (int t = 0; t < 8; ++t)
-    zc[t] = *reinterpret_cast<const u32x2*>(Z + min(rbeg + rsub + t, rows - 1) * ldz + fl);
-#pragma unroll
-  for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u]);
-#pragma unroll
-  for (int u = 0; u < NSEG; ++u)
-    if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[0][ldst[u]]) = stg[u];
-  __syncthreads();
-  for (int64_t rb = rbeg; rb < rend; rb += 16) {
-    const int buf = (int)(((rb - rbeg) >> 4) & 1);
-    const bool more = rb + 16 < rend;
-    if (more) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-        zn[t] = *reinterpret_cast<const u32x2*>(Z + min(rb + 16 + rsub + t, rows - 1) * ldz + fl);
-#pragma unroll
-      for (int u = 0; u < NSEG; ++u)
-        stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u] + (rb + 16 - rbeg));
-    }
-    // a[q] = feature fl + q at the lane's 8 rows (pairs of rows per dword)
+    for (int t = 0; t < 8; ++t) zc[t] = *reinterpret_cast<const u32x2*>(zs + zoff + t * 512);
     u32x4 a[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
@@ -809,23 +853,40 @@ ztr_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, i
       a[2][h] = __builtin_amdgcn_perm(zc[2 * h + 1].y, zc[2 * h].y, 0x05040100u);
       a[3][h] = __builtin_amdgcn_perm(zc[2 * h + 1].y, zc[2 * h].y, 0x07060302u);
     }
-    // R fragment: plane fg / 2, rows 8 (fg & 1) .. + 7 of the stage (16 bytes)
-    const int boff = (fg >> 1) * NC * PITCH + 2 * rsub;
 #pragma unroll
     for (int t = 0; t < NTC; ++t) {
-      const u32x4 bv = *reinterpret_cast<const u32x4*>(&lds[buf][boff + (t * 16 + fr) * PITCH]);
+      const u32x4 bv = *reinterpret_cast<const u32x4*>(qs + boff + t * 512);
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q][t] = mfma_bf16x8(a[q], bv, acc[q][t]);
     }
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < NSEG; ++u)
-        if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[buf ^ 1][ldst[u]]) = stg[u];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) zc[t] = zn[t];
-    }
-    __syncthreads();
+  };
+  // Step c reads stage c % 4 and refills the stage of step c - 1 with step
+  // c + 3.  Every step issues its refill, past the last step with the last
+  // step's rows again (never read), so the loads in flight are always those
+  // of the next two steps and no refill sits under a branch (which would make
+  // the compiler wait for all of them before any LDS read).
+  auto step = [&](int c, const unsigned char* zs, const unsigned char* qs, unsigned char* zn,
+                  unsigned char* qn) {
+    wait_vm<2 * NLOAD>();
+    bare_barrier();
+    issue(rbeg + 16 * (int64_t)min(c + 3, nsteps - 1), zn, qn);
+    compute(zs, qs);
+  };
+
+  issue(rbeg, z0, q0);
+  issue(rbeg + 16 * (int64_t)min(1, nsteps - 1), z1, q1);
+  issue(rbeg + 16 * (int64_t)min(2, nsteps - 1), z2, q2);
+  int c = 0;
+  for (; c + 4 <= nsteps; c += 4) {
+    step(c, z0, q0, z3, q3);
+    step(c + 1, z1, q1, z0, q0);
+    step(c + 2, z2, q2, z1, q1);
+    step(c + 3, z3, q3, z2, q2);
   }
+  if (c < nsteps) step(c, z0, q0, z3, q3);
+  if (c + 1 < nsteps) step(c + 1, z1, q1, z0, q0);
+  if (c + 2 < nsteps) step(c + 2, z2, q2, z1, q1);
+  wait_vm<0>();   // no load into LDS may still be in flight when the workgroup ends
 #pragma unroll
   for (int t = 0; t < NTC; ++t) {
     const int nt = nc0 + t;
@@ -1007,29 +1068,29 @@ static void launch_ztr_bf16(const void* Z, int64_t ldz, int64_t rows, int64_t s,
 }
 
 template <int NTC>
-static void launch_ztr_bf16_lds(const void* Z, int64_t ldz, int64_t rows, int64_t s,
+static void launch_ztr_bf16_dma(const void* Z, int64_t ldz, int64_t rows, int64_t s,
                                 const void* Rt, int64_t ldr, int64_t mp, int64_t split_rows,
                                 void* part, hipStream_t st) {
   const int ntiles = (int)(mp / 16);
   const int64_t nsplit = (rows + split_rows - 1) / split_rows;
   dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
-  ztr_bf16_lds_kernel<NTC><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, s,
+  ztr_bf16_dma_kernel<NTC><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, s,
                                               (const uint16_t*)Rt, ldr, mp, split_rows,
                                               (float*)part);
 }
 
-// Up to two output tiles read R directly, more share it through LDS.
+// Up to two output tiles read R directly, more share it through LDS stages.
 static void ztr_bf16_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rt,
                               int64_t ldr, int64_t mp, int64_t split_rows, void* part,
                               hipStream_t st) {
   const int nt = (int)(mp / 16);
   if (nt == 1) launch_ztr_bf16<1>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
   else if (nt == 2) launch_ztr_bf16<2>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
-  else if (nt <= 4) launch_ztr_bf16_lds<4>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
-  else if (nt <= 6) launch_ztr_bf16_lds<6>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
-  else if (nt <= 8) launch_ztr_bf16_lds<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
-  else if (nt <= 10) launch_ztr_bf16_lds<10>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
-  else launch_ztr_bf16_lds<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 4) launch_ztr_bf16_dma<4>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 6) launch_ztr_bf16_dma<6>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 8) launch_ztr_bf16_dma<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 10) launch_ztr_bf16_dma<10>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else launch_ztr_bf16_dma<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
 }
 
 }  // namespace
