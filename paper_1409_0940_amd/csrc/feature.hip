@@ -316,14 +316,16 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
 // rows past the edge read as zero and one 32-bit offset per thread addresses
 // all of its segments.  The feature tile is the MFMA's M operand and the row
 // tile its N operand: a lane ends with 4 adjacent features of one row, packed
-// to BF16 and stored as one 8-byte write.  The k-steps are those of
-// regen_kernel.
+// to BF16; the tile is then staged in LDS and stored as whole rows.  The
+// k-steps are those of regen_kernel.
 // ---------------------------------------------------------------------------
 constexpr int WBM = 256, WBN = 256, WNT = 512, WKROW = 128, WPITCH = WKROW + 16;
 constexpr int WSEG = WKROW / 16;                 // 16-byte segments per staged row
 constexpr int WNS = WBM * WSEG / WNT;            // segments per thread and operand (4)
 constexpr int WRSTEP = WNT / WSEG;               // rows between a thread's segments (64)
 constexpr int WTJ = 4;                           // feature tiles per wave
+constexpr int WZPITCH = 2 * WBN + 32;            // bytes per row of a Z tile staged in LDS
+static_assert(WBM * WZPITCH <= 2 * (WBM + WBN) * WPITCH, "a Z tile fits in the staging LDS");
 
 // Raw buffer descriptor over [p, p + bytes): loads past the end return zero.
 // p and bytes are wave-uniform; rebuilding them from readfirstlane halves
@@ -486,24 +488,38 @@ regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
     }
 
     // Epilogue: lane holds features 4 fg .. 4 fg + 3 of tile j for row fr of
-    // tile i; phase + bias -> cos -> two packed BF16 pairs -> one 8-byte store.
-    // Tiles that cross the row or feature edge store element by element.
+    // tile i; phase + bias -> cos -> two packed BF16 pairs.  A whole tile
+    // goes to LDS (free after the last chunk's barrier) as rows of 256
+    // values, then leaves as 512-byte rows, 16 bytes a lane, with
+    // non-temporal stores: an 8-byte store from the MFMA layout touches 16
+    // rows.  Tiles that cross the row or feature edge store element by
+    // element.
     if (row0 + WBM <= rows && col0 + WBN <= cols) {
+      unsigned char* zt = &lds[0][0];
 #pragma unroll
       for (int j = 0; j < TJ; ++j) {
-        const int64_t f = col0 + wn * (16 * TJ) + j * 16 + 4 * fg;
+        const int fl = wn * (16 * TJ) + j * 16 + 4 * fg;
+        const int64_t f = col0 + fl;
         const float b0 = bias[f], b1 = bias[f + 1], b2 = bias[f + 2], b3 = bias[f + 3];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const int64_t row = row0 + wm * 128 + i * 16 + fr;
           uint2 v;
           v.x = pack_bf16x2(scale * rff_cos_bf16out(acc[j][i][0] + b0),
                             scale * rff_cos_bf16out(acc[j][i][1] + b1));
           v.y = pack_bf16x2(scale * rff_cos_bf16out(acc[j][i][2] + b2),
                             scale * rff_cos_bf16out(acc[j][i][3] + b3));
-          *reinterpret_cast<uint2*>(Z + row * ldz + f) = v;
+          *reinterpret_cast<uint2*>(zt + (wm * 128 + i * 16 + fr) * WZPITCH + fl * 2) = v;
         }
       }
+      __syncthreads();
+      constexpr int RPP = WNT / 32;                // rows per pass: 32 lanes a row
+#pragma unroll 1
+      for (int ps = 0; ps < WBM / RPP; ++ps) {
+        const int r = ps * RPP + tid / 32, sg = tid % 32;
+        const u32x4 w = *reinterpret_cast<const u32x4*>(zt + r * WZPITCH + sg * 16);
+        __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(Z + (row0 + r) * ldz + col0 + sg * 8));
+      }
+      __syncthreads();   // the next tile's first chunk reuses this LDS
     } else {
 #pragma unroll
       for (int j = 0; j < TJ; ++j) {
@@ -650,10 +666,11 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
           (float)scale, (float*)Z, ldz);
       break;
     case BS_PREC_BF16: {
-      // wide tiles: the 8-byte Z stores need ldz and the base 8-byte aligned,
-      // the 32-bit buffer offsets a tile of 256 rows below 2 GiB
+      // wide tiles: the 16-byte row stores of Z need ldz and the base 16-byte
+      // aligned (else regen_kernel, same bits), the 32-bit buffer offsets a
+      // tile of 256 rows below 2 GiB
       const int64_t wt = ((rows + WBM - 1) / WBM) * ((cols + WBN - 1) / WBN);
-      if (ldz % 4 == 0 && reinterpret_cast<uintptr_t>(Z) % 8 == 0 && wt <= 0x7fffffff &&
+      if (ldz % 8 == 0 && reinterpret_cast<uintptr_t>(Z) % 16 == 0 && wt <= 0x7fffffff &&
           Kp <= ((int64_t)1 << 21)) {
         // persistent: one workgroup per CU (a multiple of the 8 XCDs)
         const int64_t nwg = std::min<int64_t>(std::max(8, cu_count() / 8 * 8), (wt + 7) / 8 * 8);
