@@ -277,6 +277,49 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
   }
 
   // Epilogue: lane holds D[acc_row(lane / 16, r)][lane % 16] of each 16 x 16 tile.
+  // Float Z of a whole tile leaves through LDS, half a tile (64 rows, the
+  // rows of waves wm = h) at a time, as 512-byte rows with 16-byte
+  // non-temporal stores; straight from the MFMA layout a store instruction
+  // writes 64 bytes into each of 4 rows.  The LDS is free once every wave
+  // has passed the barrier below (the last chunk's products may follow the
+  // loop's last barrier).
+  if constexpr (sizeof(ZT) == 4) {
+    constexpr int ZP = BN + 4;                     // floats per staged row (528 B)
+    static_assert(BM / 2 * ZP * 4 <= (int)sizeof(lds), "half a Z tile fits in the staging LDS");
+    if (row0 + BM <= rows && col0 + BN <= cols && ldz % 4 == 0 &&
+        reinterpret_cast<uintptr_t>(Z) % 16 == 0) {
+      float* zt = reinterpret_cast<float*>(&lds[0][0][0][0]);
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (wm == h) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int cl = wn * 64 + j * 16 + fr;
+            const acc_t bcol = bias[col0 + cl];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const float z = scale * rff_cosf(acc[i][j][r] + bcol);
+                zt[(i * 16 + acc_row<acc_t>(fg, r)) * ZP + cl] = z;
+              }
+          }
+        }
+        __syncthreads();
+        constexpr int RPP = NTHREADS / 32;         // rows per pass: 32 lanes a row
+#pragma unroll 2
+        for (int ps = 0; ps < BM / 2 / RPP; ++ps) {
+          const int r = ps * RPP + tid / 32, sg = tid % 32;
+          const v4f w = *reinterpret_cast<const v4f*>(zt + r * ZP + sg * 4);
+          __builtin_nontemporal_store(
+              w, reinterpret_cast<v4f*>(Z + (row0 + h * (BM / 2) + r) * ldz + col0 + sg * 4));
+        }
+        __syncthreads();
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t col = col0 + wn * 64 + j * 16 + fr;
