@@ -169,7 +169,7 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.b_q = (size_t)L.R * L.C * slot;
   L.b_ws = (size_t)L.ws_rows * row_bytes;
   L.b_row = (size_t)L.n * L.mp * 8;
-  L.b_rop = L.prec == BSADMM_BF16 ? (size_t)2 * L.mp * L.R * L.nbpad * 2
+  L.b_rop = bs::r_planes(L.prec, L.mp) ? (size_t)2 * L.mp * L.R * L.nbpad * 2
                                   : (size_t)L.n * L.mp * L.vb;
   L.b_col = (size_t)L.spad * L.mp * 8;
   L.b_colR = (size_t)L.R * L.spad * L.mp * 8;
@@ -328,7 +328,7 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
       tm.begin();
       for (int i = i0; i < i1; ++i) {
         const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-        const char* Ri = L.prec == BSADMM_BF16
+        const char* Ri = bs::r_planes(L.prec, L.mp)
                              ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
                              : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
         HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb,

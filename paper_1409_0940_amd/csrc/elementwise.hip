@@ -488,7 +488,7 @@ hipError_t row_pre(int prec, int loss, const double* wts, double cfac, int64_t n
   unsigned g = grid_for(n * m);
   if (loss >= 3)
     row_prox_kernel<<<grid_for(n), 256, 0, st>>>(loss, wts, n, m, mp, Y, Obar, nu, O);
-  if (prec == BS_PREC_BF16)
+  if (r_planes(prec, mp))
     row_pre_bf16_kernel<<<g, 256, 0, st>>>(loss, wts, cfac, n, R, m, mp, nbpad, Y, Obar, nu, Dbar,
                                            O, (uint16_t*)Rop);
   else if (prec == BS_PREC_F64)

@@ -902,6 +902,165 @@ ztr_bf16_dma_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, i
 }
 
 // ---------------------------------------------------------------------------
+// BF16X3 transpose products for many output columns: Z in FP32, R as BF16
+// head and residual planes (the layout of ztr_bf16_dma_kernel).  A lane
+// splits each of its Z values into a BF16 head h = RNE(z) and residual
+// l = RNE(z - h) (z - h is exact in FP32) and accumulates h x (R head +
+// R residual) + l x R head in FP32: per output tile and feature one
+// 16x16x32 MFMA with the head pairs the step's 16 rows with both R planes,
+// and one with the residual in the lanes of the head plane (zero in those
+// of the residual plane) adds l x R head.  The dropped l x R residual is
+// below 2^-16 of the product.  Stages of 16 rows (16 KB of Z, 2 x NC x 32 B
+// of R) fill a ring of 3 by direct global-to-LDS loads two steps ahead,
+// with the waits, barrier and unconditional refills of ztr_bf16_dma_kernel;
+// two workgroups fit a CU.  Z stage row r holds the workgroup's 256
+// features in order (a lane's 16-byte fragment reads cover 256 contiguous
+// bytes per 16 lanes).  Same grid and output as ztr_bf16_kernel.
+// ---------------------------------------------------------------------------
+template <int NTC>
+__global__ void __launch_bounds__(256, 2)
+ztr_bf16x3_dma_kernel(const float* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
+                      const uint16_t* __restrict__ Rt, int64_t ldr, int64_t mp,
+                      int64_t split_rows, float* __restrict__ part) {
+  constexpr int NC = NTC * 16;
+  constexpr int ZB = 16 * 1024;                    // Z bytes of a stage (16 loads of 1 KB)
+  constexpr int RB = 2 * NC * 32;                  // R bytes of a stage (NTC loads of 1 KB)
+  __shared__ __attribute__((aligned(16))) unsigned char z0[ZB], z1[ZB], z2[ZB];
+  __shared__ __attribute__((aligned(16))) unsigned char q0[RB], q1[RB], q2[RB];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar branches
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t fwg = (int64_t)blockIdx.x * 256;
+  const int64_t f0 = fwg + wave * 64;
+  const int64_t sp = blockIdx.y;
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const int64_t rbeg = sp * split_rows;
+  const int64_t rend = min(rows, rbeg + split_rows);
+  const int64_t pstride = mp * ldr;
+  const int nsteps = (int)((rend - rbeg + 15) / 16);
+
+  // Z: load k = 4 wave + u writes stage row k, lane -> features 4 lane .. + 3
+  const int64_t zcol = min(fwg + 4 * lane, s - 4);
+  constexpr int NRU = (NTC + 3) / 4;
+  constexpr int NLOAD = 4 + NRU;                   // loads per stage and wave
+  int64_t roff[NRU];
+#pragma unroll
+  for (int u = 0; u < NRU; ++u) {
+    const int k = min(wave + 4 * u, NTC - 1);
+    const int q = 64 * k + lane;
+    const int p = q / (2 * NC), c = (q >> 1) % NC;
+    const int h = (q & 1) ^ (((c >> 2) ^ (c >> 3)) & 1);
+    const int64_t col = min(nc0 * 16 + c, (int)mp - 1);
+    roff[u] = p * pstride + col * ldr + 8 * h;
+  }
+  auto issue = [&](int64_t rb, unsigned char* zs, unsigned char* qs) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 4 * wave + u;
+      __builtin_amdgcn_global_load_lds((const void*)(Z + min(rb + k, rows - 1) * ldz + zcol),
+                                       (BS_LDS void*)(zs + k * 1024), 16, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < NRU; ++u)
+      __builtin_amdgcn_global_load_lds((const void*)(Rt + roff[u] + rb),
+                                       (BS_LDS void*)(qs + min(wave + 4 * u, NTC - 1) * 1024),
+                                       16, 0, 0);
+  };
+
+  v4f acc[4][NTC];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  // Z rows 8 (fg & 1) + t, features wave * 64 + 4 fr .. + 3; R fragment as
+  // in ztr_bf16_dma_kernel; the residual enters in lane groups 0 and 1 only
+  const int rsub = 8 * (fg & 1);
+  const int zoff = rsub * 1024 + (wave * 64 + 4 * fr) * 4;
+  const int boff = (((fg >> 1) * NC + fr) * 2 + ((fg & 1) ^ (((fr >> 2) ^ (fr >> 3)) & 1))) * 16;
+  const bool lo_lane = fg < 2;
+  // Two passes per step keep one set of A fragments live: the heads against
+  // both R planes, then the residuals (lane groups 0, 1) against R's head.
+  auto split = [&](const unsigned char* zs, bool lo, u32x4 (&a)[4]) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const v4f za = *reinterpret_cast<const v4f*>(zs + zoff + (2 * h) * 1024);
+      const v4f zb = *reinterpret_cast<const v4f*>(zs + zoff + (2 * h + 1) * 1024);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t hp = pack_bf16x2(za[q], zb[q]);
+        if (!lo) {
+          a[q][h] = hp;
+        } else {
+          const float ha = __builtin_bit_cast(float, hp << 16);
+          const float hb = __builtin_bit_cast(float, hp & 0xffff0000u);
+          a[q][h] = lo_lane ? pack_bf16x2(za[q] - ha, zb[q] - hb) : 0u;
+        }
+      }
+      if (h % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  // R fragments are read one output tile ahead of their products
+  auto prods = [&](const unsigned char* qs, const u32x4 (&a)[4]) {
+    u32x4 bv = *reinterpret_cast<const u32x4*>(qs + boff);
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const u32x4 bn = *reinterpret_cast<const u32x4*>(qs + boff + min(t + 1, NTC - 1) * 512);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q][t] = mfma_bf16x8(a[q], bv, acc[q][t]);
+      __builtin_amdgcn_sched_barrier(0);
+      bv = bn;
+    }
+  };
+  // (scheduling barriers keep the passes, and the steps, from overlapping in
+  // registers)
+  auto compute = [&](const unsigned char* zs, const unsigned char* qs) {
+    u32x4 a[4];
+    __builtin_amdgcn_sched_barrier(0);
+    split(zs, false, a);
+    prods(qs, a);
+    __builtin_amdgcn_sched_barrier(0);
+    split(zs, true, a);
+    prods(qs, a);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // step c reads stage c % 3 and refills the stage of step c - 1 with step c + 2
+  auto step = [&](int c, const unsigned char* zs, const unsigned char* qs, unsigned char* zn,
+                  unsigned char* qn) {
+    wait_vm<NLOAD>();
+    bare_barrier();
+    issue(rbeg + 16 * (int64_t)min(c + 2, nsteps - 1), zn, qn);
+    compute(zs, qs);
+  };
+
+  issue(rbeg, z0, q0);
+  issue(rbeg + 16 * (int64_t)min(1, nsteps - 1), z1, q1);
+  int c = 0;
+  for (; c + 3 <= nsteps; c += 3) {
+    step(c, z0, q0, z2, q2);
+    step(c + 1, z1, q1, z0, q0);
+    step(c + 2, z2, q2, z1, q1);
+  }
+  if (c < nsteps) step(c, z0, q0, z2, q2);
+  if (c + 1 < nsteps) step(c + 1, z1, q1, z0, q0);
+  wait_vm<0>();   // no load into LDS may still be in flight when the workgroup ends
+#pragma unroll
+  for (int t = 0; t < NTC; ++t) {
+    const int nt = nc0 + t;
+    if (nt >= ntiles) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t f = f0 + 4 * acc_row<float>(fg, r) + q;
+        if (f < s) part[(sp * s + f) * mp + nt * 16 + fr] = acc[q][t][r];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Forward products from a BF16 Z for many output columns: the W' planes of a
 // 32-feature stage (2 x NC columns x 64 B) are loaded once per workgroup into
 // LDS (row pitch 80 B: the 16 columns a fragment read touches fall in
@@ -1079,6 +1238,32 @@ static void launch_ztr_bf16_dma(const void* Z, int64_t ldz, int64_t rows, int64_
                                               (float*)part);
 }
 
+template <int NTC>
+static void launch_ztr_bf16x3_dma(const void* Z, int64_t ldz, int64_t rows, int64_t s,
+                                  const void* Rt, int64_t ldr, int64_t mp, int64_t split_rows,
+                                  void* part, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  const int64_t nsplit = (rows + split_rows - 1) / split_rows;
+  dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
+  ztr_bf16x3_dma_kernel<NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, s,
+                                                (const uint16_t*)Rt, ldr, mp, split_rows,
+                                                (float*)part);
+}
+
+// BF16X3 with more than two output tiles (r_planes): one pass over Z for up
+// to 8 tiles (10 do not fit the registers), two passes of 5 for 9 or 10,
+// passes of 8 beyond.
+static void ztr_bf16x3_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s,
+                                const void* Rt, int64_t ldr, int64_t mp, int64_t split_rows,
+                                void* part, hipStream_t st) {
+  const int nt = (int)(mp / 16);
+  if (nt <= 4) launch_ztr_bf16x3_dma<4>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 6) launch_ztr_bf16x3_dma<6>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 8) launch_ztr_bf16x3_dma<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt <= 10) launch_ztr_bf16x3_dma<5>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else launch_ztr_bf16x3_dma<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+}
+
 // Up to two output tiles read R directly, more share it through LDS stages.
 static void ztr_bf16_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rt,
                               int64_t ldr, int64_t mp, int64_t split_rows, void* part,
@@ -1103,6 +1288,9 @@ hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64
   else if (prec == BS_PREC_BF16) {
     if (split_rows % 32 != 0) return hipErrorInvalidValue;
     ztr_bf16_dispatch(Z, ldz, rows, s, Rop, ldr, mp, split_rows, part, st);
+  } else if (r_planes(prec, mp)) {
+    if (split_rows % 32 != 0) return hipErrorInvalidValue;
+    ztr_bf16x3_dispatch(Z, ldz, rows, s, Rop, ldr, mp, split_rows, part, st);
   } else ztr_dispatch<float>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
   return hipGetLastError();
 }

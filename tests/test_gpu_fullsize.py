@@ -109,3 +109,11 @@ def test_digits_2m_two_row_blocks_bf16():
     blocks: n=250000, s=65536 in 8 column blocks of 8192."""
     w = wl.digits_2m()
     _run_checks(w, w.n // 8, "bf16", block=(0, 3), tol_proj=3e-2, tol_rows=3e-2, rows_sample=8)
+
+
+def test_speech_one_row_block_bf16x3():
+    """The speech workload's refined BF16 run (BF16X3 features; with 147
+    outputs its transpose product takes three BF16 products of head and
+    residual planes) at one of its 4 row blocks."""
+    w = wl.speech_100k()
+    _run_checks(w, w.n // 4, "bf16x3", block=(0, 6), tol_proj=2e-4, tol_rows=2e-4, rows_sample=8)
