@@ -73,7 +73,7 @@ struct Plan {
   size_t b_xp = 0, b_wt = 0, b_bias = 0, b_q = 0, b_ws = 0, b_row = 0, b_rop = 0, b_col = 0,
          b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0, b_prev = 0;
   // operand elements between the W' copies of consecutive row blocks
-  int64_t wop_stride() const { return prec == BSADMM_BF16 ? 2 * mp * spad : spad * mp; }
+  int64_t wop_stride() const { return bs::bf16_planes(prec, mp) ? 2 * mp * spad : spad * mp; }
   size_t total() const {
     return b_xp + b_wt + b_bias + b_q + b_ws + 5 * b_row + b_rop + 3 * b_col + 4 * b_colR + b_wop +
            b_part + b_small + b_fac_tmp + b_prev;
@@ -169,7 +169,7 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.b_q = (size_t)L.R * L.C * slot;
   L.b_ws = (size_t)L.ws_rows * row_bytes;
   L.b_row = (size_t)L.n * L.mp * 8;
-  L.b_rop = bs::r_planes(L.prec, L.mp) ? (size_t)2 * L.mp * L.R * L.nbpad * 2
+  L.b_rop = bs::bf16_planes(L.prec, L.mp) ? (size_t)2 * L.mp * L.R * L.nbpad * 2
                                   : (size_t)L.n * L.mp * L.vb;
   L.b_col = (size_t)L.spad * L.mp * 8;
   L.b_colR = (size_t)L.R * L.spad * L.mp * 8;
@@ -328,7 +328,7 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
       tm.begin();
       for (int i = i0; i < i1; ++i) {
         const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-        const char* Ri = bs::r_planes(L.prec, L.mp)
+        const char* Ri = bs::bf16_planes(L.prec, L.mp)
                              ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
                              : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
         HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb,

@@ -488,7 +488,7 @@ hipError_t row_pre(int prec, int loss, const double* wts, double cfac, int64_t n
   unsigned g = grid_for(n * m);
   if (loss >= 3)
     row_prox_kernel<<<grid_for(n), 256, 0, st>>>(loss, wts, n, m, mp, Y, Obar, nu, O);
-  if (r_planes(prec, mp))
+  if (bf16_planes(prec, mp))
     row_pre_bf16_kernel<<<g, 256, 0, st>>>(loss, wts, cfac, n, R, m, mp, nbpad, Y, Obar, nu, Dbar,
                                            O, (uint16_t*)Rop);
   else if (prec == BS_PREC_F64)
@@ -566,7 +566,7 @@ hipError_t to_wop(int prec, const double* src, int64_t nblk, int64_t spad, int64
   const int64_t count = nblk * spad * mp;
   if (count == 0) return hipSuccess;
   const unsigned g = grid_for(count);
-  if (prec == BS_PREC_BF16)
+  if (bf16_planes(prec, mp))
     to_wop_bf16_kernel<<<g, 256, 0, st>>>(src, nblk, spad, mp, (uint16_t*)dst);
   else if (prec == BS_PREC_F64)
     to_wop_kernel<double><<<g, 256, 0, st>>>(src, nblk, spad, mp, (double*)dst);

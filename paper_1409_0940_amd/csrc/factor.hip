@@ -547,9 +547,9 @@ hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, co
   if (nb <= 0) return hipSuccess;
   if (prec == BS_PREC_F64)
     launch_solve<double>(Q, S, C, b0, nb, coff, sjs, spad, mp, rhs, Wp, U, (double*)Wop, st);
-  else if (prec == BS_PREC_BF16)
+  else if (bf16_planes(prec, mp))  // BF16, and BF16X3 with more than two output tiles
     launch_solve<uint16_t>(Q, S, C, b0, nb, coff, sjs, spad, mp, rhs, Wp, U, (uint16_t*)Wop, st);
-  else  // FP32 and BF16X3 multiply FP32 operands
+  else  // FP32, and BF16X3 with one or two output tiles, multiply FP32 operands
     launch_solve<float>(Q, S, C, b0, nb, coff, sjs, spad, mp, rhs, Wp, U, (float*)Wop, st);
   return hipGetLastError();
 }

@@ -8,11 +8,11 @@
 
 namespace bs {
 
-// Whether the transpose products take R as BF16 head and residual planes
-// (the transposed layout below): always in BF16, and in BF16X3 when there
-// are more than two output tiles, where three BF16 products (head x head,
+// Whether the products take R and W' as BF16 head and residual planes (the
+// transposed layouts below): always in BF16, and in BF16X3 when there are
+// more than two output tiles, where three BF16 products (head x head,
 // head x residual, residual x head) replace the MFMA-bound FP32 ones.
-inline bool r_planes(int prec, int64_t mp) {
+inline bool bf16_planes(int prec, int64_t mp) {
   return prec == BS_PREC_BF16 || (prec == BS_PREC_BF16X3 && mp > 32);
 }
 
@@ -53,14 +53,14 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
 // BF16 multiplies BF16 head and residual planes of both, stored transposed:
 // R as [plane][mp][ldr] with ldr = R * nbpad and row block i in the segment
 // starting at i * nbpad (zero for at least 32 rows past its rows), W' as
-// [i][plane][mp][spad].  BF16X3 with more than two output tiles takes R in
-// that plane layout too (r_planes) and splits its float Z into head and
-// residual in the kernel.
+// [i][plane][mp][spad].  BF16X3 with more than two output tiles takes R and
+// W' in those plane layouts too (bf16_planes) and splits its float Z into
+// head and residual in the kernels.
 
 // Partial transpose products for one row block:
 // part[sp][f][c] = sum_{r in split sp} Z[r][f] * R[r][c], f < spad, c < mp.
 // Rop points at the block's rows; ldr is used by the plane layout only
-// (r_planes), whose split_rows must be a multiple of 32.
+// (bf16_planes), whose split_rows must be a multiple of 32.
 hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t spad,
                        const void* Rop, int64_t ldr, int64_t mp, int64_t split_rows, void* part,
                        hipStream_t st);

@@ -1164,6 +1164,135 @@ zw_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16X3 forward products for many output columns: Z in FP32, W' as BF16
+// head and residual planes (the layout of zw_bf16_lds_kernel, staged the same
+// way).  A lane splits its 8 Z values of a 32-feature stage into heads
+// h = RNE(z) and residuals l = RNE(z - h) and accumulates h x W' head +
+// h x W' residual + l x W' head (three 16x16x32 MFMAs per row tile and output
+// tile; the dropped l x W' residual is below 2^-16 of the product).  The
+// next stage's Z (two 16-byte loads per row tile) and W' are loaded while
+// the current stage's products run.  Same grid and output as zw_bf16_kernel.
+// ---------------------------------------------------------------------------
+template <int NTC>
+__global__ void __launch_bounds__(256, 2)
+zw_bf16x3_lds_kernel(const float* __restrict__ Z, int64_t ldz, int64_t n, int R, int i0,
+                     int64_t s, const uint16_t* __restrict__ Wt, int64_t wt_stride, int64_t mp,
+                     double* __restrict__ Pout) {
+  constexpr int MT = 4, NC = NTC * 16, PITCH = 80;
+  constexpr int SEGS = 2 * NC * 4;                 // 16-byte segments per stage
+  constexpr int NSEG = (SEGS + 255) / 256;         // per thread
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2][2 * NC * PITCH];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int i = i0 + (int)blockIdx.y;
+  const int64_t gi = (int64_t)i * n / R, ni = (int64_t)(i + 1) * n / R - gi;
+  const int64_t zi = gi - (int64_t)i0 * n / R;
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * MT) + wave * (16 * MT);
+  const int nc0 = blockIdx.z * NTC;
+  const int ntiles = (int)(mp / 16);
+  const uint16_t* Wb = Wt + (int64_t)i * wt_stride;
+  const int64_t pstride = mp * s;
+
+  // staged segment q = tid + 256 u: plane q / (4 NC), column (q / 4) % NC, part q % 4
+  const uint16_t* gsrc[NSEG];
+  int ldst[NSEG];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) {
+    const int q = min(tid + 256 * u, SEGS - 1);
+    const int p = q / (4 * NC), c = (q / 4) % NC, part = q % 4;
+    const int64_t col = min(nc0 * 16 + c, (int)mp - 1);
+    gsrc[u] = Wb + p * pstride + col * s + part * 8;
+    ldst[u] = tid + 256 * u < SEGS ? (p * NC + c) * PITCH + part * 16 : -1;
+  }
+  const float* zp[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+    zp[t] = Z + (zi + min(row0 + 16 * t + fr, ni - 1)) * ldz + 8 * fg;
+
+  v4f acc[MT][NTC];
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) acc[a][t] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  // heads and residuals of a lane's 8 consecutive features, packed in pairs
+  // (low half = the even feature)
+  auto split = [&](const v4f& z0, const v4f& z1, u32x4& h, u32x4& l) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float a = j < 2 ? z0[2 * j] : z1[2 * j - 4];
+      const float b = j < 2 ? z0[2 * j + 1] : z1[2 * j - 3];
+      const uint32_t hp = pack_bf16x2(a, b);
+      h[j] = hp;
+      l[j] = pack_bf16x2(a - __builtin_bit_cast(float, hp << 16),
+                         b - __builtin_bit_cast(float, hp & 0xffff0000u));
+    }
+  };
+
+  u32x4 stg[NSEG], ah[MT], al[MT];
+  v4f zn[MT][2];
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u]);
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    zn[t][0] = *reinterpret_cast<const v4f*>(zp[t]);
+    zn[t][1] = *reinterpret_cast<const v4f*>(zp[t] + 4);
+  }
+#pragma unroll
+  for (int u = 0; u < NSEG; ++u)
+    if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[0][ldst[u]]) = stg[u];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) split(zn[t][0], zn[t][1], ah[t], al[t]);
+  __syncthreads();
+  for (int64_t k0 = 0; k0 < s; k0 += 32) {
+    const int buf = (int)((k0 >> 5) & 1);
+    const bool more = k0 + 32 < s;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u) stg[u] = *reinterpret_cast<const u32x4*>(gsrc[u] + k0 + 32);
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        zn[t][0] = *reinterpret_cast<const v4f*>(zp[t] + k0 + 32);
+        zn[t][1] = *reinterpret_cast<const v4f*>(zp[t] + k0 + 36);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const u32x4 bh = *reinterpret_cast<const u32x4*>(&lds[buf][(t * 16 + fr) * PITCH + 16 * fg]);
+      const u32x4 bl =
+          *reinterpret_cast<const u32x4*>(&lds[buf][(NC + t * 16 + fr) * PITCH + 16 * fg]);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        acc[m][t] = mfma_bf16x8(ah[m], bh, acc[m][t]);
+        acc[m][t] = mfma_bf16x8(ah[m], bl, acc[m][t]);
+        acc[m][t] = mfma_bf16x8(al[m], bh, acc[m][t]);
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < NSEG; ++u)
+        if (ldst[u] >= 0) *reinterpret_cast<u32x4*>(&lds[buf ^ 1][ldst[u]]) = stg[u];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) split(zn[t][0], zn[t][1], ah[t], al[t]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NTC; ++t) {
+      const int nt = nc0 + t;
+      if (nt >= ntiles) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 16 * m + acc_row<float>(fg, r);
+        if (row < ni) Pout[(gi + row) * mp + nt * 16 + fr] = (double)acc[m][t][r];
+      }
+    }
+}
+
 // Loads batched per wave before their MFMAs: more when each load feeds few
 // instructions (few output tiles), fewer when the tile count is large.
 template <int NTC> constexpr int ztr_unroll() { return NTC <= 2 ? 8 : 4; }
@@ -1250,7 +1379,7 @@ static void launch_ztr_bf16x3_dma(const void* Z, int64_t ldz, int64_t rows, int6
                                                 (float*)part);
 }
 
-// BF16X3 with more than two output tiles (r_planes): one pass over Z for up
+// BF16X3 with more than two output tiles (bf16_planes): one pass over Z for up
 // to 8 tiles (10 do not fit the registers), two passes of 5 for 9 or 10,
 // passes of 8 beyond.
 static void ztr_bf16x3_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s,
@@ -1288,7 +1417,7 @@ hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64
   else if (prec == BS_PREC_BF16) {
     if (split_rows % 32 != 0) return hipErrorInvalidValue;
     ztr_bf16_dispatch(Z, ldz, rows, s, Rop, ldr, mp, split_rows, part, st);
-  } else if (r_planes(prec, mp)) {
+  } else if (bf16_planes(prec, mp)) {
     if (split_rows % 32 != 0) return hipErrorInvalidValue;
     ztr_bf16x3_dispatch(Z, ldz, rows, s, Rop, ldr, mp, split_rows, part, st);
   } else ztr_dispatch<float>(Z, ldz, rows, s, Rop, mp, split_rows, part, st);
@@ -1375,6 +1504,16 @@ static void launch_zw_bf16_lds(const void* Z, int64_t ldz, int64_t n, int R, int
                                              (const uint16_t*)Wt, wt_stride, mp, Pout);
 }
 
+template <int NTC>
+static void launch_zw_bf16x3_lds(const void* Z, int64_t ldz, int64_t n, int R, int i0, int nblk,
+                                 int64_t nmax, int64_t s, const void* Wt, int64_t wt_stride,
+                                 int64_t mp, double* Pout, hipStream_t st) {
+  const int ntiles = (int)(mp / 16);
+  dim3 g((unsigned)((nmax + 255) / 256), (unsigned)nblk, (unsigned)((ntiles + NTC - 1) / NTC));
+  zw_bf16x3_lds_kernel<NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, n, R, i0, s,
+                                               (const uint16_t*)Wt, wt_stride, mp, Pout);
+}
+
 // One pass over Z for up to 10 output tiles (passes of 8 beyond): up to two
 // tiles read W' directly, more share it through LDS.
 static void zw_bf16_dispatch(const void* Z, int64_t ldz, int64_t n, int R, int i0, int nblk,
@@ -1402,11 +1541,14 @@ hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t n, int R, int i0, in
               const void* Wop, int64_t wop_stride, int64_t mp, double* Pout, hipStream_t st) {
   if (i1 <= i0 || n <= 0) return hipSuccess;
   if (s % 64 != 0) return hipErrorInvalidValue;
-  if (prec == BS_PREC_BF16) {
+  if (bf16_planes(prec, mp)) {
     int64_t nmax = 0;
     for (int i = i0; i < i1; ++i)
       nmax = std::max<int64_t>(nmax, (int64_t)(i + 1) * n / R - (int64_t)i * n / R);
-    zw_bf16_dispatch(Z, ldz, n, R, i0, i1 - i0, nmax, s, Wop, wop_stride, mp, Pout, st);
+    if (prec == BS_PREC_BF16)
+      zw_bf16_dispatch(Z, ldz, n, R, i0, i1 - i0, nmax, s, Wop, wop_stride, mp, Pout, st);
+    else  // BF16X3: passes of up to 5 output tiles (the registers of 3 products)
+      launch_zw_bf16x3_lds<5>(Z, ldz, n, R, i0, i1 - i0, nmax, s, Wop, wop_stride, mp, Pout, st);
     return hipGetLastError();
   }
   const int64_t r0 = (int64_t)i0 * n / R;
