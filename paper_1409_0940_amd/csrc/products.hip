@@ -342,12 +342,16 @@ zw_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
 // distinct banks), double-buffered, and shared by the 4 waves of 32 rows, so
 // W' moves from L2 once per workgroup instead of once per wave; each wave's
 // next Z fragments and the next stage are loaded while the current step's
-// products run.  Same grid, k-permutation and output as zw_kernel (KS = 1).
+// products run.  The k-permutation and output are those of zw_kernel (KS = 1).
+// One launch covers the row blocks i0 .. i0 + gridDim.y - 1 of the partition
+// of n rows into R (grid row = row block, as in zw_bf16_kernel), so that a
+// speech-sized block of 25000 rows does not leave most of the GPU idle.
 // ---------------------------------------------------------------------------
 template <int NTC>
 __global__ void __launch_bounds__(256, 2)
-zw_f32_lds_kernel(const float* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s16,
-                  const float* __restrict__ Wt, int64_t mp, double* __restrict__ Pout) {
+zw_f32_lds_kernel(const float* __restrict__ Zg, int64_t ldz, int64_t n, int R, int i0,
+                  int64_t s16, const float* __restrict__ Wg, int64_t wt_stride, int64_t mp,
+                  double* __restrict__ Pg) {
   constexpr int NC = NTC * 16, PITCH = 80;
   constexpr int SEGS = NC * 4;                     // 16-byte segments per stage
   constexpr int NSEG = (SEGS + 255) / 256;         // per thread
@@ -355,8 +359,13 @@ zw_f32_lds_kernel(const float* __restrict__ Z, int64_t ldz, int64_t rows, int64_
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int fr = lane & 15, fg = lane >> 4;
+  const int i = i0 + (int)blockIdx.y;
+  const int64_t gi = (int64_t)i * n / R, rows = (int64_t)(i + 1) * n / R - gi;
+  const float* Z = Zg + (gi - (int64_t)i0 * n / R) * ldz;
+  const float* Wt = Wg + (int64_t)i * wt_stride;
+  double* Pout = Pg + gi * mp;
   const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
-  const int nc0 = blockIdx.y * NTC;
+  const int nc0 = blockIdx.z * NTC;
   const int ntiles = (int)(mp / 16);
 
   // staged segment q = tid + 256 u: column q / 4 of the workgroup's NC,
@@ -1455,12 +1464,29 @@ static void launch_zw(const void* Z, int64_t ldz, int64_t rows, int64_t s16, con
 }
 
 template <int NTC>
-static void launch_zw_lds(const void* Z, int64_t ldz, int64_t rows, int64_t s16, const void* Wop,
+static void launch_zw_lds(const void* Z, int64_t ldz, int64_t n, int R, int i0, int nblk,
+                          int64_t nmax, int64_t s16, const void* Wop, int64_t wop_stride,
                           int64_t mp, double* Pout, hipStream_t st) {
   const int ntiles = (int)(mp / 16);
-  dim3 g((unsigned)((rows + 127) / 128), (unsigned)((ntiles + NTC - 1) / NTC));
-  zw_f32_lds_kernel<NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, rows, s16, (const float*)Wop,
-                                            mp, Pout);
+  dim3 g((unsigned)((nmax + 127) / 128), (unsigned)nblk, (unsigned)((ntiles + NTC - 1) / NTC));
+  zw_f32_lds_kernel<NTC><<<g, 256, 0, st>>>((const float*)Z, ldz, n, R, i0, s16,
+                                            (const float*)Wop, wop_stride, mp, Pout);
+}
+
+// FP32 operands with more than two output tiles: all row blocks in one
+// launch, one pass over Z for up to 10 tiles, passes of 8 beyond.
+static void zw_f32_lds_dispatch(const void* Z, int64_t ldz, int64_t n, int R, int i0, int nblk,
+                                int64_t nmax, int64_t s16, const void* Wop, int64_t wop_stride,
+                                int64_t mp, double* Pout, hipStream_t st) {
+  const int nt = (int)(mp / 16);
+#define BS_ZWF(NTC) \
+  launch_zw_lds<NTC>(Z, ldz, n, R, i0, nblk, nmax, s16, Wop, wop_stride, mp, Pout, st)
+  if (nt <= 4) BS_ZWF(4);
+  else if (nt <= 6) BS_ZWF(6);
+  else if (nt <= 8) BS_ZWF(8);
+  else if (nt <= 10) BS_ZWF(10);
+  else BS_ZWF(8);
+#undef BS_ZWF
 }
 
 template <typename ZT>
@@ -1470,14 +1496,9 @@ static void zw_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s16, c
   if constexpr (sizeof(ZT) == 8) {
     if (nt == 1) launch_zw<ZT, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
     else launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-  } else {  // FP32 operands: more than two tiles share W' through LDS
+  } else {  // FP32 operands, one or two tiles (more: zw_f32_lds_dispatch)
     if (nt == 1) launch_zw<ZT, 1>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt == 2) launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 4) launch_zw_lds<4>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 6) launch_zw_lds<6>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 8) launch_zw_lds<8>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else if (nt <= 10) launch_zw_lds<10>(Z, ldz, rows, s16, Wop, mp, Pout, st);
-    else launch_zw_lds<8>(Z, ldz, rows, s16, Wop, mp, Pout, st);
+    else launch_zw<ZT, 2>(Z, ldz, rows, s16, Wop, mp, Pout, st);
   }
 }
 
@@ -1549,6 +1570,13 @@ hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t n, int R, int i0, in
       zw_bf16_dispatch(Z, ldz, n, R, i0, i1 - i0, nmax, s, Wop, wop_stride, mp, Pout, st);
     else  // BF16X3: passes of up to 5 output tiles (the registers of 3 products)
       launch_zw_bf16x3_lds<5>(Z, ldz, n, R, i0, i1 - i0, nmax, s, Wop, wop_stride, mp, Pout, st);
+    return hipGetLastError();
+  }
+  if (prec != BS_PREC_F64 && mp > 32) {
+    int64_t nmax = 0;
+    for (int i = i0; i < i1; ++i)
+      nmax = std::max<int64_t>(nmax, (int64_t)(i + 1) * n / R - (int64_t)i * n / R);
+    zw_f32_lds_dispatch(Z, ldz, n, R, i0, i1 - i0, nmax, s, Wop, wop_stride, mp, Pout, st);
     return hipGetLastError();
   }
   const int64_t r0 = (int64_t)i0 * n / R;
