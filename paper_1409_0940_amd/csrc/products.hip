@@ -529,104 +529,6 @@ gram_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
 }
 
 // ---------------------------------------------------------------------------
-// Transpose products from a BF16 Z on the 16x16x16 BF16 instruction, one row
-// block per launch: part[sp][f][c] = sum_{r in split sp} Z[r][f] R[r][c].
-// R comes as BF16 head and residual planes stored transposed, Rt[p][c][r]
-// (plane stride mp * ldr, zero past the block's rows), and both planes are
-// multiplied, so R keeps ~16 significant bits.
-// A lane loads a 4-row x 4-feature block of Z (four 8-byte loads of adjacent
-// rows) and transposes it in registers; instruction q of a step takes feature
-// 4 m + q as its row m and the 16 rows of the step as k.  split_rows is a
-// multiple of 16, so every 16-row step lies in one split.
-// ---------------------------------------------------------------------------
-template <int NTC, int U>
-__global__ void __launch_bounds__(256)
-ztr_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t s,
-                const uint16_t* __restrict__ Rt, int64_t ldr, int64_t mp, int64_t split_rows,
-                float* __restrict__ part) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int fr = lane & 15, fg = lane >> 4;
-  const int64_t f0 = (int64_t)blockIdx.x * 256 + wave * 64;
-  const int64_t sp = blockIdx.y;
-  const int nc0 = blockIdx.z * NTC;
-  const int ntiles = (int)(mp / 16);
-  const int64_t rbeg = sp * split_rows;
-  const int64_t rend = min(rows, rbeg + split_rows);
-  const int64_t rlast = (rows - 1) / 16 * 16;       // start of the block's last step
-  const int64_t fl = f0 + 4 * fr;
-  const int64_t pstride = mp * ldr;
-
-  v4f acc[4][NTC];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int t = 0; t < NTC; ++t) acc[q][t] = v4f{0.f, 0.f, 0.f, 0.f};
-
-  if (f0 < s) {
-    for (int64_t rb = rbeg; rb < rend; rb += 16 * U) {
-      u32x2 z[U][4], rv[U][NTC][2];
-      bool ok[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t r16 = rb + 16 * u;
-        ok[u] = r16 < rend;                 // whole step inside the split, or none of it
-        const int64_t rs = min(r16, rlast);  // in-bounds stand-in for a step past the end
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int64_t r = min(rs + 4 * fg + t, rows - 1);
-          z[u][t] = *reinterpret_cast<const u32x2*>(Z + r * ldz + fl);
-        }
-#pragma unroll
-        for (int t = 0; t < NTC; ++t) {
-          const int nt = min(nc0 + t, ntiles - 1);
-          const uint16_t* rp = Rt + (int64_t)(nt * 16 + fr) * ldr + rs + 4 * fg;
-          rv[u][t][0] = *reinterpret_cast<const u32x2*>(rp);
-          rv[u][t][1] = *reinterpret_cast<const u32x2*>(rp + pstride);
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        // a[q] = feature fl + q at rows 4 fg .. 4 fg + 3 of the step
-        u32x2 a[4];
-        a[0].x = __builtin_amdgcn_perm(z[u][1].x, z[u][0].x, 0x05040100u);
-        a[0].y = __builtin_amdgcn_perm(z[u][3].x, z[u][2].x, 0x05040100u);
-        a[1].x = __builtin_amdgcn_perm(z[u][1].x, z[u][0].x, 0x07060302u);
-        a[1].y = __builtin_amdgcn_perm(z[u][3].x, z[u][2].x, 0x07060302u);
-        a[2].x = __builtin_amdgcn_perm(z[u][1].y, z[u][0].y, 0x05040100u);
-        a[2].y = __builtin_amdgcn_perm(z[u][3].y, z[u][2].y, 0x05040100u);
-        a[3].x = __builtin_amdgcn_perm(z[u][1].y, z[u][0].y, 0x07060302u);
-        a[3].y = __builtin_amdgcn_perm(z[u][3].y, z[u][2].y, 0x07060302u);
-        const u32x2 zero2 = {0u, 0u};
-#pragma unroll
-        for (int t = 0; t < NTC; ++t) {
-          const u32x2 bh = ok[u] ? rv[u][t][0] : zero2;
-          const u32x2 bl = ok[u] ? rv[u][t][1] : zero2;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            acc[q][t] = mfma_bf16x4(a[q], bh, acc[q][t]);
-            acc[q][t] = mfma_bf16x4(a[q], bl, acc[q][t]);
-          }
-        }
-      }
-    }
-  }
-  // lane holds D[m = 4 fg + r][n = fr]; feature = f0 + 4 m + q
-#pragma unroll
-  for (int t = 0; t < NTC; ++t) {
-    const int nt = nc0 + t;
-    if (nt >= ntiles) continue;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t f = f0 + 4 * acc_row<float>(fg, r) + q;
-        if (f < s) part[(sp * s + f) * mp + nt * 16 + fr] = acc[q][t][r];
-      }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Forward products from a BF16 Z on the 16x16x32 BF16 instruction, all row
 // blocks of a group in one launch (grid.y = block):
 // P[r][c] = sum_f Z[r][f] W'_i[f][c] for the rows r of block i.
@@ -765,8 +667,8 @@ __device__ __forceinline__ void bare_barrier() {
 // wave waits for its own loads of the step, then one barrier makes the whole
 // stage visible; the barrier also orders the reads of the stage refilled
 // next (the previous step's) before its refill.  A lane reads its 8-row x
-// 4-feature block of Z from the stage and transposes it with byte permutes
-// as in ztr_bf16_kernel; one 16x16x32 MFMA per output tile and feature takes
+// 4-feature block of Z from the stage and transposes it in registers with
+// byte permutes; one 16x16x32 MFMA per output tile and feature takes
 // k = 32 as the step's 16 rows against R's head plane (k < 16) and against
 // its residual plane (k >= 16): lane group fg holds k = 8 fg .. 8 fg + 7,
 // i.e. rows 8 (fg & 1) .. + 7 of plane fg / 2.
@@ -775,7 +677,10 @@ __device__ __forceinline__ void bare_barrier() {
 // * Z row r (512 B) holds its 16-byte segment g at (g + 8 (r / 8)) mod 32;
 // * R: 16-byte segment (plane p, column c, half h: rows 8h .. 8h + 7) at
 //   index (p NC + c) 2 + (h ^ (((c >> 2) ^ (c >> 3)) & 1)).
-// Same grid and output as ztr_bf16_kernel.
+// Output: part[sp][f][c] = sum over the rows r of split sp of Z[r][f] R[r][c];
+// R comes as BF16 head and residual planes stored transposed, Rt[p][c][r]
+// (plane stride mp * ldr, zero for 32 rows past the block's rows).  Grid:
+// 256 features x splits x passes of NTC output tiles.
 // ---------------------------------------------------------------------------
 template <int NTC>
 __global__ void __launch_bounds__(256, 2)
@@ -924,7 +829,7 @@ ztr_bf16_dma_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, i
 // with the waits, barrier and unconditional refills of ztr_bf16_dma_kernel;
 // two workgroups fit a CU.  Z stage row r holds the workgroup's 256
 // features in order (a lane's 16-byte fragment reads cover 256 contiguous
-// bytes per 16 lanes).  Same grid and output as ztr_bf16_kernel.
+// bytes per 16 lanes).  Same grid and output as ztr_bf16_dma_kernel.
 // ---------------------------------------------------------------------------
 template <int NTC>
 __global__ void __launch_bounds__(256, 2)
@@ -1352,19 +1257,6 @@ static void ztr_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, co
 }
 
 template <int NTC>
-static void launch_ztr_bf16(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rt,
-                            int64_t ldr, int64_t mp, int64_t split_rows, void* part,
-                            hipStream_t st) {
-  constexpr int U = NTC <= 2 ? 4 : (NTC <= 6 ? 2 : 1);
-  const int ntiles = (int)(mp / 16);
-  const int64_t nsplit = (rows + split_rows - 1) / split_rows;
-  dim3 g((unsigned)((s + 255) / 256), (unsigned)nsplit, (unsigned)((ntiles + NTC - 1) / NTC));
-  ztr_bf16_kernel<NTC, U><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, s,
-                                             (const uint16_t*)Rt, ldr, mp, split_rows,
-                                             (float*)part);
-}
-
-template <int NTC>
 static void launch_ztr_bf16_dma(const void* Z, int64_t ldz, int64_t rows, int64_t s,
                                 const void* Rt, int64_t ldr, int64_t mp, int64_t split_rows,
                                 void* part, hipStream_t st) {
@@ -1402,13 +1294,13 @@ static void ztr_bf16x3_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_
   else launch_ztr_bf16x3_dma<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
 }
 
-// Up to two output tiles read R directly, more share it through LDS stages.
+// All tile counts go through the LDS stages (passes of 8 beyond 10 tiles).
 static void ztr_bf16_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t s, const void* Rt,
                               int64_t ldr, int64_t mp, int64_t split_rows, void* part,
                               hipStream_t st) {
   const int nt = (int)(mp / 16);
-  if (nt == 1) launch_ztr_bf16<1>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
-  else if (nt == 2) launch_ztr_bf16<2>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  if (nt == 1) launch_ztr_bf16_dma<1>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
+  else if (nt == 2) launch_ztr_bf16_dma<2>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
   else if (nt <= 4) launch_ztr_bf16_dma<4>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
   else if (nt <= 6) launch_ztr_bf16_dma<6>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
   else if (nt <= 8) launch_ztr_bf16_dma<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
