@@ -59,16 +59,33 @@ typedef enum {
 /* ------------------------------------------------------------- precision */
 /* Arithmetic of the feature regeneration and of the Z products.  The ADMM
  * state, the Cholesky factorisation and the cached inverse are always FP64.
+ * R = Delta-bar/(C+1) + nu is the operand of the transpose product Z^T R and
+ * W' that of the forward product Z W'.
  *   FP64  : phase X W + b, cos and products in FP64 (FP64 MFMA).
- *   FP32  : FP32 MFMA with FP32 accumulation, phase and cos in FP32; Z FP32.
+ *   FP32  : FP32 MFMA with FP32 accumulation, phase and cos in FP32; Z FP32;
+ *           R and W' rounded to FP32 for the products.
  *   BF16  : X and W rounded to BF16 (round to nearest even), BF16 MFMA with
  *           FP32 accumulation, b added to the FP32 phase, cos in FP32, Z
- *           stored in BF16; products on FP32 MFMA (Z widened, R and W' FP32).
- *   BF16X3: refined BF16.  X and W are each split into a BF16 head and a BF16
- *           residual (the rounding error of the head), and the phase sums the
- *           three products head*head + head*residual + residual*head on BF16
- *           MFMA with FP32 accumulation; Z is stored in FP32 and the products
- *           are FP32.  rff_map returns float for BF16X3.                    */
+ *           stored in BF16.  The products are BF16 MFMA with FP32
+ *           accumulation over the exact BF16 Z and two BF16 planes of R and
+ *           W' each, a head h = bf16(v) and a residual bf16(v - h), so the
+ *           operand keeps about 16 significant bits.  The phase error is about
+ *           2^-8 |X||W| per element; objective error <= 1e-2 (measured far
+ *           below it on the benchmark workloads).
+ *   BF16X3: split-operand BF16 features.  X and W are each split into a BF16
+ *           head and a BF16 residual (the rounding error of the head), and the
+ *           phase sums the three products head*head + head*residual +
+ *           residual*head on BF16 MFMA with FP32 accumulation (phase error
+ *           <= 3 * 2^-16 sum |x||w|); Z is stored in FP32.  With at most two
+ *           16-column output tiles (m <= 32) the products are FP32 MFMA; with
+ *           more they are three BF16 MFMA products per element (Z's head and
+ *           residual against the head and residual planes of R and W', the
+ *           residual-by-residual term dropped, below 2^-16 of the product).
+ *           rff_map returns float for BF16X3.
+ *   BF16R : BF16 iterations with iterative refinement of the graph projection
+ *           (see bsadmm_refine_schedule): features, Gram and products as BF16;
+ *           on the refinement iterations the projection is corrected through
+ *           the same FP64 factor with a residual formed from BF16X3 features. */
 enum { BSADMM_FP64 = 0, BSADMM_FP32 = 1, BSADMM_BF16 = 2, BSADMM_BF16X3 = 3 };
 
 /* ------------------------------------------------------------------ loss */
@@ -112,6 +129,16 @@ enum { BSADMM_L2 = 0 };
 enum { BSADMM_Z_AUTO = 0, BSADMM_Z_STORE = 1, BSADMM_Z_KEEP = 2 };
 
 /* -------------------------------------------------------------- problem */
+/* Problem flags.
+ * BSADMM_F_GRAPH: bsadmm_iterate calls that do not ask for per-phase timing
+ *   replay HIP graphs of the iteration instead of launching its kernels one
+ *   by one: the launch sequence of one iteration (and of a chunk of 16, or of
+ *   one adaptation period of at most 64 iterations) is captured on first use
+ *   on a private stream and launched on the handle's stream.  The kernels and
+ *   their order are the same, so the iterates are bit for bit those of the
+ *   eager path; the gain is host launch time, which bounds small problems. */
+enum { BSADMM_F_GRAPH = 1 };
+
 /* Problem of eq. problem_linear with Z = sqrt(2/s) cos(X W + b):
  *   minimise (1/n) sum_r V(y_r, W_model^T z(x_r)) + lambda ||W_model||_F^2.
  * The ADMM penalty rho applies to n times that objective (the loss prox has
@@ -145,15 +172,20 @@ typedef struct bsadmm_problem {
   /* Penalty adaptation (not in the paper): residual balancing of Boyd,
    * Parikh, Chu, Peleato and Eckstein (2011), section 3.4.1.  After every
    * rho_adapt_every-th iteration (counted over the handle's life; 0 = fixed
-   * rho) the primal residual r (exchange residual Delta-bar and consensus
-   * residuals W - W-bar, W'_i - W-bar) and the dual residual
-   * s = rho sqrt((C+1) ||O-bar - O-bar_prev||^2 + (R+1) ||W-bar - W-bar_prev||^2)
-   * are compared: rho is multiplied by tau when r > mu s and divided by tau
-   * when s > mu r, and the scaled duals nu, mu, mu' are divided by the same
-   * factor.  The cached factors do not depend on rho.  The check and the
-   * decision run on the device, stream-ordered: no host synchronisation.  */
+   * rho) the primal residual r and the dual residual s of that iteration are
+   * compared: rho is multiplied by tau when r > mu s and divided by tau when
+   * s > mu r, and the scaled duals nu, mu, mu' are divided by the same
+   * factor.  r and s are those of ADMM on the block problem (eq. prob2)
+   * written as x = z (Boyd et al., section 3.3): x stacks O_i, W_j and the
+   * graph-projection outputs O_ij = Z_ij W'_ij, W'_ij; z their projections
+   * O-bar_i, W-bar_j, O-bar_ij (eq. obar_ij), W-bar; r = ||x - z|| and
+   * s = rho ||z - z_prev|| over every stacked copy.  In terms of the kept
+   * state, r^2 = ||Delta-bar||^2/(C+1) + ||W - W-bar||^2 + sum_i ||W'_i - W-bar||^2,
+   * and the O-bar_ij part of s uses ||Z_ij dW'_ij||^2 = <dW'_ij, dU_ij>.
+   * The cached factors do not depend on rho.  The check and the decision run
+   * on the device, stream-ordered: no host synchronisation.                */
   int32_t rho_adapt_every;  /* >= 0                                         */
-  int32_t reserved0;        /* 0                                            */
+  int32_t flags;            /* 0 or BSADMM_F_GRAPH                          */
   double rho_adapt_mu;      /* > 1; 0 selects 10                            */
   double rho_adapt_tau;     /* > 1; 0 selects 2                             */
 } bsadmm_problem;
@@ -169,8 +201,11 @@ enum {
   BSADMM_PH_COUNT = 8
 };
 
+/* Requests of bsadmm_stats.want. */
+enum { BSADMM_WANT_RESIDUALS = 1, BSADMM_WANT_OBJECTIVE = 2 };
+
 typedef struct bsadmm_stats {
-  int64_t iters_done;       /* total iterations run on the handle          */
+  int64_t iters_done;       /* out: total iterations run on the handle      */
   int32_t timed;            /* in: nonzero asks for per-phase timing        */
   int32_t launches;         /* out: launches of the regeneration kernel in
                                the call (one per row-block group per
@@ -180,7 +215,13 @@ typedef struct bsadmm_stats {
   double rho;               /* out: penalty after the call                 */
   int32_t rho_changes;      /* out: penalty changes by adaptation over the
                                handle's life                               */
-  int32_t reserved1;
+  int32_t want;             /* in: BSADMM_WANT_* bits                       */
+  double r_primal;          /* out (WANT_RESIDUALS, iters > 0): primal and   */
+  double r_dual;            /* dual residual of the call's last iteration, as
+                               defined for penalty adaptation (0 otherwise) */
+  double objective;         /* out (WANT_OBJECTIVE): F(W-bar) after the call
+                               (as bsadmm_objective; one extra regeneration
+                               pass), 0 otherwise                          */
 } bsadmm_stats;
 
 typedef struct bsadmm_handle bsadmm_handle;
@@ -254,7 +295,11 @@ BSADMM_API int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, flo
 
 /* ----------------------------------------------------------------------
  * bsadmm_get_coef -- copy the consensus model W-bar (s x m, FP64) into a
- * caller-owned device buffer.  Synchronises.  Errors: EINVAL, ESTATE.
+ * caller-owned device buffer.  The paper does not name the model a run
+ * returns; read here as W-bar, the consensus model that the root averages
+ * from the local models and distributes to every node (Algorithm 1, the
+ * reduce and broadcast of W-bar, and the schematic figure that follows it).
+ * At convergence W-bar = W = W'_i.  Synchronises.  Errors: EINVAL, ESTATE.
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_get_coef(const bsadmm_handle* h, double* Wbar);
 
@@ -278,11 +323,16 @@ enum {
 /* ----------------------------------------------------------------------
  * bsadmm_state_size -- number of doubles of state array `which`.
  * bsadmm_export_state / bsadmm_import_state -- copy one state array to /
- * from a caller-owned device buffer (checkpoint and resume: exporting all
- * BSADMM_ST_COUNT arrays, META included, and importing them into a handle
- * set up from the same inputs continues the run exactly, also under penalty
- * adaptation).  Both synchronise.  Errors: EINVAL (bad `which`, null
- * pointer, an imported META with rho <= 0 or a negative count), ESTATE.
+ * from a caller-owned device buffer, dense row-major with the sizes listed
+ * above.  The arrays are the variables Algorithm 1 initialises to zero and
+ * carries from one iteration to the next (its initialisation step), with
+ * W'_i stacked over the row blocks, so they are the whole state of the
+ * iteration: exporting all BSADMM_ST_COUNT arrays, META included, and
+ * importing them into a handle set up from the same inputs continues the
+ * run exactly, also under penalty adaptation (checkpoint and resume).  The
+ * factor cache (eq. cache) is not state: setup rebuilds it from X, W, b.
+ * Both synchronise.  Errors: EINVAL (bad `which`, null pointer, an imported
+ * META with rho <= 0 or a negative count), ESTATE.
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_state_size(const bsadmm_handle* h, int32_t which, int64_t* count);
 BSADMM_API int bsadmm_export_state(const bsadmm_handle* h, int32_t which, double* dst);
@@ -327,10 +377,15 @@ BSADMM_API int bsadmm_monitor(bsadmm_handle* h, double* out);
  * -------------------------------------------------------------------- */
 BSADMM_API int bsadmm_set_rho(bsadmm_handle* h, double rho, int32_t rescale_duals);
 
-/* bsadmm_destroy -- free everything the handle owns.  NULL is allowed. */
+/* bsadmm_destroy -- wait for the handle's stream, then free everything the
+ * handle owns: operand copies, the factor cache of eq. cache, the state and
+ * the workspaces (the memory of the paper's per-process model, eq. mem).
+ * The caller's X, Y, W, b are untouched.  NULL is allowed.  Returns OK.   */
 BSADMM_API int bsadmm_destroy(bsadmm_handle* h);
 
-/* Message of the last non-OK status on this thread ("" if none). */
+/* Message of the last non-OK status on this thread ("" if none); a library
+ * convention, not part of the method.  The string stays valid until the
+ * next call into the library on the same thread.                         */
 BSADMM_API const char* bsadmm_last_error(void);
 
 #ifdef __cplusplus

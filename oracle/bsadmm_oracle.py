@@ -358,21 +358,41 @@ def set_rho(state: dict, rho_new: float) -> dict:
     return out
 
 
-def residuals(p: Problem, state: dict, Obar_prev, Wbar_prev):
-    """(primal, dual) residual norms after an iteration.
+def residuals(p: Problem, state: dict, prev: dict, cache=None):
+    """(primal, dual) residual norms of the iteration that took ``prev`` to
+    ``state``, for ADMM on the block-splitting problem (eq. prob2) written as
+    x = z: x stacks the prox / graph-projection outputs (O_i, W_j, O_ij,
+    W_ij) and z their projections onto the constraint sets C1 and C2
+    (O-bar_i, W-bar_j, O-bar_ij, W-bar_ij = W-bar_j).  Following Boyd et al.
+    (2011, section 3.3) for that form, the primal residual is x - z and the
+    dual residual rho (z - z_prev), each over every stacked copy.
 
-    Primal: the constraint violations the iteration leaves, i.e. the exchange
-    residual O_i - sum_j O'_ij (= Delta-bar) and the consensus residuals
-    W_j - W-bar_j and W'_ij - W-bar_j.  Dual: rho times the change of the
-    averaged variables, each counted once per copy that is averaged into it
-    (C + 1 for O-bar, R + 1 for W-bar).
+    With the exchange gap Delta-bar_i = O_i - sum_j O_ij the projection gives
+    O_i - O-bar_i = Delta-bar_i / (C + 1) and O_ij - O-bar_ij = -Delta-bar_i / (C + 1)
+    (eq. obar_ij, eq. obar), so the O part of the primal residual is
+    ||Delta-bar||^2 / (C + 1).  The per-block O-bar_ij = O_ij + Delta-bar_i / (C + 1)
+    of the dual residual is rebuilt here from O_ij = Z_ij W'_ij, with O_i - Delta-bar_i
+    as sum_j O_ij.
     """
-    r2 = (np.sum(state["Dbar"] ** 2) + np.sum((state["Wc"] - state["Wbar"]) ** 2)
+    rows, cols = _blocks(p)
+    C, R = p.C, p.R
+    Dbar, Dprev = state["Dbar"], prev["Dbar"]
+    # primal: x - z over O_i, O_ij (C copies), W_j, W_ij (R copies)
+    r2 = (np.sum(Dbar ** 2) / (C + 1.0)
+          + np.sum((state["Wc"] - state["Wbar"]) ** 2)
           + np.sum((state["Wp"] - state["Wbar"][None]) ** 2))
+    # dual: change of O-bar_i, O-bar_ij, W-bar_j and its R copies W-bar_ij
+    s2 = np.sum((state["Obar"] - prev["Obar"]) ** 2)
+    s2 += (R + 1.0) * np.sum((state["Wbar"] - prev["Wbar"]) ** 2)
+    for i, (r0, r1) in enumerate(rows):
+        dgap = (Dbar[r0:r1] - Dprev[r0:r1]) / (C + 1.0)
+        for j, (c0, c1) in enumerate(cols):
+            Z = (cache.Zblock(i, j) if cache is not None
+                 else rff_block(p.X, p.W, p.b, rows[i], cols[j], p.s))
+            dOij = Z @ (state["Wp"][i, c0:c1] - prev["Wp"][i, c0:c1])
+            s2 += np.sum((dOij + dgap) ** 2)
     rho = float(state["rho"])
-    s2 = rho * rho * ((p.C + 1) * np.sum((state["Obar"] - Obar_prev) ** 2)
-                      + (p.R + 1) * np.sum((state["Wbar"] - Wbar_prev) ** 2))
-    return math.sqrt(r2), math.sqrt(s2)
+    return math.sqrt(r2), rho * math.sqrt(s2)
 
 
 def balance_factor(r: float, s: float, mu: float, tau: float) -> float:
@@ -421,7 +441,16 @@ class _BlockCache:
 def admm(p: Problem, iters: int, state=None, variant: str = "fixed",
          regenerate: bool = False, cache: _BlockCache | None = None, callback=None,
          adapt=None):
-    """Run ``iters`` iterations of the reorganised block-splitting ADMM.
+    """Run ``iters`` iterations of block-splitting ADMM in its memory-efficient
+    form: the block update equations with O_ij and O-bar_ij never stored.
+
+    Per block the graph projection (eq. gpWij with the cache of eq. cache) needs
+    Z_ij^T O-bar_ij, and O-bar_ij = O_ij + Delta-bar_i / (C + 1) (eq. obar_ij)
+    turns it into U_ij + Z_ij^T Delta-bar_i / (C + 1) with U_ij = Z_ij^T O_ij
+    kept from the previous visit; the exchange gap Delta_i = O_i - sum_j O_ij
+    and O-bar_i = C/(C+1) O_i + sum_j O_ij / (C + 1) (eq. obar) are running sums
+    over the column blocks.  Z_ij is regenerated (or taken from the cache) on
+    each visit.
 
     Returns (state, cache).  ``state`` holds O, Obar, nu, Dbar (n x m), the
     regulariser-prox output Wc, the consensus W-bar, mu (s x m), the
@@ -441,48 +470,46 @@ def admm(p: Problem, iters: int, state=None, variant: str = "fixed",
     Y = np.asarray(p.Y, dtype=np.float64)
     for it in range(iters):
         tau, kappa = weights(p, float(st["rho"]))
-        # step 4: loss prox on the row state
+        # the two prox updates: loss on O-bar_i - nu_i, regulariser on W-bar_j - mu_j
         O = prox_loss(p.loss, st["Obar"] - st["nu"], Y, tau)
-        # step 6: regulariser prox on the consensus model
         Wc = prox_l2(st["Wbar"] - st["mu"], kappa)
-        # steps 11-12
-        Delta = O.copy()
+        # running sums over the column blocks: gap O_i - sum_j O_ij and O-bar_i
+        gap = O.copy()
         Obar = (C / (C + 1.0)) * O
         Wp = np.empty_like(st["Wp"])
         U = np.empty_like(st["U"])
         for i, (r0, r1) in enumerate(rows):
-            Dbar_i = st["Dbar"][r0:r1]
-            nu_i = st["nu"][r0:r1]
+            # Z_ij^T (O-bar_ij + nu_i) = U_ij + Z_ij^T (Delta-bar_i / (C+1) + nu_i)
+            rhs_rows = st["Dbar"][r0:r1] / (C + 1.0) + st["nu"][r0:r1]
             for j, (c0, c1) in enumerate(cols):
-                Z = cache.Zblock(i, j)                       # step 15
-                L = cache.chol(i, j, Z)                      # step 16
-                A = Z.T @ (Dbar_i / (C + 1.0) + nu_i)        # step 17 (+ Z^T nu)
-                rhs = st["Wbar"][c0:c1] - st["mup"][i, c0:c1] + st["U"][i, c0:c1] + A
-                Wp[i, c0:c1] = sla.cho_solve(L, rhs)         # step 18
-                Op = Z @ Wp[i, c0:c1]                        # step 19
-                Delta[r0:r1] -= Op                           # step 20
-                U[i, c0:c1] = Z.T @ Op                       # step 21
-                Obar[r0:r1] += Op / (C + 1.0)                # step 22
-        # step 25
-        Dbar = Delta
-        # steps 27-29: consensus average over the R local models
+                Z = cache.Zblock(i, j)
+                L = cache.chol(i, j, Z)
+                rhs = (st["Wbar"][c0:c1] - st["mup"][i, c0:c1] + st["U"][i, c0:c1]
+                       + Z.T @ rhs_rows)
+                Wp[i, c0:c1] = sla.cho_solve(L, rhs)          # eq. gpWij
+                Oij = Z @ Wp[i, c0:c1]                         # eq. gpOij
+                gap[r0:r1] -= Oij
+                U[i, c0:c1] = Z.T @ Oij
+                Obar[r0:r1] += Oij / (C + 1.0)                 # eq. obar
+        Dbar = gap
+        # consensus average of W_j and the R local models W_ij
         Wbar_new = (Wc + Wp.sum(axis=0)) / (R + 1.0)
         if variant == "fixed":
             mu = st["mu"] + Wc - Wbar_new
             mup = st["mup"] + Wp - Wbar_new[None]
         elif variant == "literal_g1":
+            # Algorithm 1's order: the mu updates before the average
             mu = st["mu"] + Wc - st["Wbar"]
             mup = st["mup"] + Wp - st["Wbar"][None]
         else:
             raise ValueError(variant)
-        # step 33
         nu = st["nu"] + O - Obar
         prev = st
         st = {"O": O, "Obar": Obar, "nu": nu, "Dbar": Dbar, "Wc": Wc, "Wbar": Wbar_new,
               "mu": mu, "Wp": Wp, "mup": mup, "U": U, "rho": prev["rho"],
               "k": np.array(int(prev["k"]) + 1)}
         if adapt is not None and adapt[0] > 0 and int(st["k"]) % adapt[0] == 0:
-            r, sd = residuals(p, st, prev["Obar"], prev["Wbar"])
+            r, sd = residuals(p, st, prev, cache)
             f = balance_factor(r, sd, adapt[1], adapt[2])
             if f != 1.0:
                 st = set_rho(st, float(st["rho"]) * f)
@@ -545,6 +572,9 @@ def admm_reference(p: Problem, iters: int, callback=None):
                                 for i in range(R)]),
                 "mup": np.stack([np.concatenate([mu_ij[(i, j)] for j in range(C)])
                                  for i in range(R)]),
+                # the stacked per-block variables of the update equations
+                "Oij": dict(Oij), "Obar_ij": dict(Obar_ij), "Wij": dict(Wij),
+                "Oi": list(Oi), "Obar_i": list(Obar_i), "Wj": list(Wj), "Wbar_j": list(Wbar),
             })
     return {"Wbar": np.concatenate(Wbar), "O": np.concatenate(Oi),
             "Obar": np.concatenate(Obar_i), "nu": np.concatenate(nu)}

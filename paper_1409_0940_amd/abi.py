@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(PKG, "libbsadmm.so")
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 LOSS = {"squared": 0, "hinge": 1, "mc_hinge": 2, "l1": 3, "cs_hinge": 4, "softmax": 5}
 Z_MODE = {"auto": 0, "store": 1, "keep": 2}
+F_GRAPH = 1
+WANT_RESIDUALS, WANT_OBJECTIVE = 1, 2
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTPD", 5: "ENONFINITE",
           6: "ESTATE", 7: "ENOTIMPL"}
 STATE = {"O": 0, "Obar": 1, "nu": 2, "Dbar": 3, "Wc": 4, "Wbar": 5, "mu": 6, "Wp": 7,
@@ -38,7 +40,7 @@ class BsadmmProblem(ctypes.Structure):
         ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("W", ctypes.c_void_p),
         ("b", ctypes.c_void_p), ("stream", ctypes.c_void_p),
         ("hbm_budget_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
-        ("rho_adapt_every", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("rho_adapt_every", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("rho_adapt_mu", ctypes.c_double), ("rho_adapt_tau", ctypes.c_double),
     ]
 
@@ -47,7 +49,8 @@ class BsadmmStats(ctypes.Structure):
     _fields_ = [
         ("iters_done", ctypes.c_int64), ("timed", ctypes.c_int32), ("launches", ctypes.c_int32),
         ("phase_ms", ctypes.c_double * 8), ("iterate_ms", ctypes.c_double),
-        ("rho", ctypes.c_double), ("rho_changes", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+        ("rho", ctypes.c_double), ("rho_changes", ctypes.c_int32), ("want", ctypes.c_int32),
+        ("r_primal", ctypes.c_double), ("r_dual", ctypes.c_double), ("objective", ctypes.c_double),
     ]
 
 
@@ -146,8 +149,9 @@ def rff_map(X, W, b, precision="fp32", out=None, stream=None):
 
 def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
                  stream=None, hbm_budget_bytes=0, workspace_bytes=0, check=True, z_mode="auto",
-                 rho_adapt=None):
-    """bsadmm_problem for device tensors; rho_adapt = (every, mu, tau) or None."""
+                 rho_adapt=None, graph=False):
+    """bsadmm_problem for device tensors; rho_adapt = (every, mu, tau) or None;
+    graph=True sets BSADMM_F_GRAPH (iterations replayed as HIP graphs)."""
     n, d = X.shape
     m = Y.shape[1]
     s = W.shape[1]
@@ -170,6 +174,7 @@ def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="f
     p.workspace_bytes = workspace_bytes
     if rho_adapt is not None:
         p.rho_adapt_every, p.rho_adapt_mu, p.rho_adapt_tau = rho_adapt
+    p.flags = F_GRAPH if graph else 0
     return p
 
 
@@ -189,13 +194,21 @@ def bsadmm_setup(p):
     return h
 
 
-def bsadmm_iterate(h, iters, timed=False):
+def bsadmm_iterate(h, iters, timed=False, residuals=False, objective=False):
+    """Run iterations and return the stats; residuals / objective ask for the
+    last iteration's primal and dual residuals and for F(W-bar) afterwards."""
     st = BsadmmStats()
     st.timed = 1 if timed else 0
+    st.want = (WANT_RESIDUALS if residuals else 0) | (WANT_OBJECTIVE if objective else 0)
     _check("bsadmm_iterate", lib().bsadmm_iterate(h, iters, ctypes.byref(st)))
-    return {"iters_done": st.iters_done, "launches": st.launches, "iterate_ms": st.iterate_ms,
-            "phase_ms": {k: st.phase_ms[i] for i, k in enumerate(PHASES)},
-            "rho": st.rho, "rho_changes": st.rho_changes}
+    out = {"iters_done": st.iters_done, "launches": st.launches, "iterate_ms": st.iterate_ms,
+           "phase_ms": {k: st.phase_ms[i] for i, k in enumerate(PHASES)},
+           "rho": st.rho, "rho_changes": st.rho_changes}
+    if residuals:
+        out["r_primal"], out["r_dual"] = st.r_primal, st.r_dual
+    if objective:
+        out["objective"] = st.objective
+    return out
 
 
 def bsadmm_iterate_async(h, iters):

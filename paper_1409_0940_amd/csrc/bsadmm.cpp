@@ -100,6 +100,7 @@ int validate(const bsadmm_problem* p) {
   if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return fail(BSADMM_EINVAL, "need rho > 0");
   if (!(p->sigma > 0.0) || !std::isfinite(p->sigma)) return fail(BSADMM_EINVAL, "need sigma > 0");
   if (p->rho_adapt_every < 0) return fail(BSADMM_EINVAL, "need rho_adapt_every >= 0");
+  if (p->flags & ~BSADMM_F_GRAPH) return fail(BSADMM_EINVAL, "unknown flag bits");
   if (p->rho_adapt_mu != 0.0 && !(p->rho_adapt_mu > 1.0 && std::isfinite(p->rho_adapt_mu)))
     return fail(BSADMM_EINVAL, "rho_adapt_mu must be 0 or finite and > 1");
   if (p->rho_adapt_tau != 0.0 && !(p->rho_adapt_tau > 1.0 && std::isfinite(p->rho_adapt_tau)))
@@ -175,9 +176,10 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.b_colR = (size_t)L.R * L.spad * L.mp * 8;
   L.b_wop = (size_t)L.R * L.spad * L.mp * L.vb;
   L.b_part = (size_t)L.R * L.nsplit_max * L.spad * L.mp * L.vb;
-  L.b_small = 256 + 2 * (size_t)L.C * 8 + 6 * kMonBlocks * 8 + bs::BS_W_COUNT * 8;
-  // previous O-bar and W-bar for the dual residual of penalty adaptation
-  L.b_prev = p->rho_adapt_every > 0 ? L.b_row + L.b_col : 0;
+  L.b_small = 256 + 2 * (size_t)L.C * 8 + 9 * kMonBlocks * 8 + bs::BS_W_COUNT * 8;
+  // copies of O-bar, O, Delta-bar, W-bar, W', U from before a checked
+  // iteration, for the dual residual of penalty adaptation
+  L.b_prev = p->rho_adapt_every > 0 ? 3 * L.b_row + L.b_col + 2 * L.b_colR : 0;
   L.b_fac_tmp = (size_t)L.fac_batch * (slot + (size_t)L.S * 64 * 8);
   return BSADMM_OK;
 }
@@ -190,7 +192,8 @@ struct bsadmm_handle {
   hipStream_t st = nullptr;
   double scale = 0;
   double* wts = nullptr;  // device penalty block (bs::BS_W_*)
-  double *Obar_prev = nullptr, *Wbar_prev = nullptr;
+  double *Obar_prev = nullptr, *Wbar_prev = nullptr, *O_prev = nullptr, *Dbar_prev = nullptr,
+         *Wp_prev = nullptr, *U_prev = nullptr;
   std::vector<void*> allocs;
   void *Xp = nullptr, *Wt = nullptr, *bias = nullptr, *Z = nullptr, *Rop = nullptr,
        *Wop = nullptr, *part = nullptr;
@@ -203,6 +206,11 @@ struct bsadmm_handle {
   int64_t iters = 0;
   bool poisoned = false;
   std::vector<hipEvent_t> evpool;
+  // HIP graphs of the iteration (BSADMM_F_GRAPH): one plain and one checked
+  // iteration, and a chunk of iterations; captured on `cap`, launched on st.
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gx_one[2] = {nullptr, nullptr};
+  hipGraphExec_t gx_chunk = nullptr;
 
   // Stream-ordered allocations on the handle's stream: freeing a handle does
   // not synchronise the device, so other solves keep running.
@@ -214,6 +222,9 @@ struct bsadmm_handle {
     return e;
   }
   ~bsadmm_handle() {
+    for (hipGraphExec_t g : {gx_one[0], gx_one[1], gx_chunk})
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     for (void* a : allocs) (void)hipFreeAsync(a, st);
   }
@@ -228,7 +239,8 @@ namespace {
   } while (0)
 
 // Feature regeneration of the rows of group g into the workspace.
-hipError_t regen_group(bsadmm_handle* h, int i0, int i1, const void* Xop, int64_t xps) {
+hipError_t regen_group(bsadmm_handle* h, int i0, int i1, const void* Xop, int64_t xps,
+                       hipStream_t s) {
   const Plan& L = h->L;
   const int64_t r0 = L.rstart[i0], rows = L.rstart[i1] - r0;
   const size_t bb = L.prec == BSADMM_FP64 ? 8 : 4;
@@ -236,7 +248,7 @@ hipError_t regen_group(bsadmm_handle* h, int i0, int i1, const void* Xop, int64_
     hipError_t e = bs::regen(L.prec, (const char*)Xop + (size_t)r0 * L.Kp * L.op, xps, rows,
                              (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.s * L.Kp,
                              L.sj[j], (const char*)h->bias + (size_t)L.cstart[j] * bb, L.Kp,
-                             h->scale, (char*)h->Z + (size_t)L.coff[j] * L.zb, L.spad, h->st);
+                             h->scale, (char*)h->Z + (size_t)L.coff[j] * L.zb, L.spad, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -272,12 +284,12 @@ struct PhaseTimer {
 };
 
 // Multiply the scaled duals nu, mu, mu' by the device factor wts[BS_W_DUAL].
-hipError_t rescale_duals(bsadmm_handle* h) {
+hipError_t rescale_duals(bsadmm_handle* h, hipStream_t s) {
   const Plan& L = h->L;
   const double* f = h->wts + bs::BS_W_DUAL;
-  hipError_t e = bs::scale(h->nu, L.n * L.mp, f, h->st);
-  if (e == hipSuccess) e = bs::scale(h->mu, L.spad * L.mp, f, h->st);
-  if (e == hipSuccess) e = bs::scale(h->mup, (int64_t)L.R * L.spad * L.mp, f, h->st);
+  hipError_t e = bs::scale(h->nu, L.n * L.mp, f, s);
+  if (e == hipSuccess) e = bs::scale(h->mu, L.spad * L.mp, f, s);
+  if (e == hipSuccess) e = bs::scale(h->mup, (int64_t)L.R * L.spad * L.mp, f, s);
   return e;
 }
 
@@ -285,12 +297,212 @@ hipError_t rescale_duals(bsadmm_handle* h) {
 // by rho_old / rho.
 hipError_t apply_rho(bsadmm_handle* h, double rho, bool rescale) {
   hipError_t e = bs::set_rho(h->wts, rho, (double)h->L.n * h->p.lambda, rescale ? 1 : 0, h->st);
-  if (e == hipSuccess && rescale) e = rescale_duals(h);
+  if (e == hipSuccess && rescale) e = rescale_duals(h, h->st);
   return e;
 }
 
-int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
+// F(W) of eq. problem_linear for Wmodel (device s x m FP64) or W-bar: one
+// regeneration pass over all rows and one forward product, fixed-order sums.
+int objective_of(bsadmm_handle* h, const double* Wmodel, double* F) {
   const Plan& L = h->L;
+  hipStream_t st = h->st;
+  constexpr int NB = 1024;
+  double *wpad = nullptr, *part = nullptr;
+  void* wop = nullptr;
+  auto cleanup = [&]() {
+    if (wpad) (void)hipFreeAsync(wpad, st);
+    if (part) (void)hipFreeAsync(part, st);
+    if (wop) (void)hipFreeAsync(wop, st);
+  };
+  if (hipMallocAsync((void**)&wpad, (size_t)L.spad * L.mp * 8, st) != hipSuccess ||
+      hipMallocAsync((void**)&part, 2 * NB * 8, st) != hipSuccess ||
+      hipMallocAsync(&wop, (size_t)L.spad * L.mp * L.vb, st) != hipSuccess) {
+    cleanup();
+    return fail(BSADMM_ENOMEM, "device allocation failed in objective");
+  }
+  hipError_t e = hipSuccess;
+  if (Wmodel) {
+    e = hipMemsetAsync(wpad, 0, (size_t)L.spad * L.mp * 8, st);
+    for (int j = 0; j < L.C && e == hipSuccess; ++j)
+      e = bs::pad(Wmodel + (size_t)L.cstart[j] * L.m, L.sj[j], L.m, L.mp,
+                  wpad + (size_t)L.coff[j] * L.mp, st);
+  } else {
+    e = hipMemcpyAsync(wpad, h->Wbar, (size_t)L.spad * L.mp * 8, hipMemcpyDeviceToDevice, st);
+  }
+  if (e == hipSuccess) e = bs::to_wop(L.prec, wpad, 1, L.spad, L.mp, wop, st);
+  // forward pass Z W over all rows into the P buffer (free between iterations)
+  for (size_t g = 0; g < L.groups.size() && e == hipSuccess; ++g) {
+    const int i0 = L.groups[g].first, i1 = L.groups[g].second;
+    if (!L.keep) e = regen_group(h, i0, i1, h->Xp, L.n * L.Kp, st);
+    if (e == hipSuccess)
+      e = bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, wop, 0, L.mp, h->P, st);
+  }
+  if (e == hipSuccess)
+    e = bs::loss_partial(kernel_loss(h->p.loss), h->P, h->p.Y, L.n, L.m, L.mp, part,
+                         NB, st);
+  if (e == hipSuccess) e = bs::sumsq_partial(wpad, L.spad * L.mp, part + NB, NB, st);
+  std::vector<double> hp(2 * NB);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, 2 * NB * 8, hipMemcpyDeviceToHost, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e, "objective");
+  }
+  if (e2 != hipSuccess) {
+    h->poisoned = true;
+    return hip_fail(e2, "objective synchronize");
+  }
+  double loss = 0.0, reg = 0.0;
+  for (int k = 0; k < NB; ++k) loss += hp[k];
+  for (int k = 0; k < NB; ++k) reg += hp[NB + k];
+  *F = loss / (double)L.n + h->p.lambda * reg;
+  return BSADMM_OK;
+}
+
+// Whether iteration number `k` (1-based over the handle's life) ends with a
+// residual-balancing check.
+inline bool checked_iteration(const bsadmm_handle* h, int64_t k) {
+  const int every = h->p.rho_adapt_every;
+  return every > 0 && k % every == 0;
+}
+
+// Enqueue one iteration on stream `s` (the handle's stream, or the capture
+// stream of a HIP graph; then tm is null: no events are recorded).
+int enqueue_iteration(bsadmm_handle* h, hipStream_t s, bool check, bool want_res,
+                      PhaseTimer* tm, int& launches) {
+  const Plan& L = h->L;
+  const double cfac = 1.0 / (double)(L.C + 1);
+  const double amu = h->p.rho_adapt_mu > 0.0 ? h->p.rho_adapt_mu : 10.0;
+  const double atau = h->p.rho_adapt_tau > 0.0 ? h->p.rho_adapt_tau : 2.0;
+  const hipStream_t st = s;
+  auto begin = [&]() { if (tm) tm->begin(); };
+  auto end = [&](int ph) { if (tm) tm->end(ph); };
+  if (check || want_res) {  // the state before this iteration, for the dual residual
+    const int64_t rowc = L.n * L.mp, colc = L.spad * L.mp, colRc = (int64_t)L.R * colc;
+    HCHK(bs::copy(h->Obar_prev, h->Obar, rowc, s));
+    HCHK(bs::copy(h->O_prev, h->O, rowc, s));
+    HCHK(bs::copy(h->Dbar_prev, h->Dbar, rowc, s));
+    HCHK(bs::copy(h->Wbar_prev, h->Wbar, colc, s));
+    HCHK(bs::copy(h->Wp_prev, h->Wp, colRc, s));
+    HCHK(bs::copy(h->U_prev, h->U, colRc, s));
+  }
+  begin();
+  HCHK(bs::row_pre(L.prec, kernel_loss(h->p.loss), h->wts, cfac, L.n, L.R, L.m, L.mp, L.nbpad,
+                   h->p.Y, h->Obar, h->nu, h->Dbar, h->O, h->Rop, s));
+  end(BSADMM_PH_ROW);
+  begin();
+  HCHK(bs::col_pre(h->wts, L.spad, L.m, L.mp, h->Wbar, h->mu, h->Wc, s));
+  end(BSADMM_PH_COL);
+  for (const auto& g : L.groups) {
+    const int i0 = g.first, i1 = g.second;
+    const int64_t r0 = L.rstart[i0];
+    if (!L.keep) {  // a kept Z was generated at setup
+      begin();
+      HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp, st));
+      launches += L.C;
+      end(BSADMM_PH_REGEN);
+    }
+    begin();
+    for (int i = i0; i < i1; ++i) {
+      const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
+      const char* Ri = bs::bf16_planes(L.prec, L.mp)
+                           ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
+                           : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
+      HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb, L.spad,
+                           ni, L.spad, Ri, (int64_t)L.R * L.nbpad, L.mp, L.split_rows,
+                           (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.vb, s));
+    }
+    HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
+                        L.mp, h->Wbar, h->mup, h->U, h->rhs, s));
+    end(BSADMM_PH_ZTR);
+    begin();
+    HCHK(bs::solve(L.prec, h->Q, L.S, L.C, i0 * L.C, (i1 - i0) * L.C, h->d_coff, h->d_sj, L.spad,
+                   L.mp, h->rhs, h->Wp, h->U, h->Wop, s));
+    end(BSADMM_PH_SOLVE);
+    begin();
+    HCHK(bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, h->Wop, L.wop_stride(), L.mp, h->P,
+                s));
+    end(BSADMM_PH_ZW);
+  }
+  begin();
+  HCHK(bs::row_post(L.n, L.m, L.mp, L.C, h->O, h->P, h->Obar, h->nu, h->Dbar, s));
+  end(BSADMM_PH_ROW);
+  begin();
+  HCHK(bs::col_post(L.R, L.spad, L.m, L.mp, h->Wc, h->Wp, h->Wbar, h->mu, h->mup, s));
+  end(BSADMM_PH_COL);
+  if (check || want_res) {
+    double* sums = h->mon_part + 8 * kMonBlocks;
+    const bs::ResidualArgs ra{h->Dbar,    h->Wc,      h->Wp,        h->Wbar,      h->Obar,
+                              h->O,       h->U,       h->Obar_prev, h->Wbar_prev, h->Wp_prev,
+                              h->O_prev,  h->Dbar_prev, h->U_prev};
+    HCHK(bs::residuals(ra, L.R, L.n, L.spad, L.m, L.mp, h->mon_part, kMonBlocks, sums, s));
+    // norms at the penalty of this iteration, before a balancing step changes it
+    if (want_res) HCHK(bs::residual_norms(sums, h->wts, L.R, L.C, sums + 8, s));
+    if (check) {  // residual balancing, decided on the device (no read-back)
+      HCHK(bs::adapt(sums, h->wts, L.R, L.C, (double)L.n * h->p.lambda, amu, atau, s));
+      HCHK(rescale_duals(h, s));
+    }
+  }
+  return BSADMM_OK;
+}
+
+// Capture `count` iterations, the first of which is iteration k0 + 1 of the
+// handle's life, into an executable HIP graph (kernel nodes only).
+int capture_iterations(bsadmm_handle* h, int count, int64_t k0, hipGraphExec_t* out) {
+  *out = nullptr;
+  if (!h->cap) HCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  HCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  int launches = 0, rc = BSADMM_OK;
+  for (int t = 0; t < count && rc == BSADMM_OK; ++t)
+    rc = enqueue_iteration(h, h->cap, checked_iteration(h, k0 + t + 1), false, nullptr,
+                           launches);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap, &g);
+  if (rc != BSADMM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return BSADMM_OK;
+}
+
+// Iterations by graph replay: chunks of `chunk` iterations (one adaptation
+// period, or 16 without adaptation) where the count and alignment allow,
+// single iterations (plain or checked) otherwise.
+int replay_iterations(bsadmm_handle* h, int iters, int& launches) {
+  const Plan& L = h->L;
+  const int every = h->p.rho_adapt_every;
+  const int chunk = every > 0 ? (every <= 64 ? every : 0) : 16;
+  const int per_iter = L.keep ? 0 : L.C * (int)L.groups.size();
+  int it = 0;
+  while (it < iters) {
+    const int64_t k0 = h->iters + it;
+    const bool aligned = every > 0 ? k0 % every == 0 : true;
+    hipGraphExec_t* gx;
+    int count;
+    if (chunk > 1 && aligned && iters - it >= chunk) {
+      gx = &h->gx_chunk;
+      count = chunk;
+    } else {
+      gx = &h->gx_one[checked_iteration(h, k0 + 1) ? 1 : 0];
+      count = 1;
+    }
+    if (!*gx) {
+      int rc = capture_iterations(h, count, k0, gx);
+      if (rc) return rc;
+    }
+    HCHK(hipGraphLaunch(*gx, h->st));
+    it += count;
+    launches += count * per_iter;
+  }
+  return BSADMM_OK;
+}
+
+int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
   PhaseTimer tm{h, st && st->timed != 0};
   hipEvent_t all0 = nullptr, all1 = nullptr;
   if (st) {
@@ -299,70 +511,34 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
     if (all0) HCHK(hipEventRecord(all0, h->st));
   }
   int launches = 0;
-  const double cfac = 1.0 / (double)(L.C + 1);
-  const int every = h->p.rho_adapt_every;
-  const double amu = h->p.rho_adapt_mu > 0.0 ? h->p.rho_adapt_mu : 10.0;
-  const double atau = h->p.rho_adapt_tau > 0.0 ? h->p.rho_adapt_tau : 2.0;
-  for (int it = 0; it < iters; ++it) {
-    const bool check = every > 0 && (h->iters + it + 1) % every == 0;
-    if (check) {  // O-bar and W-bar before this iteration, for the dual residual
-      HCHK(hipMemcpyAsync(h->Obar_prev, h->Obar, L.b_row, hipMemcpyDeviceToDevice, h->st));
-      HCHK(hipMemcpyAsync(h->Wbar_prev, h->Wbar, L.b_col, hipMemcpyDeviceToDevice, h->st));
-    }
-    tm.begin();
-    HCHK(bs::row_pre(L.prec, kernel_loss(h->p.loss), h->wts, cfac, L.n, L.R, L.m,
-                     L.mp, L.nbpad, h->p.Y, h->Obar, h->nu, h->Dbar, h->O, h->Rop, h->st));
-    tm.end(BSADMM_PH_ROW);
-    tm.begin();
-    HCHK(bs::col_pre(h->wts, L.spad, L.m, L.mp, h->Wbar, h->mu, h->Wc, h->st));
-    tm.end(BSADMM_PH_COL);
-    for (const auto& g : L.groups) {
-      const int i0 = g.first, i1 = g.second;
-      const int64_t r0 = L.rstart[i0];
-      if (!L.keep) {  // a kept Z was generated at setup
-        tm.begin();
-        HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp));
-        launches += L.C;
-        tm.end(BSADMM_PH_REGEN);
-      }
-      tm.begin();
-      for (int i = i0; i < i1; ++i) {
-        const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-        const char* Ri = bs::bf16_planes(L.prec, L.mp)
-                             ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
-                             : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
-        HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb,
-                             L.spad, ni, L.spad, Ri, (int64_t)L.R * L.nbpad, L.mp, L.split_rows,
-                             (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.vb,
-                             h->st));
-      }
-      HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
-                          L.mp, h->Wbar, h->mup, h->U, h->rhs, h->st));
-      tm.end(BSADMM_PH_ZTR);
-      tm.begin();
-      HCHK(bs::solve(L.prec, h->Q, L.S, L.C, i0 * L.C, (i1 - i0) * L.C, h->d_coff, h->d_sj,
-                     L.spad, L.mp, h->rhs, h->Wp, h->U, h->Wop, h->st));
-      tm.end(BSADMM_PH_SOLVE);
-      tm.begin();
-      HCHK(bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, h->Wop, L.wop_stride(), L.mp,
-                  h->P, h->st));
-      tm.end(BSADMM_PH_ZW);
-    }
-    tm.begin();
-    HCHK(bs::row_post(L.n, L.m, L.mp, L.C, h->O, h->P, h->Obar, h->nu, h->Dbar, h->st));
-    tm.end(BSADMM_PH_ROW);
-    tm.begin();
-    HCHK(bs::col_post(L.R, L.spad, L.m, L.mp, h->Wc, h->Wp, h->Wbar, h->mu, h->mup, h->st));
-    tm.end(BSADMM_PH_COL);
-    if (check) {  // residual balancing, decided on the device (no read-back)
-      double* sums = h->mon_part + 5 * kMonBlocks;
-      HCHK(bs::residuals(h->Dbar, h->Wc, h->Wp, h->Wbar, h->Obar, h->Obar_prev, h->Wbar_prev, L.R,
-                         L.n, L.spad, L.m, L.mp, h->mon_part, kMonBlocks, sums, h->st));
-      HCHK(bs::adapt(sums, h->wts, L.R, L.C, (double)L.n * h->p.lambda, amu, atau, h->st));
-      HCHK(rescale_duals(h));
+  const bool want_res = st && (st->want & BSADMM_WANT_RESIDUALS) && iters > 0;
+  if (want_res && !h->Obar_prev) {  // state copies, allocated on first request
+    const Plan& L = h->L;
+    for (auto pr : {std::make_pair(&h->Obar_prev, L.b_row), std::make_pair(&h->O_prev, L.b_row),
+                    std::make_pair(&h->Dbar_prev, L.b_row), std::make_pair(&h->Wbar_prev, L.b_col),
+                    std::make_pair(&h->Wp_prev, L.b_colR), std::make_pair(&h->U_prev, L.b_colR)})
+      if (h->alloc((void**)pr.first, pr.second) != hipSuccess)
+        return fail(BSADMM_ENOMEM, "device allocation failed for the residual copies");
+  }
+  // with residuals asked for, the last iteration runs eagerly and reports them
+  const int bulk = want_res ? iters - 1 : iters;
+  if ((h->p.flags & BSADMM_F_GRAPH) && !tm.on) {
+    int rc = replay_iterations(h, bulk, launches);
+    if (rc) return rc;
+    h->iters += bulk;
+  } else {
+    for (int it = 0; it < bulk; ++it) {
+      int rc = enqueue_iteration(h, h->st, checked_iteration(h, h->iters + 1), false, &tm,
+                                 launches);
+      if (rc) return rc;
+      h->iters += 1;
     }
   }
-  h->iters += iters;
+  if (want_res) {
+    int rc = enqueue_iteration(h, h->st, checked_iteration(h, h->iters + 1), true, &tm, launches);
+    if (rc) return rc;
+    h->iters += 1;
+  }
   if (st) {
     if (all1) HCHK(hipEventRecord(all1, h->st));
     HCHK(hipStreamSynchronize(h->st));
@@ -381,6 +557,18 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
     st->rho = w[bs::BS_W_RHO];
     st->rho_changes = (int32_t)w[bs::BS_W_CHANGES];
     st->iters_done = h->iters;
+    st->objective = 0.0;
+    if (st->want & BSADMM_WANT_OBJECTIVE) {
+      int rc = objective_of(h, nullptr, &st->objective);
+      if (rc) return rc;
+    }
+    st->r_primal = st->r_dual = 0.0;
+    if (want_res) {
+      double rs[2];
+      HCHK(hipMemcpy(rs, h->mon_part + 8 * kMonBlocks + 8, sizeof rs, hipMemcpyDeviceToHost));
+      st->r_primal = rs[0];
+      st->r_dual = rs[1];
+    }
   }
   return BSADMM_OK;
 }
@@ -419,14 +607,18 @@ int do_setup(bsadmm_handle* h) {
   ALLOC(h->part, L.b_part);
   if (L.b_prev) {
     ALLOC(h->Obar_prev, L.b_row);
+    ALLOC(h->O_prev, L.b_row);
+    ALLOC(h->Dbar_prev, L.b_row);
     ALLOC(h->Wbar_prev, L.b_col);
+    ALLOC(h->Wp_prev, L.b_colR);
+    ALLOC(h->U_prev, L.b_colR);
   }
   ALLOC(tmp, L.b_small);
   h->dflag = (int*)tmp;
   h->d_coff = (int64_t*)((char*)tmp + 256);
   h->d_sj = h->d_coff + L.C;
   h->mon_part = (double*)(h->d_sj + L.C);
-  h->wts = h->mon_part + 6 * kMonBlocks;
+  h->wts = h->mon_part + 9 * kMonBlocks;
   hipStream_t st = h->st;
   HCHK(hipMemcpyAsync(h->d_coff, L.coff.data(), L.C * 8, hipMemcpyHostToDevice, st));
   HCHK(hipMemcpyAsync(h->d_sj, L.sj.data(), L.C * 8, hipMemcpyHostToDevice, st));
@@ -478,7 +670,7 @@ int do_setup(bsadmm_handle* h) {
   for (const auto& g : L.groups) {
     const int i0 = g.first, i1 = g.second;
     const int64_t r0 = L.rstart[i0];
-    HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp));
+    HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp, st));
     for (int i = i0; i < i1; ++i)
       for (int j = 0; j < L.C; ++j)
         HCHK(bs::gram(L.prec, (const char*)h->Z + (size_t)(L.rstart[i] - r0) * L.spad * L.zb,
@@ -757,60 +949,7 @@ int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F) {
   g_err.clear();
   if (!h || !F) return fail(BSADMM_EINVAL, "NULL argument");
   if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
-  const Plan& L = h->L;
-  hipStream_t st = h->st;
-  constexpr int NB = 1024;
-  double *wpad = nullptr, *part = nullptr;
-  void* wop = nullptr;
-  auto cleanup = [&]() {
-    if (wpad) (void)hipFreeAsync(wpad, st);
-    if (part) (void)hipFreeAsync(part, st);
-    if (wop) (void)hipFreeAsync(wop, st);
-  };
-  if (hipMallocAsync((void**)&wpad, (size_t)L.spad * L.mp * 8, st) != hipSuccess ||
-      hipMallocAsync((void**)&part, 2 * NB * 8, st) != hipSuccess ||
-      hipMallocAsync(&wop, (size_t)L.spad * L.mp * L.vb, st) != hipSuccess) {
-    cleanup();
-    return fail(BSADMM_ENOMEM, "device allocation failed in objective");
-  }
-  hipError_t e = hipSuccess;
-  if (Wmodel) {
-    e = hipMemsetAsync(wpad, 0, (size_t)L.spad * L.mp * 8, st);
-    for (int j = 0; j < L.C && e == hipSuccess; ++j)
-      e = bs::pad(Wmodel + (size_t)L.cstart[j] * L.m, L.sj[j], L.m, L.mp,
-                  wpad + (size_t)L.coff[j] * L.mp, st);
-  } else {
-    e = hipMemcpyAsync(wpad, h->Wbar, (size_t)L.spad * L.mp * 8, hipMemcpyDeviceToDevice, st);
-  }
-  if (e == hipSuccess) e = bs::to_wop(L.prec, wpad, 1, L.spad, L.mp, wop, st);
-  // forward pass Z W over all rows into the P buffer (free between iterations)
-  for (size_t g = 0; g < L.groups.size() && e == hipSuccess; ++g) {
-    const int i0 = L.groups[g].first, i1 = L.groups[g].second;
-    if (!L.keep) e = regen_group(h, i0, i1, h->Xp, L.n * L.Kp);
-    if (e == hipSuccess)
-      e = bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, wop, 0, L.mp, h->P, st);
-  }
-  if (e == hipSuccess)
-    e = bs::loss_partial(kernel_loss(h->p.loss), h->P, h->p.Y, L.n, L.m, L.mp, part,
-                         NB, st);
-  if (e == hipSuccess) e = bs::sumsq_partial(wpad, L.spad * L.mp, part + NB, NB, st);
-  std::vector<double> hp(2 * NB);
-  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, 2 * NB * 8, hipMemcpyDeviceToHost, st);
-  hipError_t e2 = hipStreamSynchronize(st);
-  cleanup();
-  if (e != hipSuccess) {
-    h->poisoned = true;
-    return hip_fail(e, "objective");
-  }
-  if (e2 != hipSuccess) {
-    h->poisoned = true;
-    return hip_fail(e2, "objective synchronize");
-  }
-  double loss = 0.0, reg = 0.0;
-  for (int k = 0; k < NB; ++k) loss += hp[k];
-  for (int k = 0; k < NB; ++k) reg += hp[NB + k];
-  *F = loss / (double)L.n + h->p.lambda * reg;
-  return BSADMM_OK;
+  return objective_of(h, Wmodel, F);
 }
 
 int bsadmm_destroy(bsadmm_handle* h) {

@@ -377,22 +377,62 @@ __global__ void diffsq_partial_kernel(const double* __restrict__ Wp, const doubl
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// part[block] = this block's share of sum (a - ap) * (b - bp) over the first
+// `m` columns of `rows` padded (ld = mp) rows.
+__global__ void diffdot_partial_kernel(const double* __restrict__ a, const double* __restrict__ ap,
+                                       const double* __restrict__ b, const double* __restrict__ bp,
+                                       int64_t rows, int64_t m, int64_t mp,
+                                       double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  GRID_STRIDE(e, rows * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    acc += (a[o] - ap[o]) * (b[o] - bp[o]);
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void copy_kernel(double* __restrict__ dst, const double* __restrict__ src,
+                            int64_t count) {
+  GRID_STRIDE(e, count) dst[e] = src[e];
+}
+
 __global__ void scale_kernel(double* __restrict__ a, int64_t count, const double* __restrict__ f) {
   const double v = *f;
   if (v == 1.0) return;
   GRID_STRIDE(e, count) a[e] *= v;
 }
 
-// Residual balancing step on the device (one thread): compares the primal
-// residual sqrt(q0 + q1 + q2) with the dual one rho sqrt((C+1) q3 + (R+1) q4)
-// and updates the penalty block; wts[BS_W_DUAL] gets the factor the scaled
-// duals must be multiplied by (1 when rho stays).
+// Residual balancing step on the device (one thread).  The sums q are those
+// of residuals(): with the exchange gap Delta-bar = O - P (P = sum_j O'_ij),
+// ADMM on the block problem written as x = z has
+//   primal^2 = ||Delta-bar||^2 / (C+1) + ||W - W-bar||^2 + sum_i ||W'_i - W-bar||^2
+// (O_i - O-bar_i = Delta-bar_i / (C+1) and O'_ij - O-bar_ij = -Delta-bar_i / (C+1)
+// for each of the C blocks), and
+//   dual^2 / rho^2 = ||dO-bar||^2 + sum_ij ||dO-bar_ij||^2 + (R+1) ||dW-bar||^2
+// with O-bar_ij = O'_ij + Delta-bar_i / (C+1).  Expanding the middle sum,
+//   sum_ij ||dO'_ij||^2 = sum_ij <dW'_ij, dU_ij>  (O'_ij = Z_ij W'_ij, U_ij = G_ij W'_ij)
+//   + 2 <dP, dDelta-bar> / (C+1) + C ||dDelta-bar||^2 / (C+1)^2,
+// and <dP, dDelta-bar> = <dO, dDelta-bar> - ||dDelta-bar||^2.  The penalty
+// block is updated; wts[BS_W_DUAL] gets the factor for the scaled duals
+// (1 when rho stays).
+__device__ inline void residual_pair(const double* __restrict__ q, double rho, int R, int C,
+                                     double& r, double& sd) {
+  const double c1 = (double)(C + 1);
+  r = sqrt(q[0] / c1 + q[1] + q[2]);
+  const double blocks = q[5] + 2.0 * (q[6] - q[7]) / c1 + (double)C * q[7] / (c1 * c1);
+  const double s2 = q[3] + (double)(R + 1) * q[4] + blocks;
+  sd = rho * sqrt(s2 > 0.0 ? s2 : 0.0);
+}
+
 __global__ void adapt_kernel(const double* __restrict__ q, double* __restrict__ wts, int R, int C,
                              double n_lambda, double mu, double tau_f) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const double rho = wts[BS_W_RHO];
-  const double r = sqrt(q[0] + q[1] + q[2]);
-  const double sd = rho * sqrt((double)(C + 1) * q[3] + (double)(R + 1) * q[4]);
+  double r, sd;
+  residual_pair(q, rho, R, C, r, sd);
   const double f = r > mu * sd ? tau_f : (sd > mu * r ? 1.0 / tau_f : 1.0);
   wts[BS_W_DUAL] = 1.0 / f;
   if (f != 1.0) {
@@ -402,6 +442,18 @@ __global__ void adapt_kernel(const double* __restrict__ q, double* __restrict__ 
     wts[BS_W_KAPPA] = n_lambda / nr;
     wts[BS_W_CHANGES] += 1.0;
   }
+}
+
+// out[0], out[1] = primal and dual residual norms from the sums q at the
+// current penalty (the same formulas as the balancing step).
+__global__ void residual_norms_kernel(const double* __restrict__ q,
+                                      const double* __restrict__ wts, int R, int C,
+                                      double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double r, sd;
+  residual_pair(q, wts[BS_W_RHO], R, C, r, sd);
+  out[0] = r;
+  out[1] = sd;
 }
 
 // Penalty set from the host: rho, the two prox weights and the dual factor
@@ -440,16 +492,26 @@ hipError_t monitor(int loss, const double* P, const float* Y, const double* Wp,
   return hipGetLastError();
 }
 
-hipError_t residuals(const double* Dbar, const double* Wc, const double* Wp, const double* Wbar,
-                     const double* Obar, const double* Obar_prev, const double* Wbar_prev, int R,
-                     int64_t n, int64_t spad, int64_t m, int64_t mp, double* part, int nb,
-                     double* out, hipStream_t st) {
-  sumsq_partial_kernel<<<nb, 256, 0, st>>>(Dbar, n * mp, part);
-  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Wc, Wbar, 1, spad, m, mp, part + nb);
-  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Wp, Wbar, R, spad, m, mp, part + 2 * nb);
-  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Obar, Obar_prev, 1, n, m, mp, part + 3 * nb);
-  diffsq_partial_kernel<<<nb, 256, 0, st>>>(Wbar, Wbar_prev, 1, spad, m, mp, part + 4 * nb);
-  final_reduce_kernel<<<5, 256, 0, st>>>(part, nb, 1.0, 1.0, 1.0, 1.0, out);
+hipError_t residuals(const ResidualArgs& a, int R, int64_t n, int64_t spad, int64_t m,
+                     int64_t mp, double* part, int nb, double* out, hipStream_t st) {
+  const int64_t cols = (int64_t)R * spad;
+  sumsq_partial_kernel<<<nb, 256, 0, st>>>(a.Dbar, n * mp, part);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(a.Wc, a.Wbar, 1, spad, m, mp, part + nb);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(a.Wp, a.Wbar, R, spad, m, mp, part + 2 * nb);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(a.Obar, a.Obar_prev, 1, n, m, mp, part + 3 * nb);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(a.Wbar, a.Wbar_prev, 1, spad, m, mp, part + 4 * nb);
+  diffdot_partial_kernel<<<nb, 256, 0, st>>>(a.Wp, a.Wp_prev, a.U, a.U_prev, cols, m, mp,
+                                             part + 5 * nb);
+  diffdot_partial_kernel<<<nb, 256, 0, st>>>(a.O, a.O_prev, a.Dbar, a.Dbar_prev, n, m, mp,
+                                             part + 6 * nb);
+  diffsq_partial_kernel<<<nb, 256, 0, st>>>(a.Dbar, a.Dbar_prev, 1, n, m, mp, part + 7 * nb);
+  final_reduce_kernel<<<8, 256, 0, st>>>(part, nb, 1.0, 1.0, 1.0, 1.0, out);
+  return hipGetLastError();
+}
+
+hipError_t copy(double* dst, const double* src, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  copy_kernel<<<grid_for(count), 256, 0, st>>>(dst, src, count);
   return hipGetLastError();
 }
 
@@ -462,6 +524,12 @@ hipError_t scale(double* a, int64_t count, const double* f, hipStream_t st) {
 hipError_t adapt(const double* sums, double* wts, int R, int C, double n_lambda, double mu,
                  double tau_f, hipStream_t st) {
   adapt_kernel<<<1, 64, 0, st>>>(sums, wts, R, C, n_lambda, mu, tau_f);
+  return hipGetLastError();
+}
+
+hipError_t residual_norms(const double* sums, const double* wts, int R, int C, double* out,
+                          hipStream_t st) {
+  residual_norms_kernel<<<1, 64, 0, st>>>(sums, wts, R, C, out);
   return hipGetLastError();
 }
 

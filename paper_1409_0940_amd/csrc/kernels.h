@@ -114,22 +114,33 @@ hipError_t unpad(const double* src, int64_t rows, int64_t m, int64_t mp, double*
                  hipStream_t st);
 hipError_t pad(const double* src, int64_t rows, int64_t m, int64_t mp, double* dst,
                hipStream_t st);
-// Penalty adaptation: out[0..4] = ||Dbar||^2, ||Wc - Wbar||^2,
-// sum_i ||Wp_i - Wbar||^2, ||Obar - Obar_prev||^2, ||Wbar - Wbar_prev||^2
-// (fixed-order sums; part holds 5 nb partials).
-hipError_t residuals(const double* Dbar, const double* Wc, const double* Wp, const double* Wbar,
-                     const double* Obar, const double* Obar_prev, const double* Wbar_prev, int R,
-                     int64_t n, int64_t spad, int64_t m, int64_t mp, double* part, int nb,
-                     double* out, hipStream_t st);
+// Penalty adaptation: the eight fixed-order sums the residual-balancing step
+// needs, from the state after an iteration and a copy of it from before:
+// out[0] = ||Dbar||^2, out[1] = ||Wc - Wbar||^2, out[2] = sum_i ||Wp_i - Wbar||^2,
+// out[3] = ||dObar||^2, out[4] = ||dWbar||^2, out[5] = <dWp, dU>,
+// out[6] = <dO, dDbar>, out[7] = ||dDbar||^2 (d: change over the iteration;
+// part holds 8 nb partials).
+struct ResidualArgs {
+  const double *Dbar, *Wc, *Wp, *Wbar, *Obar, *O, *U;
+  const double *Obar_prev, *Wbar_prev, *Wp_prev, *O_prev, *Dbar_prev, *U_prev;
+};
+hipError_t residuals(const ResidualArgs& a, int R, int64_t n, int64_t spad, int64_t m,
+                     int64_t mp, double* part, int nb, double* out, hipStream_t st);
+// dst[e] = src[e] for e < count (a kernel, so it may sit in a captured graph).
+hipError_t copy(double* dst, const double* src, int64_t count, hipStream_t st);
 // a[e] *= *f for e < count (nothing when *f == 1).
 hipError_t scale(double* a, int64_t count, const double* f, hipStream_t st);
 // Penalty block on the device (doubles): rho, the loss-prox weight 1/rho, the
 // regulariser weight n lambda / rho, the factor for the scaled duals from the
 // last change, and the number of changes made by adapt.
 enum { BS_W_RHO = 0, BS_W_TAU = 1, BS_W_KAPPA = 2, BS_W_DUAL = 3, BS_W_CHANGES = 4, BS_W_COUNT = 8 };
-// Residual balancing from the five sums of residuals(): updates wts.
+// Residual balancing from the eight sums of residuals(): updates wts.
 hipError_t adapt(const double* sums, double* wts, int R, int C, double n_lambda, double mu,
                  double tau_f, hipStream_t st);
+// out[0..1] = primal and dual residual norms from the sums of residuals() at
+// the penalty in wts (read when the kernel runs).
+hipError_t residual_norms(const double* sums, const double* wts, int R, int C, double* out,
+                          hipStream_t st);
 // wts <- penalty rho (dual factor rho_old / rho when rescale, else 1).
 hipError_t set_rho(double* wts, double rho, double n_lambda, int rescale, hipStream_t st);
 // Operand copy of nblk blocks of W' ([spad][mp] doubles each) in the layout

@@ -13,7 +13,7 @@ class Solver:
 
     def __init__(self, X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
                  stream=None, hbm_budget_bytes=0, workspace_bytes=0, z_mode="auto",
-                 rho_adapt=None):
+                 rho_adapt=None, graph=False):
         self._keep = (X, Y, W, b)
         self.n, self.d = X.shape
         self.m = Y.shape[1]
@@ -23,11 +23,11 @@ class Solver:
         self.stream = stream
         self.problem = abi.make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss, precision,
                                         stream, hbm_budget_bytes, workspace_bytes, z_mode=z_mode,
-                                        rho_adapt=rho_adapt)
+                                        rho_adapt=rho_adapt, graph=graph)
         self.h = abi.bsadmm_setup(self.problem)
 
-    def iterate(self, iters, timed=False):
-        return abi.bsadmm_iterate(self.h, iters, timed)
+    def iterate(self, iters, timed=False, residuals=False, objective=False):
+        return abi.bsadmm_iterate(self.h, iters, timed, residuals, objective)
 
     def iterate_async(self, iters):
         abi.bsadmm_iterate_async(self.h, iters)

@@ -161,8 +161,19 @@ def test_adaptation_settings_validate_and_add_buffers():
     assert abi.bsadmm_validate(_problem(adapt=(5, 5.0, 2.0))) == 0
     fixed = abi.bsadmm_footprint(_problem())
     adapt = abi.bsadmm_footprint(_problem(adapt=(10, 0.0, 0.0)))
-    n, m, s = 1000, 1, 512
-    assert adapt - fixed == n * 16 * 8 + (s // 2 // 64 * 64 * 2) * 16 * 8
+    n, mp, spad, R = 1000, 16, 512, 2
+    # copies of O-bar, O, Delta-bar (n x mp), W-bar (spad x mp), W' and U
+    # (R x spad x mp) from before a checked iteration
+    assert adapt - fixed == 3 * n * mp * 8 + spad * mp * 8 + 2 * R * spad * mp * 8
+
+
+def test_flags_validate():
+    p = _problem()
+    p.flags = abi.F_GRAPH
+    assert abi.bsadmm_validate(p) == 0
+    p.flags = 2
+    assert abi.bsadmm_validate(p) == 1
+    assert "flag" in pkg.lib().bsadmm_last_error().decode()
 
 
 def test_set_rho_rejects_bad_arguments_without_device():

@@ -111,3 +111,24 @@ def test_adaptation_speeds_up_convergence_from_a_bad_penalty():
         err[adapt is None] = np.linalg.norm(S.coef().cpu().numpy() - Wstar) / np.linalg.norm(Wstar)
         S.close()
     assert err[False] < 0.1 * err[True], err
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_stats_residuals_and_objective_match_oracle(case):
+    """bsadmm_stats r_primal / r_dual of a call's last iteration and F(W-bar)
+    after it, against the oracle's residuals and objective (FP64)."""
+    S, p, (X, Y, W, b) = _setup(case, "fp64", adapt=None)
+    st, cache = o.admm(p, 6)
+    S.iterate(6)
+    for k in (1, 4):
+        out = S.iterate(k, residuals=True, objective=True)
+        prev = st
+        if k > 1:
+            prev, cache = o.admm(p, k - 1, state=st, cache=cache)
+        st, cache = o.admm(p, 1, state=prev, cache=cache)
+        r, s = o.residuals(p, st, prev, cache)
+        assert abs(out["r_primal"] - r) <= 1e-9 * r, (out["r_primal"], r)
+        assert abs(out["r_dual"] - s) <= 1e-9 * s, (out["r_dual"], s)
+        F = o.objective(p.loss, o.rff(X, W, b), Y, st["Wbar"], p.lam)
+        assert abs(out["objective"] - F) <= 1e-10 * abs(F), (out["objective"], F)
+    S.close()
