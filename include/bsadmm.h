@@ -82,11 +82,20 @@ typedef enum {
  *           residual against the head and residual planes of R and W', the
  *           residual-by-residual term dropped, below 2^-16 of the product).
  *           rff_map returns float for BF16X3.
- *   BF16R : BF16 iterations with iterative refinement of the graph projection
- *           (see bsadmm_refine_schedule): features, Gram and products as BF16;
- *           on the refinement iterations the projection is corrected through
- *           the same FP64 factor with a residual formed from BF16X3 features. */
-enum { BSADMM_FP64 = 0, BSADMM_FP32 = 1, BSADMM_BF16 = 2, BSADMM_BF16X3 = 3 };
+ *   BF16R : BF16 iterations with iterative refinement of the products of the
+ *           graph projection (eq. gpWij).  The factor of eq. cache is built
+ *           once from FP32-faithful (BF16X3) features.  Every iteration
+ *           regenerates BF16 features Zt and runs the BF16 products; on the
+ *           first iteration and every refine_every-th after it (a refinement
+ *           iteration) it also regenerates BF16X3 features Zf, forms the
+ *           defect dZ = bf16(Zf - Zt) and the defects of both products,
+ *           dZ_ij^T R_i and sum_j dZ_ij W'_ij, which every iteration until
+ *           the next refinement adds to its BF16 products.  The added defect
+ *           is that of the last refinement's operands, so at a fixed point
+ *           the corrected products equal the FP32-faithful ones and the
+ *           iteration converges to the FP32-faithful problem's fixed point.
+ *           Objective and predictions use Zt + dZ.  rff_map rejects BF16R. */
+enum { BSADMM_FP64 = 0, BSADMM_FP32 = 1, BSADMM_BF16 = 2, BSADMM_BF16X3 = 3, BSADMM_BF16R = 4 };
 
 /* ------------------------------------------------------------------ loss */
 /* V(y, o) of eq. basicproblem, entering only through its prox (paragraph
@@ -188,6 +197,9 @@ typedef struct bsadmm_problem {
   int32_t flags;            /* 0 or BSADMM_F_GRAPH                          */
   double rho_adapt_mu;      /* > 1; 0 selects 10                            */
   double rho_adapt_tau;     /* > 1; 0 selects 2                             */
+  int32_t refine_every;     /* BF16R: iterations between refinements, >= 0;
+                               0 selects 5.  Must be 0 for other precisions */
+  int32_t reserved2;        /* 0                                            */
 } bsadmm_problem;
 
 /* Phases timed with HIP events on the handle's stream (bsadmm_stats). */
@@ -198,6 +210,8 @@ enum {
   BSADMM_PH_ZW = 3,      /* sum_j Z_ij W'_ij                                */
   BSADMM_PH_ROW = 4,     /* loss prox, exchange and nu updates              */
   BSADMM_PH_COL = 5,     /* regulariser prox, consensus and mu updates      */
+  BSADMM_PH_REFINE = 6,  /* BF16R refinement: BF16X3 features, their defect
+                            and the two defect products                    */
   BSADMM_PH_COUNT = 8
 };
 
@@ -317,7 +331,11 @@ enum {
   BSADMM_ST_U = 9,     /* R x s x m U = Z_ij^T Z_ij W'_ij                   */
   BSADMM_ST_META = 10, /* 2       penalty rho and iterations done (importing
                                   them sets both; duals are not rescaled)   */
-  BSADMM_ST_COUNT = 11
+  BSADMM_ST_COUNT = 11,
+  /* BSADMM_BF16R handles only (EINVAL otherwise): the product defects kept
+   * between refinements, part of the state of a refined run.              */
+  BSADMM_ST_DEFECT_A = 11, /* R x s x m  dZ_ij^T R_i of the last refinement  */
+  BSADMM_ST_DEFECT_P = 12  /* n x m      sum_j dZ_ij W'_ij of the last one   */
 };
 
 /* ----------------------------------------------------------------------
@@ -327,9 +345,10 @@ enum {
  * above.  The arrays are the variables Algorithm 1 initialises to zero and
  * carries from one iteration to the next (its initialisation step), with
  * W'_i stacked over the row blocks, so they are the whole state of the
- * iteration: exporting all BSADMM_ST_COUNT arrays, META included, and
- * importing them into a handle set up from the same inputs continues the
- * run exactly, also under penalty adaptation (checkpoint and resume).  The
+ * iteration: exporting all BSADMM_ST_COUNT arrays, META included (and, for
+ * BSADMM_BF16R, the two product defects), and importing them into a handle
+ * set up from the same inputs continues the run exactly, also under penalty
+ * adaptation (checkpoint and resume).  The
  * factor cache (eq. cache) is not state: setup rebuilds it from X, W, b.
  * Both synchronise.  Errors: EINVAL (bad `which`, null pointer, an imported
  * META with rho <= 0 or a negative count), ESTATE.

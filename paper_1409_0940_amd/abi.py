@@ -14,7 +14,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libbsadmm.so")
 
-PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "bf16r": 4}
 LOSS = {"squared": 0, "hinge": 1, "mc_hinge": 2, "l1": 3, "cs_hinge": 4, "softmax": 5}
 Z_MODE = {"auto": 0, "store": 1, "keep": 2}
 F_GRAPH = 1
@@ -23,7 +23,10 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTPD", 5: "ENON
           6: "ESTATE", 7: "ENOTIMPL"}
 STATE = {"O": 0, "Obar": 1, "nu": 2, "Dbar": 3, "Wc": 4, "Wbar": 5, "mu": 6, "Wp": 7,
          "mup": 8, "U": 9, "meta": 10}
-PHASES = ["regen", "ztr", "solve", "zw", "row", "col"]
+# refined BF16 handles only: the product defects kept between refinements
+STATE_REFINE = {"dA": 11, "dP": 12}
+ALL_STATE = {**STATE, **STATE_REFINE}
+PHASES = ["regen", "ztr", "solve", "zw", "row", "col", "refine"]
 
 EXPORTED = ["rff_map", "bsadmm_validate", "bsadmm_footprint", "bsadmm_setup", "bsadmm_iterate",
             "bsadmm_predict", "bsadmm_get_coef", "bsadmm_state_size", "bsadmm_export_state",
@@ -42,6 +45,7 @@ class BsadmmProblem(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
         ("rho_adapt_every", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("rho_adapt_mu", ctypes.c_double), ("rho_adapt_tau", ctypes.c_double),
+        ("refine_every", ctypes.c_int32), ("reserved2", ctypes.c_int32),
     ]
 
 
@@ -149,9 +153,10 @@ def rff_map(X, W, b, precision="fp32", out=None, stream=None):
 
 def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
                  stream=None, hbm_budget_bytes=0, workspace_bytes=0, check=True, z_mode="auto",
-                 rho_adapt=None, graph=False):
+                 rho_adapt=None, graph=False, refine_every=0):
     """bsadmm_problem for device tensors; rho_adapt = (every, mu, tau) or None;
-    graph=True sets BSADMM_F_GRAPH (iterations replayed as HIP graphs)."""
+    graph=True sets BSADMM_F_GRAPH (iterations replayed as HIP graphs);
+    refine_every: refinement period of precision "bf16r" (0: the default)."""
     n, d = X.shape
     m = Y.shape[1]
     s = W.shape[1]
@@ -175,6 +180,7 @@ def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="f
     if rho_adapt is not None:
         p.rho_adapt_every, p.rho_adapt_mu, p.rho_adapt_tau = rho_adapt
     p.flags = F_GRAPH if graph else 0
+    p.refine_every = refine_every
     return p
 
 
@@ -228,17 +234,17 @@ def bsadmm_predict(h, Xt, m, out=None, stream=None):
 
 def bsadmm_state_size(h, which):
     c = ctypes.c_int64(0)
-    _check("bsadmm_state_size", lib().bsadmm_state_size(h, STATE[which], ctypes.byref(c)))
+    _check("bsadmm_state_size", lib().bsadmm_state_size(h, ALL_STATE[which], ctypes.byref(c)))
     return c.value
 
 
 def bsadmm_export_state(h, which, out):
-    _check("bsadmm_export_state", lib().bsadmm_export_state(h, STATE[which], _ptr(out)))
+    _check("bsadmm_export_state", lib().bsadmm_export_state(h, ALL_STATE[which], _ptr(out)))
     return out
 
 
 def bsadmm_import_state(h, which, src):
-    _check("bsadmm_import_state", lib().bsadmm_import_state(h, STATE[which], _ptr(src)))
+    _check("bsadmm_import_state", lib().bsadmm_import_state(h, ALL_STATE[which], _ptr(src)))
 
 
 def bsadmm_get_coef(h, out):

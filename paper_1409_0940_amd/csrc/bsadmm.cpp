@@ -58,6 +58,12 @@ constexpr int kMonBlocks = 256;  // partial sums per monitored quantity
 // Sizes and layout derived from a problem; computed on the host only.
 struct Plan {
   int prec = 0;
+  // Refined BF16 (BSADMM_BF16R): the iteration runs the BF16 kernels (prec is
+  // BF16) and every refine_every-th iteration also regenerates FP32-faithful
+  // features (BF16X3) to refresh the stored defects of the two products.
+  bool refine = false;
+  int refine_every = 0;
+  int fprec = 0;  // feature precision of the objective and of predictions
   int64_t n = 0, d = 0, m = 0, s = 0, mp = 0, Kp = 0, spad = 0, S = 0;
   int R = 1, C = 1;
   std::vector<int64_t> rstart, cstart, coff, sj;
@@ -72,11 +78,14 @@ struct Plan {
   // byte counts
   size_t b_xp = 0, b_wt = 0, b_bias = 0, b_q = 0, b_ws = 0, b_row = 0, b_rop = 0, b_col = 0,
          b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0, b_prev = 0;
+  // refined BF16: feature defects (BF16) and FP32-faithful features of a
+  // row-block group, and the stored defects of the two products
+  size_t b_wsd = 0, b_wsf = 0, b_ca = 0, b_cp = 0;
   // operand elements between the W' copies of consecutive row blocks
   int64_t wop_stride() const { return bs::bf16_planes(prec, mp) ? 2 * mp * spad : spad * mp; }
   size_t total() const {
     return b_xp + b_wt + b_bias + b_q + b_ws + 5 * b_row + b_rop + 3 * b_col + 4 * b_colR + b_wop +
-           b_part + b_small + b_fac_tmp + b_prev;
+           b_part + b_small + b_fac_tmp + b_prev + b_wsd + b_wsf + b_ca + b_cp;
   }
 };
 
@@ -92,8 +101,11 @@ int validate(const bsadmm_problem* p) {
   if ((p->loss == BSADMM_CS_HINGE || p->loss == BSADMM_SOFTMAX) && p->m < 2)
     return fail(BSADMM_EINVAL, "CS_HINGE and SOFTMAX need m >= 2");
   if (p->reg != BSADMM_L2) return fail(BSADMM_EINVAL, "unknown regulariser");
-  if (p->precision < BSADMM_FP64 || p->precision > BSADMM_BF16X3)
+  if (p->precision < BSADMM_FP64 || p->precision > BSADMM_BF16R)
     return fail(BSADMM_EINVAL, "unknown precision");
+  if (p->refine_every < 0) return fail(BSADMM_EINVAL, "need refine_every >= 0");
+  if (p->refine_every > 0 && p->precision != BSADMM_BF16R)
+    return fail(BSADMM_EINVAL, "refine_every applies to BSADMM_BF16R only");
   if (p->z_mode != BSADMM_Z_AUTO && p->z_mode != BSADMM_Z_STORE && p->z_mode != BSADMM_Z_KEEP)
     return fail(BSADMM_EINVAL, "unknown z_mode");
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(BSADMM_EINVAL, "need lambda >= 0");
@@ -116,11 +128,16 @@ int validate(const bsadmm_problem* p) {
 int make_plan(const bsadmm_problem* p, Plan& L) {
   int rc = validate(p);
   if (rc) return rc;
-  L.prec = p->precision;
+  L.refine = p->precision == BSADMM_BF16R;
+  L.prec = L.refine ? BS_PREC_BF16 : p->precision;
+  L.refine_every = L.refine ? (p->refine_every > 0 ? p->refine_every : 5) : 0;
+  L.fprec = L.refine ? BS_PREC_BF16X3 : L.prec;
   L.n = p->n; L.d = p->d; L.m = p->m; L.s = p->s; L.R = p->R; L.C = p->C;
   L.mp = rup(L.m, 16);
   L.op = bs::op_bytes(L.prec);
-  L.planes = bs::op_planes(L.prec);
+  // refined BF16 keeps X and W as BF16 head and residual planes: the head is
+  // the BF16 operand, both planes make the BF16X3 features
+  L.planes = L.refine ? 2 : bs::op_planes(L.prec);
   L.zb = bs::z_bytes(L.prec);
   L.vb = bs::vec_bytes(L.prec);
   L.Kp = bs::padded_k(L.prec, L.d);
@@ -141,7 +158,7 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.S = rup(smax, 64);
   // Row-block groups for the Z workspace (one group of all rows when Z is kept).
   L.keep = p->z_mode == BSADMM_Z_KEEP;
-  const size_t row_bytes = (size_t)L.spad * L.zb;
+  const size_t row_bytes = (size_t)L.spad * (L.refine ? 8 : L.zb);
   if (L.keep && p->workspace_bytes && p->workspace_bytes < (size_t)L.n * row_bytes)
     return fail(BSADMM_ENOMEM, "BSADMM_Z_KEEP needs " + std::to_string((size_t)L.n * row_bytes) +
                                    " B of workspace, workspace_bytes is smaller");
@@ -168,7 +185,15 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.b_wt = (size_t)L.s * L.Kp * L.op * L.planes;
   L.b_bias = (size_t)L.s * (L.prec == BSADMM_FP64 ? 8 : 4);
   L.b_q = (size_t)L.R * L.C * slot;
-  L.b_ws = (size_t)L.ws_rows * row_bytes;
+  L.b_ws = (size_t)L.ws_rows * L.spad * L.zb;
+  if (L.refine) {
+    L.b_wsd = (size_t)L.ws_rows * L.spad * 2;
+    // a kept Z keeps its defect too; the FP32-faithful features are then
+    // needed at setup only (a temporary there)
+    L.b_wsf = L.keep ? 0 : (size_t)L.ws_rows * L.spad * 4;
+    L.b_ca = (size_t)L.R * L.spad * L.mp * 8;
+    L.b_cp = (size_t)L.n * L.mp * 8;
+  }
   L.b_row = (size_t)L.n * L.mp * 8;
   L.b_rop = bs::bf16_planes(L.prec, L.mp) ? (size_t)2 * L.mp * L.R * L.nbpad * 2
                                   : (size_t)L.n * L.mp * L.vb;
@@ -197,6 +222,8 @@ struct bsadmm_handle {
   std::vector<void*> allocs;
   void *Xp = nullptr, *Wt = nullptr, *bias = nullptr, *Z = nullptr, *Rop = nullptr,
        *Wop = nullptr, *part = nullptr;
+  void *Zd = nullptr, *Zf = nullptr;  // refined BF16: feature defect, FP32-faithful features
+  double *cA = nullptr, *cP = nullptr;  // refined BF16: stored product defects
   double *Q = nullptr, *O = nullptr, *Obar = nullptr, *nu = nullptr, *Dbar = nullptr,
          *P = nullptr, *Wbar = nullptr, *mu = nullptr, *Wc = nullptr, *Wp = nullptr,
          *mup = nullptr, *U = nullptr, *rhs = nullptr;
@@ -209,7 +236,7 @@ struct bsadmm_handle {
   // HIP graphs of the iteration (BSADMM_F_GRAPH): one plain and one checked
   // iteration, and a chunk of iterations; captured on `cap`, launched on st.
   hipStream_t cap = nullptr;
-  hipGraphExec_t gx_one[2] = {nullptr, nullptr};
+  hipGraphExec_t gx_one[4] = {nullptr, nullptr, nullptr, nullptr};  // [checked + 2 refined]
   hipGraphExec_t gx_chunk = nullptr;
 
   // Stream-ordered allocations on the handle's stream: freeing a handle does
@@ -222,7 +249,7 @@ struct bsadmm_handle {
     return e;
   }
   ~bsadmm_handle() {
-    for (hipGraphExec_t g : {gx_one[0], gx_one[1], gx_chunk})
+    for (hipGraphExec_t g : {gx_one[0], gx_one[1], gx_one[2], gx_one[3], gx_chunk})
       if (g) (void)hipGraphExecDestroy(g);
     if (cap) (void)hipStreamDestroy(cap);
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
@@ -238,20 +265,39 @@ namespace {
     if (e_ != hipSuccess) return hip_fail(e_, #expr);     \
   } while (0)
 
-// Feature regeneration of the rows of group g into the workspace.
-hipError_t regen_group(bsadmm_handle* h, int i0, int i1, const void* Xop, int64_t xps,
-                       hipStream_t s) {
+// Feature regeneration of the rows of row blocks [i0, i1) into a workspace:
+// precision `prec` (the handle's, or BF16X3 for the FP32-faithful features
+// of refined BF16), `zb` bytes per stored element.
+hipError_t regen_group(bsadmm_handle* h, int i0, int i1, hipStream_t s, int prec, void* out,
+                       size_t zb) {
   const Plan& L = h->L;
   const int64_t r0 = L.rstart[i0], rows = L.rstart[i1] - r0;
   const size_t bb = L.prec == BSADMM_FP64 ? 8 : 4;
+  const int64_t xps = L.n * L.Kp;
   for (int j = 0; j < L.C; ++j) {
-    hipError_t e = bs::regen(L.prec, (const char*)Xop + (size_t)r0 * L.Kp * L.op, xps, rows,
+    hipError_t e = bs::regen(prec, (const char*)h->Xp + (size_t)r0 * L.Kp * L.op, xps, rows,
                              (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.s * L.Kp,
                              L.sj[j], (const char*)h->bias + (size_t)L.cstart[j] * bb, L.Kp,
-                             h->scale, (char*)h->Z + (size_t)L.coff[j] * L.zb, L.spad, s);
+                             h->scale, (char*)out + (size_t)L.coff[j] * zb, L.spad, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t regen_group(bsadmm_handle* h, int i0, int i1, hipStream_t s) {
+  return regen_group(h, i0, i1, s, h->L.prec, h->Z, h->L.zb);
+}
+
+// Refined BF16: FP32-faithful features of the group into `zf`, and the
+// defect bf16(Zf - Z) of the group's BF16 features into Zd.
+hipError_t defect_group(bsadmm_handle* h, int i0, int i1, hipStream_t s, void* zf) {
+  const Plan& L = h->L;
+  hipError_t e = regen_group(h, i0, i1, s, BS_PREC_BF16X3, zf, 4);
+  const int64_t rows = L.rstart[i1] - L.rstart[i0];
+  if (e == hipSuccess)
+    e = bs::feature_defect((const float*)zf, (const uint16_t*)h->Z, (uint16_t*)h->Zd,
+                           rows * L.spad, s);
+  return e;
 }
 
 struct PhaseTimer {
@@ -307,16 +353,18 @@ int objective_of(bsadmm_handle* h, const double* Wmodel, double* F) {
   const Plan& L = h->L;
   hipStream_t st = h->st;
   constexpr int NB = 1024;
-  double *wpad = nullptr, *part = nullptr;
+  double *wpad = nullptr, *part = nullptr, *pd = nullptr;
   void* wop = nullptr;
   auto cleanup = [&]() {
     if (wpad) (void)hipFreeAsync(wpad, st);
     if (part) (void)hipFreeAsync(part, st);
     if (wop) (void)hipFreeAsync(wop, st);
+    if (pd) (void)hipFreeAsync(pd, st);
   };
   if (hipMallocAsync((void**)&wpad, (size_t)L.spad * L.mp * 8, st) != hipSuccess ||
       hipMallocAsync((void**)&part, 2 * NB * 8, st) != hipSuccess ||
-      hipMallocAsync(&wop, (size_t)L.spad * L.mp * L.vb, st) != hipSuccess) {
+      hipMallocAsync(&wop, (size_t)L.spad * L.mp * L.vb, st) != hipSuccess ||
+      (L.refine && hipMallocAsync((void**)&pd, (size_t)L.n * L.mp * 8, st) != hipSuccess)) {
     cleanup();
     return fail(BSADMM_ENOMEM, "device allocation failed in objective");
   }
@@ -330,13 +378,19 @@ int objective_of(bsadmm_handle* h, const double* Wmodel, double* F) {
     e = hipMemcpyAsync(wpad, h->Wbar, (size_t)L.spad * L.mp * 8, hipMemcpyDeviceToDevice, st);
   }
   if (e == hipSuccess) e = bs::to_wop(L.prec, wpad, 1, L.spad, L.mp, wop, st);
-  // forward pass Z W over all rows into the P buffer (free between iterations)
+  // forward pass Z W over all rows into the P buffer (free between
+  // iterations); refined BF16 adds the product with the feature defect, as
+  // its iteration does (BF16 features + defect = FP32-faithful features)
   for (size_t g = 0; g < L.groups.size() && e == hipSuccess; ++g) {
     const int i0 = L.groups[g].first, i1 = L.groups[g].second;
-    if (!L.keep) e = regen_group(h, i0, i1, h->Xp, L.n * L.Kp, st);
+    if (!L.keep) e = regen_group(h, i0, i1, st);
+    if (e == hipSuccess && L.refine && !L.keep) e = defect_group(h, i0, i1, st, h->Zf);
     if (e == hipSuccess)
       e = bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, wop, 0, L.mp, h->P, st);
+    if (e == hipSuccess && L.refine)
+      e = bs::zw(L.prec, h->Zd, L.spad, L.n, L.R, i0, i1, L.spad, wop, 0, L.mp, pd, st);
   }
+  if (e == hipSuccess && L.refine) e = bs::axpy(h->P, pd, L.n * L.mp, st);
   if (e == hipSuccess)
     e = bs::loss_partial(kernel_loss(h->p.loss), h->P, h->p.Y, L.n, L.m, L.mp, part,
                          NB, st);
@@ -367,9 +421,15 @@ inline bool checked_iteration(const bsadmm_handle* h, int64_t k) {
   return every > 0 && k % every == 0;
 }
 
+// Whether iteration `k` refreshes the product defects of refined BF16: the
+// first one and every refine_every-th after it.
+inline bool refined_iteration(const bsadmm_handle* h, int64_t k) {
+  return h->L.refine && (k - 1) % h->L.refine_every == 0;
+}
+
 // Enqueue one iteration on stream `s` (the handle's stream, or the capture
 // stream of a HIP graph; then tm is null: no events are recorded).
-int enqueue_iteration(bsadmm_handle* h, hipStream_t s, bool check, bool want_res,
+int enqueue_iteration(bsadmm_handle* h, hipStream_t s, bool check, bool refine, bool want_res,
                       PhaseTimer* tm, int& launches) {
   const Plan& L = h->L;
   const double cfac = 1.0 / (double)(L.C + 1);
@@ -399,34 +459,61 @@ int enqueue_iteration(bsadmm_handle* h, hipStream_t s, bool check, bool want_res
     const int64_t r0 = L.rstart[i0];
     if (!L.keep) {  // a kept Z was generated at setup
       begin();
-      HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp, st));
+      HCHK(regen_group(h, i0, i1, st));
       launches += L.C;
       end(BSADMM_PH_REGEN);
     }
-    begin();
-    for (int i = i0; i < i1; ++i) {
-      const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-      const char* Ri = bs::bf16_planes(L.prec, L.mp)
-                           ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
-                           : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
-      HCHK(bs::ztr_partial(L.prec, (const char*)h->Z + (size_t)(ri - r0) * L.spad * L.zb, L.spad,
-                           ni, L.spad, Ri, (int64_t)L.R * L.nbpad, L.mp, L.split_rows,
-                           (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.vb, s));
+    // transpose products Z_ij^T R_i of the row blocks of the group into the
+    // split partials (feature block z: the BF16 features or their defect)
+    auto ztr_group = [&](const void* z) -> hipError_t {
+      for (int i = i0; i < i1; ++i) {
+        const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
+        const char* Ri = bs::bf16_planes(L.prec, L.mp)
+                             ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
+                             : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
+        hipError_t e = bs::ztr_partial(
+            L.prec, (const char*)z + (size_t)(ri - r0) * L.spad * L.zb, L.spad, ni, L.spad, Ri,
+            (int64_t)L.R * L.nbpad, L.mp, L.split_rows,
+            (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.vb, s);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    if (refine) {
+      // Refinement of the projection's products: FP32-faithful features of
+      // the group, their defect against the BF16 features, and the defects
+      // of both products, kept for the BF16 iterations until the next
+      // refinement: cA_i = dZ_ij^T R_i, cP_i = sum_j dZ_ij W'_ij.
+      begin();
+      if (!L.keep) HCHK(defect_group(h, i0, i1, st, h->Zf));
+      HCHK(ztr_group(h->Zd));
+      HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
+                          L.mp, nullptr, nullptr, nullptr, nullptr, h->cA, s));
+      end(BSADMM_PH_REFINE);
     }
+    begin();
+    HCHK(ztr_group(h->Z));
     HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
-                        L.mp, h->Wbar, h->mup, h->U, h->rhs, s));
+                        L.mp, h->Wbar, h->mup, h->U, L.refine ? h->cA : nullptr, h->rhs, s));
     end(BSADMM_PH_ZTR);
     begin();
     HCHK(bs::solve(L.prec, h->Q, L.S, L.C, i0 * L.C, (i1 - i0) * L.C, h->d_coff, h->d_sj, L.spad,
                    L.mp, h->rhs, h->Wp, h->U, h->Wop, s));
     end(BSADMM_PH_SOLVE);
+    if (refine) {
+      begin();
+      HCHK(bs::zw(L.prec, h->Zd, L.spad, L.n, L.R, i0, i1, L.spad, h->Wop, L.wop_stride(), L.mp,
+                  h->cP, s));
+      end(BSADMM_PH_REFINE);
+    }
     begin();
     HCHK(bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, h->Wop, L.wop_stride(), L.mp, h->P,
                 s));
     end(BSADMM_PH_ZW);
   }
   begin();
-  HCHK(bs::row_post(L.n, L.m, L.mp, L.C, h->O, h->P, h->Obar, h->nu, h->Dbar, s));
+  HCHK(bs::row_post(L.n, L.m, L.mp, L.C, h->O, h->P, L.refine ? h->cP : nullptr, h->Obar, h->nu,
+                    h->Dbar, s));
   end(BSADMM_PH_ROW);
   begin();
   HCHK(bs::col_post(L.R, L.spad, L.m, L.mp, h->Wc, h->Wp, h->Wbar, h->mu, h->mup, s));
@@ -455,8 +542,8 @@ int capture_iterations(bsadmm_handle* h, int count, int64_t k0, hipGraphExec_t* 
   HCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
   int launches = 0, rc = BSADMM_OK;
   for (int t = 0; t < count && rc == BSADMM_OK; ++t)
-    rc = enqueue_iteration(h, h->cap, checked_iteration(h, k0 + t + 1), false, nullptr,
-                           launches);
+    rc = enqueue_iteration(h, h->cap, checked_iteration(h, k0 + t + 1),
+                           refined_iteration(h, k0 + t + 1), false, nullptr, launches);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->cap, &g);
   if (rc != BSADMM_OK) {
@@ -476,7 +563,9 @@ int capture_iterations(bsadmm_handle* h, int count, int64_t k0, hipGraphExec_t* 
 int replay_iterations(bsadmm_handle* h, int iters, int& launches) {
   const Plan& L = h->L;
   const int every = h->p.rho_adapt_every;
-  const int chunk = every > 0 ? (every <= 64 ? every : 0) : 16;
+  // no chunks under refinement: its period and the adaptation period would
+  // have to be aligned
+  const int chunk = L.refine ? 0 : (every > 0 ? (every <= 64 ? every : 0) : 16);
   const int per_iter = L.keep ? 0 : L.C * (int)L.groups.size();
   int it = 0;
   while (it < iters) {
@@ -488,7 +577,8 @@ int replay_iterations(bsadmm_handle* h, int iters, int& launches) {
       gx = &h->gx_chunk;
       count = chunk;
     } else {
-      gx = &h->gx_one[checked_iteration(h, k0 + 1) ? 1 : 0];
+      gx = &h->gx_one[(checked_iteration(h, k0 + 1) ? 1 : 0) +
+                      (refined_iteration(h, k0 + 1) ? 2 : 0)];
       count = 1;
     }
     if (!*gx) {
@@ -528,14 +618,15 @@ int run_iterations(bsadmm_handle* h, int iters, bsadmm_stats* st) {
     h->iters += bulk;
   } else {
     for (int it = 0; it < bulk; ++it) {
-      int rc = enqueue_iteration(h, h->st, checked_iteration(h, h->iters + 1), false, &tm,
-                                 launches);
+      int rc = enqueue_iteration(h, h->st, checked_iteration(h, h->iters + 1),
+                                 refined_iteration(h, h->iters + 1), false, &tm, launches);
       if (rc) return rc;
       h->iters += 1;
     }
   }
   if (want_res) {
-    int rc = enqueue_iteration(h, h->st, checked_iteration(h, h->iters + 1), true, &tm, launches);
+    int rc = enqueue_iteration(h, h->st, checked_iteration(h, h->iters + 1),
+                               refined_iteration(h, h->iters + 1), true, &tm, launches);
     if (rc) return rc;
     h->iters += 1;
   }
@@ -605,6 +696,12 @@ int do_setup(bsadmm_handle* h) {
   ALLOC(h->rhs, L.b_colR);
   ALLOC(h->Wop, L.b_wop);
   ALLOC(h->part, L.b_part);
+  if (L.refine) {
+    ALLOC(h->Zd, L.b_wsd);
+    ALLOC(h->Zf, L.b_wsf);
+    ALLOC(h->cA, L.b_ca);
+    ALLOC(h->cP, L.b_cp);
+  }
   if (L.b_prev) {
     ALLOC(h->Obar_prev, L.b_row);
     ALLOC(h->O_prev, L.b_row);
@@ -635,9 +732,17 @@ int do_setup(bsadmm_handle* h) {
     HCHK(hipMemsetAsync(z, 0, L.b_colR, st));
   HCHK(hipMemsetAsync(h->Wop, 0, L.b_wop, st));
   HCHK(hipMemsetAsync(h->Z, 0, L.b_ws, st));
-  // operands and input checks
-  HCHK(bs::prep_rows(L.prec, p.X, L.n, L.d, L.Kp, h->Xp, L.n * L.Kp, h->dflag, st));
-  HCHK(bs::prep_w(L.prec, p.W, p.b, L.d, L.s, L.Kp, h->Wt, L.s * L.Kp, h->bias, h->dflag, st));
+  if (L.refine) {  // pad columns of the workspaces stay zero
+    HCHK(hipMemsetAsync(h->Zd, 0, L.b_wsd, st));
+    if (L.b_wsf) HCHK(hipMemsetAsync(h->Zf, 0, L.b_wsf, st));
+    HCHK(hipMemsetAsync(h->cA, 0, L.b_ca, st));
+    HCHK(hipMemsetAsync(h->cP, 0, L.b_cp, st));
+  }
+  // operands and input checks (refined BF16: BF16 head and residual planes,
+  // the head being the BF16 operand)
+  const int pprec = L.refine ? BS_PREC_BF16X3 : L.prec;
+  HCHK(bs::prep_rows(pprec, p.X, L.n, L.d, L.Kp, h->Xp, L.n * L.Kp, h->dflag, st));
+  HCHK(bs::prep_w(pprec, p.W, p.b, L.d, L.s, L.Kp, h->Wt, L.s * L.Kp, h->bias, h->dflag, st));
   HCHK(bs::check_finite(p.Y, L.n * L.m, h->dflag, st));
   int flag = 0;
   HCHK(hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -667,16 +772,45 @@ int do_setup(bsadmm_handle* h) {
   }
   // Gram blocks and the FP64 inverse cache (eq. cache)
   const size_t slot = (size_t)L.S * L.S;
+  // Refined BF16 builds the cache from FP32-faithful (BF16X3) features; a
+  // kept Z also keeps its defect, formed here with a temporary for them.
+  void* zf = h->Zf;
+  if (L.refine && L.keep) {
+    hipError_t e = hipMallocAsync(&zf, (size_t)L.ws_rows * L.spad * 4, st);
+    if (e != hipSuccess) return fail(BSADMM_ENOMEM, "device allocation failed for setup features");
+    e = hipMemsetAsync(zf, 0, (size_t)L.ws_rows * L.spad * 4, st);
+    if (e != hipSuccess) {
+      (void)hipFreeAsync(zf, st);
+      return hip_fail(e, "hipMemsetAsync");
+    }
+  }
+  int grc = BSADMM_OK;
   for (const auto& g : L.groups) {
     const int i0 = g.first, i1 = g.second;
     const int64_t r0 = L.rstart[i0];
-    HCHK(regen_group(h, i0, i1, h->Xp, L.n * L.Kp, st));
-    for (int i = i0; i < i1; ++i)
-      for (int j = 0; j < L.C; ++j)
-        HCHK(bs::gram(L.prec, (const char*)h->Z + (size_t)(L.rstart[i] - r0) * L.spad * L.zb,
-                      L.spad, L.rstart[i + 1] - L.rstart[i], L.coff[j], L.sj[j],
-                      h->Q + (size_t)(i * L.C + j) * slot, L.S, st));
+    hipError_t e = hipSuccess;
+    if (L.refine) {
+      if (L.keep) e = regen_group(h, i0, i1, st);
+      if (e == hipSuccess) e = L.keep ? defect_group(h, i0, i1, st, zf)
+                                      : regen_group(h, i0, i1, st, BS_PREC_BF16X3, zf, 4);
+    } else {
+      e = regen_group(h, i0, i1, st);
+    }
+    const void* gz = L.refine ? zf : h->Z;
+    const size_t gzb = L.refine ? 4 : L.zb;
+    const int gprec = L.refine ? BS_PREC_BF16X3 : L.prec;
+    for (int i = i0; i < i1 && e == hipSuccess; ++i)
+      for (int j = 0; j < L.C && e == hipSuccess; ++j)
+        e = bs::gram(gprec, (const char*)gz + (size_t)(L.rstart[i] - r0) * L.spad * gzb, L.spad,
+                     L.rstart[i + 1] - L.rstart[i], L.coff[j], L.sj[j],
+                     h->Q + (size_t)(i * L.C + j) * slot, L.S, st);
+    if (e != hipSuccess) {
+      grc = hip_fail(e, "setup Gram");
+      break;
+    }
   }
+  if (L.refine && L.keep) (void)hipFreeAsync(zf, st);
+  if (grc) return grc;
   std::vector<int64_t> sjb((size_t)L.R * L.C);
   for (int i = 0; i < L.R; ++i)
     for (int j = 0; j < L.C; ++j) sjb[(size_t)i * L.C + j] = L.sj[j];
@@ -723,6 +857,9 @@ StateRef state_ref(const bsadmm_handle* h, int which) {
     case BSADMM_ST_MUP: return {h->mup, 2};
     case BSADMM_ST_U: return {h->U, 2};
     case BSADMM_ST_META: return {h->wts, 3};
+    // refined BF16 only (null otherwise): the stored product defects
+    case BSADMM_ST_DEFECT_A: return {h->cA, 2};
+    case BSADMM_ST_DEFECT_P: return {h->cP, 0};
     default: return {nullptr, -1};
   }
 }
@@ -730,7 +867,10 @@ StateRef state_ref(const bsadmm_handle* h, int which) {
 int copy_state(const bsadmm_handle* h, int which, double* dense, bool to_dense) {
   const Plan& L = h->L;
   StateRef s = state_ref(h, which);
-  if (!s.ptr) return fail(BSADMM_EINVAL, "unknown state array");
+  if (!s.ptr)
+    return fail(BSADMM_EINVAL, (which == BSADMM_ST_DEFECT_A || which == BSADMM_ST_DEFECT_P)
+                                   ? "product defects exist for BSADMM_BF16R handles only"
+                                   : "unknown state array");
   hipStream_t st = h->st;
   if (s.kind == 3) {  // {rho, iterations}: small synchronous copies
     double meta[2];
@@ -853,7 +993,10 @@ int bsadmm_state_size(const bsadmm_handle* h, int32_t which, int64_t* count) {
   g_err.clear();
   if (!h || !count) return fail(BSADMM_EINVAL, "NULL argument");
   StateRef s = state_ref(h, which);
-  if (!s.ptr) return fail(BSADMM_EINVAL, "unknown state array");
+  if (!s.ptr)
+    return fail(BSADMM_EINVAL, (which == BSADMM_ST_DEFECT_A || which == BSADMM_ST_DEFECT_P)
+                                   ? "product defects exist for BSADMM_BF16R handles only"
+                                   : "unknown state array");
   const Plan& L = h->L;
   *count = s.kind == 0 ? L.n * L.m
                        : (s.kind == 1 ? L.s * L.m : (s.kind == 2 ? (int64_t)L.R * L.s * L.m : 2));
@@ -901,25 +1044,29 @@ int bsadmm_predict(bsadmm_handle* h, const float* Xt, int64_t nt, float* out, vo
     if (pbuf) (void)hipFreeAsync(pbuf, st);
   };
   // own feature buffer: the handle's workspace may hold a kept Z
-  if (hipMallocAsync(&xop, (size_t)chunk * L.Kp * L.op * L.planes, st) != hipSuccess ||
-      hipMallocAsync(&wop, (size_t)L.spad * L.mp * L.vb, st) != hipSuccess ||
-      hipMallocAsync(&zt, (size_t)chunk * L.spad * L.zb, st) != hipSuccess ||
+  // refined BF16 predicts with its FP32-faithful (BF16X3) features
+  const int fp = L.fprec;
+  const size_t fzb = bs::z_bytes(fp), fvb = bs::vec_bytes(fp);
+  if (hipMallocAsync(&xop, (size_t)chunk * L.Kp * bs::op_bytes(fp) * bs::op_planes(fp), st) !=
+          hipSuccess ||
+      hipMallocAsync(&wop, (size_t)L.spad * L.mp * fvb, st) != hipSuccess ||
+      hipMallocAsync(&zt, (size_t)chunk * L.spad * fzb, st) != hipSuccess ||
       hipMallocAsync((void**)&pbuf, (size_t)chunk * L.mp * 8, st) != hipSuccess) {
     cleanup();
     return fail(BSADMM_ENOMEM, "device allocation failed in predict");
   }
   const size_t bb = L.prec == BSADMM_FP64 ? 8 : 4;
-  hipError_t e = hipMemsetAsync(zt, 0, (size_t)chunk * L.spad * L.zb, st);  // pad columns
-  if (e == hipSuccess) e = bs::to_wop(L.prec, h->Wbar, 1, L.spad, L.mp, wop, st);
+  hipError_t e = hipMemsetAsync(zt, 0, (size_t)chunk * L.spad * fzb, st);  // pad columns
+  if (e == hipSuccess) e = bs::to_wop(fp, h->Wbar, 1, L.spad, L.mp, wop, st);
   for (int64_t r0 = 0; r0 < nt && e == hipSuccess; r0 += chunk) {
     const int64_t rows = std::min(chunk, nt - r0);
-    e = bs::prep_rows(L.prec, Xt + r0 * L.d, rows, L.d, L.Kp, xop, chunk * L.Kp, nullptr, st);
+    e = bs::prep_rows(fp, Xt + r0 * L.d, rows, L.d, L.Kp, xop, chunk * L.Kp, nullptr, st);
     for (int j = 0; j < L.C && e == hipSuccess; ++j)
-      e = bs::regen(L.prec, xop, chunk * L.Kp, rows,
+      e = bs::regen(fp, xop, chunk * L.Kp, rows,
                     (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.s * L.Kp, L.sj[j],
                     (const char*)h->bias + (size_t)L.cstart[j] * bb, L.Kp, h->scale,
-                    (char*)zt + (size_t)L.coff[j] * L.zb, L.spad, st);
-    if (e == hipSuccess) e = bs::zw(L.prec, zt, L.spad, rows, 1, 0, 1, L.spad, wop, 0, L.mp, pbuf, st);
+                    (char*)zt + (size_t)L.coff[j] * fzb, L.spad, st);
+    if (e == hipSuccess) e = bs::zw(fp, zt, L.spad, rows, 1, 0, 1, L.spad, wop, 0, L.mp, pbuf, st);
     if (e == hipSuccess) e = bs::scores_out(pbuf, rows, L.m, L.mp, out + r0 * L.m, st);
   }
   hipError_t e2 = hipStreamSynchronize(st);
@@ -964,7 +1111,9 @@ int rff_map(const float* X, int64_t n, int64_t d, const float* W, const float* b
             int32_t precision, void* Z_out, void* stream) {
   g_err.clear();
   if (precision < BSADMM_FP64 || precision > BSADMM_BF16X3)
-    return fail(BSADMM_EINVAL, "unknown precision");
+    return fail(BSADMM_EINVAL, precision == BSADMM_BF16R
+                                   ? "BF16R is an iteration mode: map features with BF16 or BF16X3"
+                                   : "unknown precision");
   if (n < 0 || d < 1 || s < 1) return fail(BSADMM_EINVAL, "need n >= 0, d >= 1, s >= 1");
   if (n == 0) return BSADMM_OK;
   if (!X || !W || !b || !Z_out) return fail(BSADMM_EINVAL, "NULL pointer");

@@ -219,14 +219,21 @@ __global__ void row_pre_bf16_kernel(int loss, const double* __restrict__ wts, do
   }
 }
 
+// With Pc (the stored defect of the forward product, refined BF16) the
+// product is P + Pc, written back to P so later readers see the sum.
 __global__ void row_post_kernel(int64_t n, int64_t m, int64_t mp, double a, double bfac,
-                                const double* __restrict__ O, const double* __restrict__ P,
-                                double* __restrict__ Obar, double* __restrict__ nu,
-                                double* __restrict__ Dbar) {
+                                const double* __restrict__ O, double* __restrict__ P,
+                                const double* __restrict__ Pc, double* __restrict__ Obar,
+                                double* __restrict__ nu, double* __restrict__ Dbar) {
   GRID_STRIDE(e, n * m) {
     const int64_t r = e / m, c = e - r * m;
     const int64_t o = r * mp + c;
-    const double ov = O[o], pv = P[o];
+    double pv = P[o];
+    if (Pc) {
+      pv += Pc[o];
+      P[o] = pv;
+    }
+    const double ov = O[o];
     const double ob = a * ov + bfac * pv;
     Dbar[o] = ov - pv;
     Obar[o] = ob;
@@ -399,6 +406,10 @@ __global__ void copy_kernel(double* __restrict__ dst, const double* __restrict__
   GRID_STRIDE(e, count) dst[e] = src[e];
 }
 
+__global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x, int64_t count) {
+  GRID_STRIDE(e, count) y[e] += x[e];
+}
+
 __global__ void scale_kernel(double* __restrict__ a, int64_t count, const double* __restrict__ f) {
   const double v = *f;
   if (v == 1.0) return;
@@ -515,6 +526,12 @@ hipError_t copy(double* dst, const double* src, int64_t count, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t axpy(double* y, const double* x, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  axpy_kernel<<<grid_for(count), 256, 0, st>>>(y, x, count);
+  return hipGetLastError();
+}
+
 hipError_t scale(double* a, int64_t count, const double* f, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   scale_kernel<<<grid_for(count), 256, 0, st>>>(a, count, f);
@@ -568,10 +585,10 @@ hipError_t row_pre(int prec, int loss, const double* wts, double cfac, int64_t n
   return hipGetLastError();
 }
 
-hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, const double* P,
-                    double* Obar, double* nu, double* Dbar, hipStream_t st) {
+hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, double* P,
+                    const double* Pc, double* Obar, double* nu, double* Dbar, hipStream_t st) {
   const double a = (double)C / (double)(C + 1), bfac = 1.0 / (double)(C + 1);
-  row_post_kernel<<<grid_for(n * m), 256, 0, st>>>(n, m, mp, a, bfac, O, P, Obar, nu, Dbar);
+  row_post_kernel<<<grid_for(n * m), 256, 0, st>>>(n, m, mp, a, bfac, O, P, Pc, Obar, nu, Dbar);
   return hipGetLastError();
 }
 

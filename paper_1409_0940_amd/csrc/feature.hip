@@ -694,6 +694,36 @@ hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st
   return hipGetLastError();
 }
 
+namespace {
+// dZ = bf16(Zf - Zt) elementwise, four elements a thread (count % 4 == 0).
+__global__ void defect_kernel(const float* __restrict__ Zf, const uint16_t* __restrict__ Zt,
+                              uint16_t* __restrict__ dZ, int64_t count4) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count4;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const float4 f = reinterpret_cast<const float4*>(Zf)[q];
+    const uint2 t = reinterpret_cast<const uint2*>(Zt)[q];
+    const float d0 = f.x - bf16_to_f32((uint16_t)(t.x & 0xffffu));
+    const float d1 = f.y - bf16_to_f32((uint16_t)(t.x >> 16));
+    const float d2 = f.z - bf16_to_f32((uint16_t)(t.y & 0xffffu));
+    const float d3 = f.w - bf16_to_f32((uint16_t)(t.y >> 16));
+    uint2 o;
+    o.x = (uint32_t)f32_to_bf16(d0) | ((uint32_t)f32_to_bf16(d1) << 16);
+    o.y = (uint32_t)f32_to_bf16(d2) | ((uint32_t)f32_to_bf16(d3) << 16);
+    reinterpret_cast<uint2*>(dZ)[q] = o;
+  }
+}
+}  // namespace
+
+hipError_t feature_defect(const float* Zf, const uint16_t* Zt, uint16_t* dZ, int64_t count,
+                          hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (count % 4 != 0 || reinterpret_cast<uintptr_t>(Zf) % 16 != 0 ||
+      reinterpret_cast<uintptr_t>(Zt) % 8 != 0 || reinterpret_cast<uintptr_t>(dZ) % 8 != 0)
+    return hipErrorInvalidValue;
+  defect_kernel<<<grid_1d(count / 4, 256), 256, 0, st>>>(Zf, Zt, dZ, count / 4);
+  return hipGetLastError();
+}
+
 hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
                  int64_t cols, const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
                  hipStream_t st) {

@@ -45,6 +45,11 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
                  int64_t cols, const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
                  hipStream_t st);
 
+// Feature defect of refined BF16: dZ = bf16(Zf - Zt) for count elements
+// (count % 4 == 0; Zf 16-byte, Zt and dZ 8-byte aligned).
+hipError_t feature_defect(const float* Zf, const uint16_t* Zt, uint16_t* dZ, int64_t count,
+                          hipStream_t st);
+
 // The padded feature index: feature block j occupies [coff_j, coff_j + s_j)
 // with coff_j a multiple of 64; spad is the padded total; pad entries are 0.
 
@@ -65,11 +70,13 @@ hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64
                        const void* Rop, int64_t ldr, int64_t mp, int64_t split_rows, void* part,
                        hipStream_t st);
 // For row blocks i in [i0, i1): rhs_i = W-bar - mu'_i + U_i + sum_sp part_i[sp]
-// (part laid out [i][sp < nsplit_max][spad][mp]; the split count of block i
-// follows from the row partition of n into R blocks).
+// + corr_i (part laid out [i][sp < nsplit_max][spad][mp]; the split count of
+// block i follows from the row partition of n into R blocks).  Wbar, mup, U
+// null: the base is 0 (the plain sum of the partials); corr null: no term.
 hipError_t reduce_rhs(int prec, const void* part, int64_t nsplit_max, int64_t n, int R, int i0,
                       int i1, int64_t split_rows, int64_t spad, int64_t mp, const double* Wbar,
-                      const double* mup, const double* U, double* rhs, hipStream_t st);
+                      const double* mup, const double* U, const double* corr, double* rhs,
+                      hipStream_t st);
 // For the row blocks i in [i0, i1) of the partition of n rows into R blocks:
 // Pout[r][c] = sum_f Z[r][f] * W'_i[f][c], f < spad (a multiple of 64),
 // c < mp, W'_i in the transposed operand layout with row stride spad.  Z
@@ -103,8 +110,9 @@ hipError_t solve(int prec, const double* Q, int64_t S, int C, int b0, int nb, co
 hipError_t row_pre(int prec, int loss, const double* wts, double cfac, int64_t n, int R, int64_t m,
                    int64_t mp, int64_t nbpad, const float* Y, const double* Obar, const double* nu,
                    const double* Dbar, double* O, void* Rop, hipStream_t st);
-hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, const double* P,
-                    double* Obar, double* nu, double* Dbar, hipStream_t st);
+// Pc (nullable): defect of the forward product, added to P (and P updated).
+hipError_t row_post(int64_t n, int64_t m, int64_t mp, int C, const double* O, double* P,
+                    const double* Pc, double* Obar, double* nu, double* Dbar, hipStream_t st);
 hipError_t col_pre(const double* wts, int64_t s, int64_t m, int64_t mp, const double* Wbar,
                    const double* mu, double* Wc, hipStream_t st);
 hipError_t col_post(int R, int64_t s, int64_t m, int64_t mp, const double* Wc, const double* Wp,
@@ -128,6 +136,8 @@ hipError_t residuals(const ResidualArgs& a, int R, int64_t n, int64_t spad, int6
                      int64_t mp, double* part, int nb, double* out, hipStream_t st);
 // dst[e] = src[e] for e < count (a kernel, so it may sit in a captured graph).
 hipError_t copy(double* dst, const double* src, int64_t count, hipStream_t st);
+// y[e] += x[e] for e < count.
+hipError_t axpy(double* y, const double* x, int64_t count, hipStream_t st);
 // a[e] *= *f for e < count (nothing when *f == 1).
 hipError_t scale(double* a, int64_t count, const double* f, hipStream_t st);
 // Penalty block on the device (doubles): rho, the loss-prox weight 1/rho, the

@@ -213,12 +213,14 @@ ztr_f32_lds_kernel(const float* __restrict__ Z, int64_t ldz, int64_t rows, int64
   }
 }
 
-// rhs = W-bar - mu' + U + sum over splits (fixed order), per row block.
+// rhs = W-bar - mu' + U + sum over splits (fixed order) + corr, per row
+// block; without W-bar (null) the base is 0 and without corr nothing is added.
 template <typename A>
 __global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max, int64_t n,
                                   int R, int i0, int i1, int64_t split_rows, int64_t s, int64_t mp,
                                   const double* __restrict__ Wbar, const double* __restrict__ mup,
-                                  const double* __restrict__ U, double* __restrict__ rhs) {
+                                  const double* __restrict__ U, const double* __restrict__ corr,
+                                  double* __restrict__ rhs) {
   const int64_t per = s * mp;
   const int64_t total = (int64_t)(i1 - i0) * per;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -231,7 +233,9 @@ __global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max
     double a = 0.0;
     for (int64_t sp = 0; sp < ns; ++sp) a += (double)pp[sp * per];
     const int64_t off = (int64_t)i * per + fc;
-    rhs[off] = Wbar[fc] - mup[off] + U[off] + a;
+    double v = Wbar ? Wbar[fc] - mup[off] + U[off] + a : a;
+    if (corr) v += corr[off];
+    rhs[off] = v;
   }
 }
 
@@ -1327,16 +1331,17 @@ hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64
 
 hipError_t reduce_rhs(int prec, const void* part, int64_t nsplit_max, int64_t n, int R, int i0,
                       int i1, int64_t split_rows, int64_t s, int64_t mp, const double* Wbar,
-                      const double* mup, const double* U, double* rhs, hipStream_t st) {
+                      const double* mup, const double* U, const double* corr, double* rhs,
+                      hipStream_t st) {
   int64_t total = (int64_t)(i1 - i0) * s * mp;
   if (total <= 0) return hipSuccess;
   unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
   if (prec == BS_PREC_F64)
     reduce_rhs_kernel<double><<<g, 256, 0, st>>>((const double*)part, nsplit_max, n, R, i0, i1,
-                                                 split_rows, s, mp, Wbar, mup, U, rhs);
+                                                 split_rows, s, mp, Wbar, mup, U, corr, rhs);
   else
     reduce_rhs_kernel<float><<<g, 256, 0, st>>>((const float*)part, nsplit_max, n, R, i0, i1,
-                                                split_rows, s, mp, Wbar, mup, U, rhs);
+                                                split_rows, s, mp, Wbar, mup, U, corr, rhs);
   return hipGetLastError();
 }
 

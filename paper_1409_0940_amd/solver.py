@@ -13,7 +13,7 @@ class Solver:
 
     def __init__(self, X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
                  stream=None, hbm_budget_bytes=0, workspace_bytes=0, z_mode="auto",
-                 rho_adapt=None, graph=False):
+                 rho_adapt=None, graph=False, refine_every=0):
         self._keep = (X, Y, W, b)
         self.n, self.d = X.shape
         self.m = Y.shape[1]
@@ -23,7 +23,9 @@ class Solver:
         self.stream = stream
         self.problem = abi.make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss, precision,
                                         stream, hbm_budget_bytes, workspace_bytes, z_mode=z_mode,
-                                        rho_adapt=rho_adapt, graph=graph)
+                                        rho_adapt=rho_adapt, graph=graph,
+                                        refine_every=refine_every)
+        self.precision = precision
         self.h = abi.bsadmm_setup(self.problem)
 
     def iterate(self, iters, timed=False, residuals=False, objective=False):
@@ -36,13 +38,20 @@ class Solver:
         count = abi.bsadmm_state_size(self.h, name)
         out = torch.empty(count, dtype=torch.float64, device=self.device)
         abi.bsadmm_export_state(self.h, name, out)
-        if name in ("O", "Obar", "nu", "Dbar"):
+        if name in ("O", "Obar", "nu", "Dbar", "dP"):
             return out.view(self.n, self.m)
         if name in ("Wc", "Wbar", "mu"):
             return out.view(self.s, self.m)
         if name == "meta":
             return out                        # [rho, iterations done]
         return out.view(self.R, self.s, self.m)
+
+    def state_names(self):
+        """Every exported array of the run's state (checkpoint order)."""
+        names = list(abi.STATE)
+        if self.precision == "bf16r":
+            names += list(abi.STATE_REFINE)
+        return names
 
     def set_rho(self, rho, rescale_duals=True):
         """New ADMM penalty; the duals are rescaled to keep the fixed point."""

@@ -180,3 +180,25 @@ def test_set_rho_rejects_bad_arguments_without_device():
     L = pkg.lib()
     assert L.bsadmm_set_rho(None, 1.0, 1) == 1
     assert "NULL" in L.bsadmm_last_error().decode()
+
+
+def test_refine_settings_validate():
+    p = _problem(precision="bf16r")
+    assert abi.bsadmm_validate(p) == 0
+    p.refine_every = 3
+    assert abi.bsadmm_validate(p) == 0
+    p.refine_every = -1
+    assert abi.bsadmm_validate(p) == 1
+    q = _problem(precision="bf16")
+    q.refine_every = 3
+    assert abi.bsadmm_validate(q) == 1
+    assert "BF16R" in pkg.lib().bsadmm_last_error().decode()
+    # rff_map maps features only: BF16R is rejected before any device call
+    assert pkg.lib().rff_map(None, 4, 4, None, None, 4, abi.PRECISION["bf16r"], None, None) == 1
+    assert "iteration mode" in pkg.lib().bsadmm_last_error().decode()
+
+
+def test_refine_footprint_adds_defect_buffers():
+    base = abi.bsadmm_footprint(_problem(precision="bf16"))
+    ref = abi.bsadmm_footprint(_problem(precision="bf16r"))
+    assert ref > base

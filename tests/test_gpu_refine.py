@@ -1,0 +1,114 @@
+"""Refined BF16 (BSADMM_BF16R): BF16 iterations whose two Z products are
+corrected by defects refreshed from FP32-faithful (BF16X3) features every
+refine_every-th iteration, against the FP64 oracle and against plain BF16.
+
+Bars: relative objective error at the same iteration count <= 1e-4 (the
+after-refinement bar; plain BF16 only has to meet 1e-2) and, refining every
+fifth iteration, a consensus model at least three times closer to the
+oracle's than plain BF16's on the same inputs (max error over max
+magnitude); refining every iteration, the FP32 bars on every state array.  Kept and regenerated
+Z, graph replay and checkpoint / resume must give bit for bit the same run.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import bsadmm_oracle as o
+from tests._gpu import inputs, rel_err, rel_obj_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # name, kind, n, d, s, m, R, C, loss, sigma, lam, rho
+    ("digits_sq_4x3", "digits", 4000, 784, 700, 10, 4, 3, "squared", 10.0, 1e-4, 1.0),
+    ("mc_hinge_2x2", "digits_pm1", 3000, 784, 512, 5, 2, 2, "mc_hinge", 10.0, 1e-3, 1.0),
+    ("speech_m147_2x3", "speech_pm1", 3000, 440, 530, 147, 2, 3, "mc_hinge", 8.0, 1e-3, 1.0),
+    ("ridge_1x2", "sine", 4096, 16, 512, 1, 1, 2, "squared", 4.0, 1e-3, 1.0),
+]
+
+
+def _solver(case, prec, **kw):
+    from paper_1409_0940_amd import Solver
+    _, kind, n, d, s, m, R, C, loss, sigma, lam, rho = case
+    X, Y, W, b = inputs(kind, n, d, s, m, 17, sigma)
+    S = Solver(to_dev(X), to_dev(Y), to_dev(W), to_dev(b), R, C, lam, rho, sigma, loss, prec, **kw)
+    return S, o.Problem(X, Y, W, b, R, C, lam, rho, loss), (X, Y, W, b)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_bf16r_meets_the_refined_bar_and_beats_bf16(case):
+    """Every fifth iteration refined: the objective bar of refined BF16 and a
+    model at least three times closer to the oracle's than plain BF16's."""
+    iters = 40
+    S, p, (X, Y, W, b) = _solver(case, "bf16r", refine_every=5)
+    S.iterate(iters)
+    Wr = S.coef().cpu().numpy()
+    S.close()
+    B, _, _ = _solver(case, "bf16")
+    B.iterate(iters)
+    Wb = B.coef().cpu().numpy()
+    B.close()
+    st, _ = o.admm(p, iters)
+    e_r, e_b = rel_err(Wr, st["Wbar"]), rel_err(Wb, st["Wbar"])
+    assert e_r <= 0.3 * e_b, (e_r, e_b)
+    assert rel_obj_err(p.loss, X, Y, W, b, Wr, st["Wbar"], p.lam) <= 1e-4
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_bf16r_refined_every_iteration_has_fp32_faithful_products(case):
+    """With refine_every = 1 every product is BF16 features plus their fresh
+    defect, i.e. FP32-faithful: the state meets the FP32 bars (1e-3 per
+    array, 1e-4 objective)."""
+    from tests._gpu import BLK_NAMES, COL_NAMES, ROW_NAMES
+    S, p, (X, Y, W, b) = _solver(case, "bf16r", refine_every=1)
+    S.iterate(20)
+    st, _ = o.admm(p, 20)
+    for name in ROW_NAMES + COL_NAMES + BLK_NAMES:
+        g = S.state(name).cpu().numpy()
+        assert rel_err(g, st[name]) <= 1e-3, (name, rel_err(g, st[name]))
+    Wg = S.coef().cpu().numpy()
+    assert rel_obj_err(p.loss, X, Y, W, b, Wg, st["Wbar"], p.lam) <= 1e-4
+    S.close()
+
+
+def test_bf16r_kept_z_graph_and_checkpoint_are_bitwise():
+    case = CASES[2]
+    runs = []
+    for kw in (dict(), dict(z_mode="keep"), dict(graph=True)):
+        S, _, _ = _solver(case, "bf16r", refine_every=3, **kw)
+        for k in (1, 4, 2, 7):          # 14 iterations over several calls
+            if kw.get("graph"):
+                S.iterate_async(k)
+            else:
+                S.iterate(k)
+        runs.append({k: S.state(k).cpu().numpy() for k in S.state_names()})
+        S.close()
+    for r in runs[1:]:
+        for k in runs[0]:
+            assert np.array_equal(runs[0][k], r[k]), k
+    # checkpoint after 8 iterations (not a refinement iteration) and resume
+    S, _, _ = _solver(case, "bf16r", refine_every=3)
+    S.iterate(8)
+    saved = {k: S.state(k).clone() for k in S.state_names()}
+    S.close()
+    T, _, _ = _solver(case, "bf16r", refine_every=3)
+    for k, v in saved.items():
+        T.set_state(k, v)
+    T.iterate(6)
+    for k in runs[0]:
+        assert np.array_equal(T.state(k).cpu().numpy(), runs[0][k]), k
+    T.close()
+
+
+def test_bf16r_objective_and_predict_use_fp32_faithful_features():
+    case = CASES[0]
+    S, p, (X, Y, W, b) = _solver(case, "bf16r")
+    S.iterate(10)
+    Wg = S.coef().cpu().numpy()
+    Fo = o.objective(p.loss, o.rff(X, W, b), Y, Wg, p.lam)
+    assert abs(S.objective() - Fo) <= 1e-5 * abs(Fo)
+    Xt = X[:700]
+    ref = o.predict(Xt, W, b, Wg)
+    got = S.predict(to_dev(Xt)).cpu().numpy().astype(np.float64)
+    assert rel_err(got, ref) <= 1e-4
+    S.close()
