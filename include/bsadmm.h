@@ -255,6 +255,31 @@ BSADMM_API int rff_map(const float* X, int64_t n, int64_t d, const float* W, con
             int64_t s, int32_t precision, void* Z_out, void* stream);
 
 /* ----------------------------------------------------------------------
+ * rff_map_noalloc -- rff_map for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, layouts and results as rff_map (the same
+ * kernels, so the same bits), but it allocates nothing and does not
+ * synchronise: the operand staging lives in a 64 MiB array the library keeps
+ * on each GPU for the life of the process, and the work is only enqueued on
+ * `stream`.  The caller still passes X, W, b and Z_out.
+ * Limit: W staged in the operand layout (s x Kp elements of 8, 4 or 2 bytes,
+ * two planes for BF16X3; Kp = d rounded up to the kernel's K chunk) plus the
+ * s offsets plus 256 rows of X must fit in the 64 MiB; X is staged in row
+ * chunks, so n is not limited.  Larger problems fail with EINVAL and a
+ * message naming the limit.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on a
+ * GPU (different streams, or host threads, without ordering between them)
+ * race and may return wrong features.  Order them on one stream or
+ * synchronise between them.  Nothing in the scratch needs to start at zero
+ * (each call writes all staging it reads).
+ * Errors: as rff_map (EINVAL also for the size limit); device errors of the
+ * enqueued kernels surface at the caller's next synchronisation.
+ * -------------------------------------------------------------------- */
+BSADMM_API int rff_map_noalloc(const float* X, int64_t n, int64_t d, const float* W,
+                               const float* b, int64_t s, int32_t precision, void* Z_out,
+                               void* stream);
+
+/* ----------------------------------------------------------------------
  * bsadmm_validate -- host-only argument checks of a problem (no HIP call,
  * no device access): n >= R >= 1, s >= C >= 1, d >= 1, 1 <= m <= 1024,
  * m == 1 for HINGE, m >= 2 for CS_HINGE and SOFTMAX, lambda >= 0, rho > 0,

@@ -28,7 +28,7 @@ STATE_REFINE = {"dA": 11, "dP": 12}
 ALL_STATE = {**STATE, **STATE_REFINE}
 PHASES = ["regen", "ztr", "solve", "zw", "row", "col", "refine"]
 
-EXPORTED = ["rff_map", "bsadmm_validate", "bsadmm_footprint", "bsadmm_setup", "bsadmm_iterate",
+EXPORTED = ["rff_map", "rff_map_noalloc", "bsadmm_validate", "bsadmm_footprint", "bsadmm_setup", "bsadmm_iterate",
             "bsadmm_predict", "bsadmm_get_coef", "bsadmm_state_size", "bsadmm_export_state",
             "bsadmm_import_state", "bsadmm_objective", "bsadmm_monitor", "bsadmm_set_rho",
             "bsadmm_destroy", "bsadmm_last_error"]
@@ -78,6 +78,7 @@ def lib():
         vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         PP = ctypes.POINTER(BsadmmProblem)
         L.rff_map.argtypes = [vp, i64, i64, vp, vp, i64, i32, vp, vp]
+        L.rff_map_noalloc.argtypes = [vp, i64, i64, vp, vp, i64, i32, vp, vp]
         L.bsadmm_validate.argtypes = [PP]
         L.bsadmm_footprint.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
         L.bsadmm_setup.argtypes = [PP, ctypes.POINTER(vp)]
@@ -148,6 +149,22 @@ def rff_map(X, W, b, precision="fp32", out=None, stream=None):
         out = torch.empty((n, s), dtype=dt, device=X.device)
     _check("rff_map", lib().rff_map(_ptr(X), n, d, _ptr(W), _ptr(b), s, PRECISION[precision],
                                     _ptr(out), _stream(stream)))
+    return out
+
+
+def rff_map_noalloc(X, W, b, precision, out, stream=None):
+    """rff_map through the entry point that allocates nothing: the caller
+    passes the output (n x s, dtype of the precision); work is only enqueued."""
+    n, d = X.shape
+    s = W.shape[1]
+    _need_cuda_f32("X", X, (n, d))
+    _need_cuda_f32("W", W, (d, s))
+    _need_cuda_f32("b", b, (s,))
+    if tuple(out.shape) != (n, s) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous n x s tensor")
+    _check("rff_map_noalloc", lib().rff_map_noalloc(_ptr(X), n, d, _ptr(W), _ptr(b), s,
+                                                    PRECISION[precision], _ptr(out),
+                                                    _stream(stream)))
     return out
 
 

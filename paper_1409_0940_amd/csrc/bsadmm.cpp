@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -912,6 +913,36 @@ int copy_state(const bsadmm_handle* h, int which, double* dense, bool to_dense) 
   return BSADMM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of rff_map_noalloc: the operand staging that rff_map allocates per
+// call (W and b in the operand layout, a chunk of X rows) lives here instead.
+// Each GPU the library runs on holds its own copy until the process ends.  In
+// host code `scratch` only names the symbol: its device address on the
+// current device comes from hipGetSymbolAddress, looked up once per device on
+// the first call there and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(void** out) {
+  int dev = -1;
+  HCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(BSADMM_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(BSADMM_EDEVICE, "hipGetSymbolAddress returned NULL for the scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BSADMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1141,6 +1172,49 @@ int rff_map(const float* X, int64_t n, int64_t d, const float* W, const float* b
   cleanup();
   if (e != hipSuccess) return hip_fail(e, "rff_map");
   if (e2 != hipSuccess) return hip_fail(e2, "rff_map synchronize");
+  return BSADMM_OK;
+}
+
+int rff_map_noalloc(const float* X, int64_t n, int64_t d, const float* W, const float* b,
+                    int64_t s, int32_t precision, void* Z_out, void* stream) {
+  g_err.clear();
+  if (precision < BSADMM_FP64 || precision > BSADMM_BF16X3)
+    return fail(BSADMM_EINVAL, precision == BSADMM_BF16R
+                                   ? "BF16R is an iteration mode: map features with BF16 or BF16X3"
+                                   : "unknown precision");
+  if (n < 0 || d < 1 || s < 1) return fail(BSADMM_EINVAL, "need n >= 0, d >= 1, s >= 1");
+  if (n == 0) return BSADMM_OK;
+  if (!X || !W || !b || !Z_out) return fail(BSADMM_EINVAL, "NULL pointer");
+  // scratch layout: Wt (s x Kp operand planes), bias, then X rows in chunks
+  const int64_t Kp = bs::padded_k(precision, d);
+  const size_t opb = bs::op_bytes(precision) * bs::op_planes(precision);
+  const size_t wbytes = (size_t)rup((int64_t)s * Kp * (int64_t)opb, 256);
+  const size_t bbytes = (size_t)rup(s * (precision == BSADMM_FP64 ? 8 : 4), 256);
+  const size_t row_bytes = (size_t)Kp * opb;
+  constexpr int64_t kMinChunk = 256;
+  if (wbytes + bbytes + (size_t)kMinChunk * row_bytes > kScratchBytes)
+    return fail(BSADMM_EINVAL, "rff_map_noalloc: W (" + std::to_string(wbytes) + " B staged) and " +
+                                   "256 rows of X need more than the " +
+                                   std::to_string(kScratchBytes >> 20) + " MiB scratch");
+  int64_t chunk = (int64_t)((kScratchBytes - wbytes - bbytes) / row_bytes) / kMinChunk * kMinChunk;
+  chunk = std::min<int64_t>(chunk, n);
+  void* base = nullptr;
+  int rc = scratch_ptr(&base);
+  if (rc) return rc;
+  char* wt = (char*)base;
+  char* bias = wt + wbytes;
+  char* xop = bias + bbytes;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t zb = bs::z_bytes(precision);
+  hipError_t e = bs::prep_w(precision, W, b, d, s, Kp, wt, s * Kp, bias, nullptr, st);
+  for (int64_t r0 = 0; r0 < n && e == hipSuccess; r0 += chunk) {
+    const int64_t rows = std::min(chunk, n - r0);
+    e = bs::prep_rows(precision, X + r0 * d, rows, d, Kp, xop, chunk * Kp, nullptr, st);
+    if (e == hipSuccess)
+      e = bs::regen(precision, xop, chunk * Kp, rows, wt, s * Kp, s, bias, Kp,
+                    std::sqrt(2.0 / (double)s), (char*)Z_out + (size_t)r0 * s * zb, s, st);
+  }
+  if (e != hipSuccess) return hip_fail(e, "rff_map_noalloc");
   return BSADMM_OK;
 }
 

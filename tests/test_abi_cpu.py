@@ -202,3 +202,13 @@ def test_refine_footprint_adds_defect_buffers():
     base = abi.bsadmm_footprint(_problem(precision="bf16"))
     ref = abi.bsadmm_footprint(_problem(precision="bf16r"))
     assert ref > base
+
+
+def test_noalloc_rejects_oversize_before_any_device_call():
+    # W of 12000 x 784 doubles (75 MB) does not fit the 64 MiB scratch; fake
+    # pointers: the size check comes before any device work
+    L = pkg.lib()
+    rc = L.rff_map_noalloc(0x10000, 256, 784, 0x20000, 0x30000, 12000, 0, 0x40000, None)
+    assert rc == 1
+    assert "MiB scratch" in L.bsadmm_last_error().decode()
+    assert L.rff_map_noalloc(None, 0, 4, None, None, 4, 1, None, None) == 0   # n = 0: no work
