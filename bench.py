@@ -1,41 +1,70 @@
 """Benchmark: ADMM iterations per second of block-splitting ADMM over random
-Fourier features on one MI355X, with the roofline of the dominant kernel and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+Fourier features on one MI355X, with the roofline of the dominant kernel, the
+error of every result against the FP64 oracle, and the oracle itself timed on
+the host cores on a bounded sample of the same workload.
 
 A step is one full iteration of Algorithm 1 (regeneration of every block of
 Z, both Z products, the graph-projection solves, prox / consensus / dual
 updates) over the whole problem; setup (Gram + FP64 inverse cache) is timed
 separately.  Inputs are synthetic and resident in HBM before timing.
 
-Default workload: digit-like inputs n = 200000, d = 784, m = 10 one-hot
-classes, sigma = 10, s = 10240 random features, 4 x 4 blocks, squared loss,
-lambda = 1e-4, rho = 1, FP32 arithmetic.  The same iteration count is also
-run in the plain FP64 form, in BF16 and in refined BF16 (BF16X3); each
-model's objective is evaluated with the FP64 form's feature map and reported
-as a relative error against the FP64 form's objective.
+Headline (the JSON line's value): the digit-like workload n = 200000,
+d = 784, m = 10 one-hot classes, sigma = 10, s = 10240 random features, 4 x 4
+blocks, squared loss, lambda = 1e-4, rho = 1, FP32 arithmetic.  The same
+workload is also run in the plain FP64 form, in BF16, in split-operand BF16
+(BF16X3), in refined BF16 (BF16R, at several refinement periods) and with Z
+kept in HBM.  Three more workloads get records of their own under
+"workloads": the FP64 ridge (n = 4096, 1 x 2, 100 iterations; eager launches
+and HIP-graph replay), the speech-like one (n = 100000, d = 440, s = 32768,
+m = 147, one-vs-all hinge, 4 x 8) in FP32, FP64, BF16, BF16X3 and BF16R, and
+the 2M-row one (s = 65536, 16 x 8, Z never stored) in BF16, BF16X3, BF16R.
+
+Errors: every run of a workload with a committed oracle golden
+(tests/golden/oracle_*.npz, written by the oracle) repeats the golden's
+iteration count and reports the relative objective error
+|F(W-bar) - F_oracle| / |F_oracle| and the coefficient error
+||W-bar - W-bar_oracle|| / ||W-bar_oracle|| over the golden's sampled feature
+rows.  F(W-bar) of a GPU model is evaluated on the device with FP64 features
+(BF16X3 features for the 2M-row workload, whose golden is its first two row
+blocks: the same d, s, s_j, C and m on a 2 x 8 grid, 5 iterations).
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
+import statistics
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "bf16x3": 2500.0}   # dense MFMA TFLOP/s
-DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "bf16x3": "bf16x3"}
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "bf16x3": 2500.0, "bf16r": 2500.0}
+HBM_PEAK_GBS = 8000.0
+DTYPE = {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "bf16x3": "bf16x3", "bf16r": "bf16"}
 # MFMA products issued per algorithmic phase product (BF16X3: head*head,
 # head*residual, residual*head)
-MFMA_PASSES = {"fp32": 1, "fp64": 1, "bf16": 1, "bf16x3": 3}
-
+MFMA_PASSES = {"fp32": 1, "fp64": 1, "bf16": 1, "bf16x3": 3, "bf16r": 1}
+REGEN_KERNEL = {"fp32": "regen_kernel<FP32>", "fp64": "regen_kernel<FP64>",
+                "bf16": "regen_bf16_wide_kernel", "bf16x3": "regen_kernel<BF16X3>",
+                "bf16r": "regen_bf16_wide_kernel"}
+Z_BYTES = {"fp32": 4, "fp64": 8, "bf16": 2, "bf16x3": 4, "bf16r": 2}
 
 TRAFFIC_PROFILE = {("digits_n200000_d784_s10240_m10", "fp32"):
                    "profiles/regen_fp32_digits_n200000_s10240_traffic.md"}
 KERNEL_SOURCES = ["paper_1409_0940_amd/csrc/feature.hip", "paper_1409_0940_amd/csrc/common.h"]
+
+# residual balancing of the serving solves: check every 10 iterations, mu = 5, tau = 2
+SERVING_ADAPT = (10, 5.0, 2.0)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def recorded_traffic(workload, precision):
@@ -60,201 +89,439 @@ def recorded_traffic(workload, precision):
     return float(vals["traffic_bytes_per_launch"])
 
 
-# residual balancing of the serving solves: check every 10 iterations, mu = 5, tau = 2
-SERVING_ADAPT = (10, 5.0, 2.0)
+def load_golden(name):
+    """Oracle golden of a workload (see tests/golden/make_oracle_goldens.py)."""
+    import glob
+    paths = sorted(glob.glob(os.path.join(ROOT, "tests", "golden", f"oracle_{name}_it*.npz")))
+    if not paths:
+        return None
+    z = np.load(paths[0], allow_pickle=False)
+    g = {k: z[k] for k in z.files}
+    g["meta"] = json.loads(str(g["meta"]))
+    return g
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+# ---------------------------------------------------------------------------
+# GPU runs
+# ---------------------------------------------------------------------------
+
+def solver(w, dev_inputs, prec, R=None, **kw):
+    from paper_1409_0940_amd import Solver
+    Xd, Yd, Wd, bd = dev_inputs
+    return Solver(Xd, Yd, Wd, bd, R or w.R, w.C, w.lam, w.rho, w.sigma, w.loss, prec, **kw)
 
 
-def gpu_run(w, precision, steps, warmup, dev_inputs, z_mode="auto"):
+def run_precision(w, dev_inputs, prec, steps, warmup, graph=False, **kw):
     """Setup, warm-up, timed iterations; returns (solver, record)."""
     import torch
-    from paper_1409_0940_amd import Solver
-
-    Xd, Yd, Wd, bd = dev_inputs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    S = Solver(Xd, Yd, Wd, bd, w.R, w.C, w.lam, w.rho, w.sigma, w.loss, precision,
-               z_mode=z_mode)
+    S = solver(w, dev_inputs, prec, graph=graph, **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     if warmup:
         S.iterate(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = S.iterate(steps, timed=True)
+    if graph:          # replayed graphs: no per-phase events
+        S.iterate_async(steps)
+        st = None
+    else:
+        st = S.iterate(steps, timed=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # algorithmic flops of the regeneration launches (2 n d s per step, spread
-    # over one launch per feature block and row-block group) over their time
-    launches = st["launches"]
-    flops = 2.0 * w.n * w.d * w.s * steps / launches if launches else 0.0
-    launch_ms = st["phase_ms"]["regen"] / launches if launches else 0.0
-    achieved = flops / (launch_ms * 1e-3) / 1e12 if launch_ms else 0.0
-    rec = {"value": steps / wall, "ms_per_step": 1e3 * wall / steps, "setup_s": setup_s,
-           "launch_ms": launch_ms, "achieved": achieved, "launches": launches,
-           "flops_per_launch": flops,
-           "phase_ms_per_step": {k: v / steps for k, v in st["phase_ms"].items()},
-           "coef": S.coef()}
-    log(f"{precision}/{z_mode}: setup {setup_s:.2f} s, {steps} steps {wall:.3f} s "
-        f"({rec['value']:.2f} it/s), regen {launch_ms:.3f} ms/launch")
+    rec = {"value": steps / wall, "unit": "iters/s", "ms_per_step": 1e3 * wall / steps,
+           "setup_s": setup_s, "iters_done": warmup + steps}
+    if st is not None:
+        launches = st["launches"]
+        rec["phase_ms_per_step"] = {k: v / steps for k, v in st["phase_ms"].items()}
+        if launches:
+            # algorithmic flops of the regeneration launches: 2 n d s per step,
+            # over one launch per feature block and row-block group
+            flops = 2.0 * w.n * w.d * w.s * steps / launches
+            launch_ms = st["phase_ms"]["regen"] / launches
+            achieved = flops / (launch_ms * 1e-3) / 1e12
+            rec["roofline"] = {"bound": "mfma", "kernel": REGEN_KERNEL[prec],
+                               "achieved": round(achieved, 2), "peak": PEAK[prec],
+                               "unit": "TFLOP/s", "frac": round(achieved / PEAK[prec], 4),
+                               "traffic": recorded_traffic(w.name, prec),
+                               "flops_per_launch": flops, "avg_launch_ms": round(launch_ms, 4),
+                               "launches": launches, "mfma_passes": MFMA_PASSES[prec]}
+        # the two Z products stream Z once each: algorithmic bytes n * s * p
+        zbytes = w.n * w.s * Z_BYTES[prec]
+        prod = {}
+        for ph in ("ztr", "zw"):
+            ms = st["phase_ms"][ph] / steps
+            if ms > 0:
+                gbs = zbytes / (ms * 1e-3) / 1e9
+                prod[ph] = {"ms": round(ms, 4), "GB_per_s": round(gbs, 1),
+                            "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        rec["products_hbm"] = prod
+    log(f"{w.name} {prec}{'/graph' if graph else ''}{kw or ''}: setup {setup_s:.2f} s, "
+        f"{steps} steps {wall:.3f} s ({rec['value']:.2f} it/s)")
     return S, rec
 
 
-def cpu_baseline(w, X, Y, Wr, b):
-    """Oracle iteration on one row block (R = 1, same C, s, d), scaled by R."""
-    from oracle import bsadmm_oracle as o
+def add_errors(rec, S, golden, F_eval, Wbar=None):
+    """Objective and coefficient error of a run at the golden's iteration count."""
+    if golden is None:
+        return
+    Wg = S.coef().cpu().numpy() if Wbar is None else Wbar
+    F = F_eval(Wg)
+    rows = golden["rows"]
+    ref = golden["wbar_rows"]
+    rec["iters_compared"] = int(golden["iters"])
+    rec["obj_rel_err_vs_oracle"] = abs(F - float(golden["F"])) / abs(float(golden["F"]))
+    rec["coef_err_vs_oracle"] = float(np.linalg.norm(Wg[rows] - ref) / np.linalg.norm(ref))
+    rec["objective"] = F
+
+
+def errors_at_golden(w, dev_inputs, prec, golden, F_eval, timed_solver, timed_iters, **kw):
+    """Error of `prec` against the golden; reuses the timed solver when it ran
+    exactly the golden's iteration count, else runs a fresh solve."""
+    if golden is None:
+        return {}
+    rec = {}
+    gi = int(golden["iters"])
+    if timed_solver is not None and timed_iters == gi:
+        add_errors(rec, timed_solver, golden, F_eval)
+        return rec
+    S = solver(w, dev_inputs, prec, **kw)
+    S.iterate(gi)
+    add_errors(rec, S, golden, F_eval)
+    S.close()
+    return rec
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample of the workload
+# ---------------------------------------------------------------------------
+
+def _blas_info():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        info = threadpool_info()
+        blas = [i for i in info if i.get("user_api") == "blas"]
+        if blas:
+            return {"blas": f"{blas[0].get('internal_api')} {blas[0].get('version')}",
+                    "blas_threads": int(blas[0].get("num_threads", 1))}
     except Exception:
-        threads = os.cpu_count() or 1
+        pass
+    return {"blas": "unknown", "blas_threads": os.cpu_count() or 1}
+
+
+def _time_oracle_iteration(w, X, Y, Wr, b, rows, thread_counts, repeats=3):
+    """Median wall time of one oracle iteration on the sub-problem: the first
+    `rows` rows, feature block 0 (s_j features), one block (R = C = 1), the
+    workload's d, m, loss and lambda, Z regenerated each iteration as the
+    method prescribes.  The first iteration (which builds the factor) is not
+    timed; then `repeats` iterations are timed at each thread count."""
+    from oracle import bsadmm_oracle as o
+    from threadpoolctl import threadpool_limits
+    sj = w.s // w.C
+    p = o.Problem(X[:rows], Y[:rows], Wr[:, :sj], b[:sj], 1, 1, w.lam, w.rho, w.loss)
+    out = {}
+    with threadpool_limits(limits=max(thread_counts)):
+        st, cache = o.admm(p, 1, regenerate=True)
+    for thr in thread_counts:
+        times = []
+        with threadpool_limits(limits=thr):
+            for _ in range(repeats):
+                t0 = time.perf_counter()
+                st, cache = o.admm(p, 1, state=st, cache=cache)
+                times.append(time.perf_counter() - t0)
+        out[thr] = statistics.median(times)
+    return out
+
+
+def cpu_baseline(w, X, Y, Wr, b, max_rows=8192):
+    """Oracle time per full iteration, extrapolated from block visits.
+
+    The oracle's iteration visits the R x C blocks in turn; a visit costs an
+    affine function of the block's rows (feature map and products linear in
+    the rows; the solve with the cached factor and the column-side steps
+    independent of them).  Both coefficients come from the median time of an
+    iteration of the one-block sub-problem at two row counts, n1 and
+    n2 = 2 n1 <= max_rows; the full iteration is R C (a + b n_i).  Timed with
+    all BLAS threads and with one."""
     ni = w.n // w.R
-    p = o.Problem(X[:ni], Y[:ni], Wr, b, 1, w.C, w.lam, w.rho, w.loss)
-    cache = o._BlockCache(p, regenerate=True)
-    t0 = time.perf_counter()
-    for j in range(w.C):                       # setup: factors, not timed
-        cache.chol(0, j, cache.Zblock(0, j))
-    log(f"oracle setup on {ni} rows: {time.perf_counter() - t0:.1f} s")
-    t0 = time.perf_counter()
-    o.admm(p, 1, cache=cache)
-    it = time.perf_counter() - t0
-    log(f"oracle iteration on {ni} rows: {it:.1f} s")
-    per_iter = it * w.R
-    return {"value": round(1.0 / per_iter, 6), "unit": "iters/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"1 iteration on row block 0 of {w.R} ({ni} x {w.d}, s={w.s}, C={w.C}), "
-                      f"Z regenerated, factors built beforehand; time x {w.R} (extrapolated)",
-            "s_per_iter": round(per_iter, 3)}
+    n2 = min(ni, max_rows)
+    n1 = max(1, n2 // 2)
+    info = _blas_info()
+    allt = info["blas_threads"]
+    out = {"unit": "iters/s", "kind": "oracle", "cores": allt,
+           "cpu_count": os.cpu_count(), "blas": info["blas"]}
+    t2 = _time_oracle_iteration(w, X, Y, Wr, b, n2, (allt, 1))
+    t1 = _time_oracle_iteration(w, X, Y, Wr, b, n1, (allt, 1)) if n1 < n2 else t2
+    for label, thr in (("all", allt), ("1thread", 1)):
+        slope = (t2[thr] - t1[thr]) / (n2 - n1) if n2 > n1 else t2[thr] / n2
+        icpt = max(0.0, t2[thr] - slope * n2)
+        out[f"s_per_iter_{label}"] = round(w.R * w.C * (icpt + slope * ni), 3)
+        out[f"sample_s_{label}"] = [round(t1[thr], 4), round(t2[thr], 4)]
+    out["value"] = round(1.0 / out["s_per_iter_all"], 6)
+    out["value_1thread"] = round(1.0 / out["s_per_iter_1thread"], 6)
+    out["sample"] = (f"median of 3 oracle iterations (after 1 untimed) of the one-block "
+                     f"sub-problem rows [0, n) x features [0, {w.s // w.C}) at n = {n1} and "
+                     f"{n2}, Z regenerated each iteration; extrapolated (affine in rows) to "
+                     f"R x C = {w.R * w.C} visits of {ni}-row blocks")
+    log(f"{w.name} oracle: {out['s_per_iter_all']:.2f} s/iter on {allt} threads, "
+        f"{out['s_per_iter_1thread']:.2f} s/iter on 1 (extrapolated)")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Workloads
+# ---------------------------------------------------------------------------
+
+def resident(arrays):
+    import torch
+    dev = torch.device("cuda:0")
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in arrays)
+
+
+def fp64_evaluator(w, dev_inputs, R=None):
+    """(handle, F(W) on the device with FP64 features)."""
+    import torch
+    E = solver(w, dev_inputs, "fp64", R=R)
+    return E, lambda Wm: E.objective(torch.from_numpy(Wm).to(dev_inputs[0].device))
+
+
+def bench_digits(args, out_cpu):
+    """The headline workload and its variants."""
+    import workloads as wl
+    w = wl.digits_200k()
+    log(f"workload {w.name}: generating inputs")
+    X, Y, Wr, b = wl.make_inputs(w)
+    dev = resident((X, Y, Wr, b))
+    golden = load_golden("digits")
+    S, head = run_precision(w, dev, args.precision, args.steps, args.warmup)
+    E, F_eval = fp64_evaluator(w, dev)
+    head.update(errors_at_golden(w, dev, args.precision, golden, F_eval, S,
+                                 args.warmup + args.steps))
+    S.close()
+    variants = {}
+    for v in [x for x in args.variants.split(",") if x and x != args.precision]:
+        prec, _, opt = v.partition(":")
+        kw = {}
+        if opt == "keep":
+            kw["z_mode"] = "keep"
+        elif opt.startswith("r"):
+            kw["refine_every"] = int(opt[1:])
+        Sv, rv = run_precision(w, dev, prec, args.steps, args.warmup, **kw)
+        rv.update(errors_at_golden(w, dev, prec, golden, F_eval, Sv,
+                                   args.warmup + args.steps, **kw))
+        Sv.close()
+        variants[v] = rv
+    E.close()
+    rec = {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "s": w.s,
+           "grid": f"{w.R}x{w.C}", "loss": w.loss, "lambda": w.lam, "rho": w.rho,
+           "sigma": w.sigma}
+    if not args.no_cpu_baseline:
+        out_cpu["digits"] = cpu_baseline(w, X, Y, Wr, b)
+    return rec, head, variants
+
+
+def bench_ridge(args):
+    """FP64 ridge, 100 iterations: launch-bound; eager launches against HIP-graph replay."""
+    import torch
+    import workloads as wl
+    w = wl.ridge_sine_4096()
+    X, Y, Wr, b = wl.make_inputs(w)
+    dev = resident((X, Y, Wr, b))
+    golden = load_golden("ridge")
+    E, F_eval = fp64_evaluator(w, dev)
+    recs = {}
+    for graph in (False, True):
+        S, r = run_precision(w, dev, "fp64", w.iters, args.warmup, graph=graph)
+        r.update(errors_at_golden(w, dev, "fp64", golden, F_eval, S, args.warmup + w.iters,
+                                  graph=graph))
+        if golden is not None and "wbar" in golden:
+            Ws = solver(w, dev, "fp64", graph=graph)
+            Ws.iterate(int(golden["iters"]))
+            Wg = Ws.coef().cpu().numpy()
+            r["coef_max_err_vs_oracle"] = float(np.abs(Wg - golden["wbar"]).max()
+                                                / np.abs(golden["wbar"]).max())
+            Ws.close()
+        S.close()
+        recs["fp64:graph" if graph else "fp64"] = r
+    E.close()
+    # the closed-form ridge solution the iteration converges to is checked in the tests
+    torch.cuda.synchronize()
+    return {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "s": w.s, "grid": f"{w.R}x{w.C}",
+            "loss": w.loss, "iters_timed": w.iters, "precisions": recs}
+
+
+def bench_speech(args, out_cpu):
+    import workloads as wl
+    w = wl.speech_100k()
+    log(f"workload {w.name}: generating inputs")
+    X, Y, Wr, b = wl.make_inputs(w)
+    dev = resident((X, Y, Wr, b))
+    golden = load_golden("speech")
+    E, F_eval = fp64_evaluator(w, dev)
+    recs = {}
+    for v in args.speech_variants.split(","):
+        prec, _, opt = v.partition(":")
+        kw = {"refine_every": int(opt[1:])} if opt.startswith("r") else {}
+        S, r = run_precision(w, dev, prec, args.steps, args.warmup, **kw)
+        r.update(errors_at_golden(w, dev, prec, golden, F_eval, S, args.warmup + args.steps,
+                                  **kw))
+        S.close()
+        recs[v] = r
+    E.close()
+    if not args.no_cpu_baseline:
+        out_cpu["speech"] = cpu_baseline(w, X, Y, Wr, b)
+    return {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "s": w.s, "grid": f"{w.R}x{w.C}",
+            "loss": w.loss, "lambda": w.lam, "rho": w.rho, "sigma": w.sigma, "precisions": recs}
+
+
+def bench_digits2m(args, out_cpu):
+    import gc
+    import torch
+    import workloads as wl
+    w = wl.digits_2m()
+    log(f"workload {w.name}: generating inputs")
+    X, Y, Wr, b = wl.make_inputs(w)
+    dev = resident((X, Y, Wr, b))
+    recs = {}
+    for v in args.big_variants.split(","):
+        prec, _, opt = v.partition(":")
+        kw = {"refine_every": int(opt[1:])} if opt.startswith("r") else {}
+        S, r = run_precision(w, dev, prec, args.big_steps, args.warmup, **kw)
+        S.close()
+        recs[v] = r
+    del dev
+    gc.collect()
+    torch.cuda.empty_cache()
+    # errors on the golden's problem: the first two row blocks (n = 250000,
+    # 2 x 8 grid, the same d, s, s_j, m), F evaluated with BF16X3 features
+    golden = load_golden("digits2m_r2")
+    if golden is not None:
+        n2 = int(golden["meta"]["n"])
+        dev2 = resident((X[:n2], Y[:n2], Wr, b))
+        w2 = wl.Workload(w.name + "_r2", n2, w.d, w.m, w.s, int(golden["meta"]["R"]), w.C,
+                         w.sigma, w.lam, w.rho, w.loss, int(golden["iters"]), w.seed, "bf16")
+        Ev = solver(w2, dev2, "bf16x3")
+        F_eval = lambda Wm: Ev.objective(torch.from_numpy(Wm).to(dev2[0].device))
+        for v in recs:
+            prec, _, opt = v.partition(":")
+            kw = {"refine_every": int(opt[1:])} if opt.startswith("r") else {}
+            S2 = solver(w2, dev2, prec, **kw)
+            S2.iterate(int(golden["iters"]))
+            e = {}
+            add_errors(e, S2, golden, F_eval)
+            S2.close()
+            recs[v].update({f"{k}": val for k, val in e.items()})
+            recs[v]["errors_on"] = f"first {n2} rows, grid {w2.R}x{w2.C}"
+        Ev.close()
+        del dev2
+    if not args.no_cpu_baseline:
+        out_cpu["digits2m"] = cpu_baseline(w, X, Y, Wr, b)
+    return {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "s": w.s, "grid": f"{w.R}x{w.C}",
+            "loss": w.loss, "lambda": w.lam, "rho": w.rho, "sigma": w.sigma,
+            "steps_timed": args.big_steps, "precisions": recs}
+
+
+def rounded(x, nd=6):
+    if isinstance(x, float):
+        return float(f"{x:.{nd}g}") if math.isfinite(x) else x
+    if isinstance(x, dict):
+        return {k: rounded(v, nd) for k, v in x.items()}
+    if isinstance(x, list):
+        return [rounded(v, nd) for v in x]
+    return x
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=list(PEAK))
-    ap.add_argument("--workload", default="digits_200k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp64,bf16,bf16x3,fp32:keep,bf16:keep",
-                    help="other precision[:z_mode] runs at the same iteration count ('' = none);"
-                         " z_mode keep = Z generated once and kept in HBM")
+    ap.add_argument("--variants", default="fp64,bf16,bf16x3,bf16r:r5,bf16r:r2,bf16r:r10,"
+                                          "fp32:keep,bf16:keep",
+                    help="other precision[:keep | :rK] runs of the headline workload at the same "
+                         "iteration count ('' = none); keep = Z generated once and kept in HBM, "
+                         "rK = BF16R refined every K-th iteration")
+    ap.add_argument("--workloads", default="ridge,speech,digits2m",
+                    help="further workloads with records of their own ('' = none)")
+    ap.add_argument("--speech-variants", default="fp32,fp64,bf16,bf16x3,bf16r:r5,bf16r:r2")
+    ap.add_argument("--big-variants", default="bf16,bf16r:r5,bf16x3")
+    ap.add_argument("--big-steps", type=int, default=10,
+                    help="timed iterations of the 2M-row workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 4 device copies of 1 GiB (HBM counter calibration) and exit")
     ap.add_argument("--serving", type=int, default=256,
                     help="requests of the serving stream to run after the step timing (0 = skip)")
-    ap.add_argument("--no-serving-compare", action="store_true",
-                    help="skip the second pass of the serving stream at a fixed penalty")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "runs on a single GPU: --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on a single GPU: --gpus must be 1"}))
         sys.exit(2)
 
     import torch
-    import workloads as wl
 
     if args.calibrate_copy:
         # known traffic: each copy reads 1 GiB and writes 1 GiB
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
+        bcopy = torch.empty_like(a)
         for _ in range(4):
-            b.copy_(a)
+            bcopy.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
                           "copies": 4}))
         return
 
-    w = getattr(wl, args.workload)()
-    log(f"workload {w.name}: generating inputs")
-    X, Y, Wr, b = wl.make_inputs(w)
-    dev = torch.device("cuda:0")
-    dev_inputs = tuple(torch.from_numpy(a).to(dev) for a in (X, Y, Wr, b))
-    log("inputs resident on the device")
+    t_start = time.perf_counter()
+    cpu = {}
+    config, head, variants = bench_digits(args, cpu)
+    others = {}
+    for name in [x for x in args.workloads.split(",") if x]:
+        fn = {"ridge": lambda: bench_ridge(args), "speech": lambda: bench_speech(args, cpu),
+              "digits2m": lambda: bench_digits2m(args, cpu)}[name]
+        others[name] = fn()
+        if name in cpu:
+            others[name]["cpu_baseline"] = cpu[name]
 
-    S, main_rec = gpu_run(w, args.precision, args.steps, args.warmup, dev_inputs)
-    S.close()
-    variants = [v for v in args.variants.split(",") if v and v != args.precision]
-    recs = {}
-    ref = None
-    for v in variants:
-        prec, _, zm = v.partition(":")
-        Sv, rv = gpu_run(w, prec, args.steps, args.warmup, dev_inputs, zm or "auto")
-        rv["prec"] = prec
-        if v == "fp64":
-            ref = Sv
-        else:
-            Sv.close()
-        recs[v] = rv
-    obj = {}
-    if ref is not None:
-        f64 = ref.objective()
-        obj["fp64"] = f64
-        for name, r in [(args.precision, main_rec)] + [(k, v) for k, v in recs.items() if k != "fp64"]:
-            obj[name] = ref.objective(r["coef"])
-        ref.close()
-    rel = lambda k: (abs(obj[k] - obj["fp64"]) / abs(obj["fp64"])) if k in obj and "fp64" in obj else None
-
-    peak = PEAK[args.precision]
     out = {
         "metric": "ADMM iters/s",
-        "value": round(main_rec["value"], 4),
+        "value": round(head["value"], 4),
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(main_rec["ms_per_step"], 3),
+        "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "s": w.s,
-                   "grid": f"{w.R}x{w.C}", "loss": w.loss, "lambda": w.lam, "rho": w.rho,
-                   "sigma": w.sigma, "precision": args.precision},
-        "roofline": {"bound": "mfma", "kernel": "regen_kernel",
-                     "achieved": round(main_rec["achieved"], 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(main_rec["achieved"] / peak, 4),
-                     "traffic": recorded_traffic(w.name, args.precision),
-                     "flops_per_launch": main_rec["flops_per_launch"],
-                     "avg_launch_ms": round(main_rec["launch_ms"], 4),
-                     "launches": main_rec["launches"],
-                     "mfma_passes": MFMA_PASSES[args.precision]},
-        "setup_s": round(main_rec["setup_s"], 3),
-        "phase_ms_per_step": {k: round(v, 4) for k, v in main_rec["phase_ms_per_step"].items()},
-        # feature-GEMM flops of a whole step over the step time, against the peak
-        "mfma_frac_of_step": round(2.0 * w.n * w.d * w.s / (main_rec["ms_per_step"] * 1e-3)
-                                   / 1e12 / peak, 4),
-        "obj_rel_err_vs_fp64": rel(args.precision),
-        "objective": obj.get(args.precision),
-        "variants": {k: {"value": round(r["value"], 4), "unit": "iters/s",
-                         "ms_per_step": round(r["ms_per_step"], 3),
-                         "setup_s": round(r["setup_s"], 3),
-                         "regen_frac": round(r["achieved"] / PEAK[r["prec"]], 4),
-                         "regen_tflops": round(r["achieved"], 2),
-                         "mfma_passes": MFMA_PASSES[r["prec"]],
-                         "phase_ms_per_step": {p: round(t, 4)
-                                               for p, t in r["phase_ms_per_step"].items()},
-                         "obj_rel_err_vs_fp64": rel(k)} for k, r in recs.items()},
+        "config": dict(config, precision=args.precision),
+        "roofline": head.get("roofline"),
+        "setup_s": round(head["setup_s"], 3),
+        "phase_ms_per_step": head.get("phase_ms_per_step"),
+        "products_hbm": head.get("products_hbm"),
+        "mfma_frac_of_step": round(2.0 * config["n"] * config["d"] * config["s"]
+                                   / (head["ms_per_step"] * 1e-3) / 1e12
+                                   / PEAK[args.precision], 4),
+        "obj_rel_err_vs_oracle": head.get("obj_rel_err_vs_oracle"),
+        "coef_err_vs_oracle": head.get("coef_err_vs_oracle"),
+        "iters_compared": head.get("iters_compared"),
+        "objective": head.get("objective"),
+        "variants": variants,
+        "workloads": others,
     }
     if args.serving:
         from paper_1409_0940_amd.serving import serve_stream
-
-        def fmt(summ):
-            return {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in summ.items()}
         log(f"serving stream: {args.serving} requests at 20/s, penalty adaptation {SERVING_ADAPT}")
-        summ, _, jobs = serve_stream(args.serving, rho_adapt=SERVING_ADAPT)
-        out["serving"] = fmt(summ)
-        log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms")
-        if not args.no_serving_compare:
-            # the same requests at the fixed penalty rho = 1
-            summ0, _, _ = serve_stream(args.serving, jobs=jobs)
-            out["serving_fixed_rho"] = fmt(summ0)
-            log(f"serving, fixed rho: p50 {summ0['p50_ms']:.1f} ms, p99 {summ0['p99_ms']:.1f} ms")
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, X, Y, Wr, b)
-    print(json.dumps(out), flush=True)
+        summ, _, _ = serve_stream(args.serving, rho_adapt=SERVING_ADAPT)
+        out["serving"] = summ
+        log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, "
+            f"{summ['solves_per_s']:.2f} solves/s")
+    if "digits" in cpu:
+        out["cpu_baseline"] = cpu["digits"]
+    out["bench_wall_s"] = time.perf_counter() - t_start
+    print(json.dumps(rounded(out)), flush=True)
 
 
 if __name__ == "__main__":

@@ -8,7 +8,9 @@ else, and stores what the GPU tests and the benchmark compare against:
                     ``iters`` iterations, evaluated with the oracle's own FP64 Z;
 * ``wbar_norm``  -- ||W-bar||_F;
 * ``rows``, ``wbar_rows`` -- W-bar at a seeded sample of feature rows (all m
-                    columns), the elements a coefficient check compares one by one;
+                    columns; 2048 rows for m <= 32, about 2^16 values for
+                    larger m), the elements a coefficient check compares one
+                    by one;
 * ``wbar``       -- the whole W-bar where it is small (s * m <= 2^16).
 
 Usage: python tests/golden/make_oracle_goldens.py [name ...]
@@ -35,7 +37,7 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 from oracle import bsadmm_oracle as o  # noqa: E402
 
-SAMPLE_ROWS = 2048
+SAMPLE_VALUES = 1 << 16     # feature rows sampled: about this many values, 256 to 2048 rows
 SAMPLE_SEED = 20140903
 
 
@@ -76,7 +78,7 @@ def make(name):
         loss += o.loss_sum(p.loss, Y[r0:r1], Oi)
     F = loss / p.n + p.lam * float((Wbar * Wbar).sum())
     g = np.random.Generator(np.random.PCG64(SAMPLE_SEED))
-    k = min(SAMPLE_ROWS, p.s)
+    k = min(p.s, max(256, min(2048, SAMPLE_VALUES // p.m // 128 * 128)))
     sample = np.sort(g.choice(p.s, size=k, replace=False)).astype(np.int64)
     meta = {"workload": w.name, "n": p.n, "d": w.d, "m": p.m, "s": p.s, "R": p.R, "C": p.C,
             "loss": p.loss, "lambda": p.lam, "rho": p.rho, "sigma": w.sigma, "iters": iters,
