@@ -89,13 +89,16 @@ def recorded_traffic(workload, precision):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def load_golden(name):
-    """Oracle golden of a workload (see tests/golden/make_oracle_goldens.py)."""
+def load_golden(name, iters=None):
+    """Oracle golden of a workload (see tests/golden/make_oracle_goldens.py):
+    the one at `iters` iterations, or the one with the fewest."""
     import glob
-    paths = sorted(glob.glob(os.path.join(ROOT, "tests", "golden", f"oracle_{name}_it*.npz")))
-    if not paths:
+    import re
+    paths = glob.glob(os.path.join(ROOT, "tests", "golden", f"oracle_{name}_it*.npz"))
+    found = {int(re.search(r"_it(\d+)\.npz$", q).group(1)): q for q in paths}
+    if not found or (iters is not None and iters not in found):
         return None
-    z = np.load(paths[0], allow_pickle=False)
+    z = np.load(found[iters if iters is not None else min(found)], allow_pickle=False)
     g = {k: z[k] for k in z.files}
     g["meta"] = json.loads(str(g["meta"]))
     return g
@@ -312,6 +315,15 @@ def bench_digits(args, out_cpu):
                                    args.warmup + args.steps, **kw))
         Sv.close()
         variants[v] = rv
+    # errors near convergence: the same runs at the 100-iteration golden
+    g100 = load_golden("digits", 100)
+    if g100 is not None:
+        for v, rv in [(args.precision, head)] + list(variants.items()):
+            prec, _, opt = v.partition(":")
+            if opt == "keep":
+                continue
+            kw = {"refine_every": int(opt[1:])} if opt.startswith("r") else {}
+            rv["at_100_iterations"] = errors_at_golden(w, dev, prec, g100, F_eval, None, 0, **kw)
     E.close()
     rec = {"workload": w.name, "n": w.n, "d": w.d, "m": w.m, "s": w.s,
            "grid": f"{w.R}x{w.C}", "loss": w.loss, "lambda": w.lam, "rho": w.rho,
@@ -508,6 +520,7 @@ def main():
         "coef_err_vs_oracle": head.get("coef_err_vs_oracle"),
         "iters_compared": head.get("iters_compared"),
         "objective": head.get("objective"),
+        "at_100_iterations": head.get("at_100_iterations"),
         "variants": variants,
         "workloads": others,
     }

@@ -83,8 +83,8 @@ typedef enum {
  *           residual-by-residual term dropped, below 2^-16 of the product).
  *           rff_map returns float for BF16X3.
  *   BF16R : BF16 iterations with iterative refinement of the products of the
- *           graph projection (eq. gpWij).  The factor of eq. cache is built
- *           once from FP32-faithful (BF16X3) features.  Every iteration
+ *           graph projection (eq. gpWij) through the same FP64 factor: the
+ *           cache of eq. cache is that of BF16.  Every iteration
  *           regenerates BF16 features Zt and runs the BF16 products; on the
  *           first iteration and every refine_every-th after it (a refinement
  *           iteration) it also regenerates BF16X3 features Zf, forms the
@@ -92,9 +92,13 @@ typedef enum {
  *           dZ_ij^T R_i and sum_j dZ_ij W'_ij, which every iteration until
  *           the next refinement adds to its BF16 products.  The added defect
  *           is that of the last refinement's operands, so at a fixed point
- *           the corrected products equal the FP32-faithful ones and the
- *           iteration converges to the FP32-faithful problem's fixed point.
- *           Objective and predictions use Zt + dZ.  rff_map rejects BF16R. */
+ *           the corrected products equal the FP32-faithful ones; the
+ *           remaining difference to the FP32-faithful fixed point is that of
+ *           the factor (BF16 against FP32-faithful Gram).  The first
+ *           iteration starts from R = W' = 0 and leaves the defects at 0, so
+ *           the first refinement that corrects anything is iteration
+ *           1 + refine_every.  The objective uses Zt + dZ and predictions the
+ *           BF16X3 features.  rff_map rejects BF16R.                        */
 enum { BSADMM_FP64 = 0, BSADMM_FP32 = 1, BSADMM_BF16 = 2, BSADMM_BF16X3 = 3, BSADMM_BF16R = 4 };
 
 /* ------------------------------------------------------------------ loss */

@@ -176,7 +176,15 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   }
   int64_t nmax = 0;
   for (int r = 0; r < L.R; ++r) nmax = std::max(nmax, L.rstart[r + 1] - L.rstart[r]);
-  L.split_rows = std::max<int64_t>(2048, rup((nmax + 63) / 64, 32));
+  // Rows per split of the transpose product: at most 2048 (the partial sums
+  // of a split, spad x mp, stay small against the Z rows it reads), and fewer
+  // for small problems, so that the (spad / 256) x splits workgroups of a
+  // launch reach about 1024; at least 256, a multiple of 32.
+  {
+    const int64_t colg = std::max<int64_t>(1, L.spad / 256);
+    const int64_t want = std::max<int64_t>(1, (1024 + colg - 1) / colg);
+    L.split_rows = std::min<int64_t>(2048, std::max<int64_t>(256, rup((nmax + want - 1) / want, 32)));
+  }
   L.nbpad = rup(nmax, 32) + 32;
   L.nsplit_max = (nmax + L.split_rows - 1) / L.split_rows;
   const size_t slot = (size_t)L.S * L.S * 8;
@@ -773,8 +781,10 @@ int do_setup(bsadmm_handle* h) {
   }
   // Gram blocks and the FP64 inverse cache (eq. cache)
   const size_t slot = (size_t)L.S * L.S;
-  // Refined BF16 builds the cache from FP32-faithful (BF16X3) features; a
-  // kept Z also keeps its defect, formed here with a temporary for them.
+  // Refined BF16 builds the cache from its BF16 features, as plain BF16 does
+  // (the refinement corrects the products through that same factor); a kept
+  // Z also keeps its defect, formed here with a temporary for the BF16X3
+  // features.
   void* zf = h->Zf;
   if (L.refine && L.keep) {
     hipError_t e = hipMallocAsync(&zf, (size_t)L.ws_rows * L.spad * 4, st);
@@ -789,21 +799,12 @@ int do_setup(bsadmm_handle* h) {
   for (const auto& g : L.groups) {
     const int i0 = g.first, i1 = g.second;
     const int64_t r0 = L.rstart[i0];
-    hipError_t e = hipSuccess;
-    if (L.refine) {
-      if (L.keep) e = regen_group(h, i0, i1, st);
-      if (e == hipSuccess) e = L.keep ? defect_group(h, i0, i1, st, zf)
-                                      : regen_group(h, i0, i1, st, BS_PREC_BF16X3, zf, 4);
-    } else {
-      e = regen_group(h, i0, i1, st);
-    }
-    const void* gz = L.refine ? zf : h->Z;
-    const size_t gzb = L.refine ? 4 : L.zb;
-    const int gprec = L.refine ? BS_PREC_BF16X3 : L.prec;
+    hipError_t e = regen_group(h, i0, i1, st);
+    if (e == hipSuccess && L.refine && L.keep) e = defect_group(h, i0, i1, st, zf);
     for (int i = i0; i < i1 && e == hipSuccess; ++i)
       for (int j = 0; j < L.C && e == hipSuccess; ++j)
-        e = bs::gram(gprec, (const char*)gz + (size_t)(L.rstart[i] - r0) * L.spad * gzb, L.spad,
-                     L.rstart[i + 1] - L.rstart[i], L.coff[j], L.sj[j],
+        e = bs::gram(L.prec, (const char*)h->Z + (size_t)(L.rstart[i] - r0) * L.spad * L.zb,
+                     L.spad, L.rstart[i + 1] - L.rstart[i], L.coff[j], L.sj[j],
                      h->Q + (size_t)(i * L.C + j) * slot, L.S, st);
     if (e != hipSuccess) {
       grc = hip_fail(e, "setup Gram");

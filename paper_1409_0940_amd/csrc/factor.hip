@@ -296,72 +296,105 @@ __global__ void identity_pad_kernel(double* __restrict__ slot, int64_t S, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Projection solve W'_b = Q_b rhs_b for block b = (i, j).  A wave owns 16
-// rows of W'_b and up to NTC column tiles; a lane loads 4 adjacent doubles of
-// a row of Q and the 4 matching rhs rows feed 4 MFMA instructions.
-// ---------------------------------------------------------------------------
+// Projection solve for one or two output tiles (mp <= 32), where the product
+// streams Q (s_j^2 doubles a block) for very little arithmetic: a workgroup
+// owns 16 rows of W'_b and its 4 waves split the k-steps (wave w takes steps
+// w, w + 4, ...), so a block of s_j rows has s_j / 16 workgroups in flight
+// instead of s_j / 64.  Each wave issues the Q and rhs loads of U steps before
+// their MFMAs, and the 4 partial sums are added in wave order through LDS.
+// Lane (fr, fg) loads 4 adjacent doubles of row row0 + fr of Q, and the 4
+// matching rhs rows make the B fragment: one FP64 MFMA per step and tile.
 // OUT is the type of the operand copy of W' for the forward products:
 // double or float in W''s own layout, or uint16_t for BF16 head and residual
 // planes stored transposed, [i][plane][mp][spad].
-template <typename OUT, int NTC>
+// ---------------------------------------------------------------------------
+template <typename OUT, int NT>
 __global__ void __launch_bounds__(256)
-solve_kernel(const double* __restrict__ Q, int64_t S, int C, int b0, const int64_t* __restrict__ coff,
-             const int64_t* __restrict__ sjs, int64_t spad, int64_t mp,
-             const double* __restrict__ rhs, double* __restrict__ Wp, double* __restrict__ U,
-             OUT* __restrict__ Wop) {
+solve_ks_kernel(const double* __restrict__ Q, int64_t S, int C, int b0,
+                const int64_t* __restrict__ coff, const int64_t* __restrict__ sjs, int64_t spad,
+                int64_t mp, const double* __restrict__ rhs, double* __restrict__ Wp,
+                double* __restrict__ U, OUT* __restrict__ Wop) {
+  constexpr int KS = 4, UN = 4;
+  __shared__ double red[KS - 1][NT][4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
   const int b = b0 + (int)blockIdx.y;
   const int i = b / C, j = b - i * C;
   const int64_t sj = sjs[j];
-  const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
-  if (row0 >= sj) return;
-  const int nc0 = blockIdx.z * NTC;
+  const int64_t row0 = (int64_t)blockIdx.x * 16;
+  if (row0 >= sj) return;  // whole workgroup: no barrier is skipped by part of it
   const int ntiles = (int)(mp / 16);
   const double* Qb = Q + (int64_t)b * S * S;
   const int64_t base = ((int64_t)i * spad + coff[j]) * mp;
   const double* rb = rhs + base;
-  const int64_t k16 = (sj + 15) / 16 * 16;  // Q pad columns are zero off the diagonal
+  const int64_t nk = (sj + 15) / 16;  // 16-value k-steps; Q pad columns are zero off the diagonal
   const double* qrow = Qb + (row0 + fr) * S + 4 * fg;
-  v4d acc[NTC];
+  v4d acc[NT];
 #pragma unroll
-  for (int t = 0; t < NTC; ++t)
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[t][r] = 0.0;
-  for (int64_t k0 = 0; k0 < k16; k0 += 16) {
-    Frag<BS_PREC_F64> a = load_frag<BS_PREC_F64>(qrow + k0);
-    const double* rk = rb + (k0 + 4 * fg) * mp + fr;
+  for (int64_t ks = wave; ks < nk; ks += KS * UN) {
+    Frag<BS_PREC_F64> a[UN];
+    Frag<BS_PREC_F64> bb[UN][NT];
 #pragma unroll
-    for (int t = 0; t < NTC; ++t) {
-      const int nt = nc0 + t;
-      if (nt < ntiles) {
-        Frag<BS_PREC_F64> bb;
+    for (int u = 0; u < UN; ++u) {
+      const int64_t k = ks + (int64_t)u * KS;
+      if (k < nk) {
+        const int64_t k0 = 16 * k;
+        a[u] = load_frag<BS_PREC_F64>(qrow + k0);
+        const double* rk = rb + (k0 + 4 * fg) * mp + fr;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) bb.v[q] = rk[q * mp + nt * 16];
-        mfma_step(acc[t], a, bb);
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bb[u][t].v[q] = t < ntiles ? rk[q * mp + t * 16] : 0.0;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[u].v[q] = 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bb[u][t].v[q] = 0.0;
       }
     }
-  }
 #pragma unroll
-  for (int t = 0; t < NTC; ++t) {
-    const int nt = nc0 + t;
-    if (nt >= ntiles) continue;
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) mfma_step(acc[t], a[u], bb[u][t]);
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave - 1][t][r][lane] = acc[t][r];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int w = 0; w < KS - 1; ++w)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[t][r] += red[w][t][r][lane];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t >= ntiles) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = row0 + acc_row<double>(fg, r);
       if (row < sj) {
-        const int64_t o = base + row * mp + nt * 16 + fr;
+        const int64_t o = base + row * mp + t * 16 + fr;
         const double w = acc[t][r];
         Wp[o] = w;
         U[o] = rhs[o] - w;
         if constexpr (sizeof(OUT) == 2) {
           uint16_t hi, lo;
           split_bf16(w, hi, lo);
-          const int64_t tcol = ((int64_t)i * 2 * mp + nt * 16 + fr) * spad + coff[j] + row;
+          const int64_t tcol = ((int64_t)i * 2 * mp + t * 16 + fr) * spad + coff[j] + row;
           Wop[tcol] = hi;
           Wop[tcol + mp * spad] = lo;
         } else {  // [i][mp][spad], like the BF16 planes
-          Wop[((int64_t)i * mp + nt * 16 + fr) * spad + coff[j] + row] = (OUT)w;
+          Wop[((int64_t)i * mp + t * 16 + fr) * spad + coff[j] + row] = (OUT)w;
         }
       }
     }
@@ -375,7 +408,7 @@ solve_kernel(const double* __restrict__ Q, int64_t S, int C, int b0, const int64
 // rhs_b (16 x mp doubles) are staged once in LDS, double-buffered, and read by
 // all 4 waves, so rhs moves from L2 once per 128 rows instead of once per 16.
 // A lane loads 4 adjacent doubles of a row of Q, which feed instructions
-// q = 0..3 with the matching rhs rows (the k-permutation of solve_kernel).
+// q = 0..3 with the matching rhs rows (the k-permutation of solve_ks_kernel).
 // ---------------------------------------------------------------------------
 template <typename OUT, int NTC>
 __global__ void __launch_bounds__(256, 2)
@@ -489,10 +522,14 @@ void launch_solve(const double* Q, int64_t S, int C, int b0, int nb, const int64
                   const int64_t* sjs, int64_t spad, int64_t mp, const double* rhs, double* Wp,
                   double* U, OUT* Wop, hipStream_t st) {
   const int ntiles = (int)(mp / 16);
-  if (ntiles <= 2) {  // few columns: Q is streamed once by 16-row waves
-    constexpr int NTC = 4;
-    dim3 g((unsigned)(S / 64), (unsigned)nb, (unsigned)((ntiles + NTC - 1) / NTC));
-    solve_kernel<OUT, NTC><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U, Wop);
+  if (ntiles <= 2) {  // few columns: Q streamed once, k split over the 4 waves
+    dim3 g((unsigned)(S / 16), (unsigned)nb);
+    if (ntiles == 1)
+      solve_ks_kernel<OUT, 1><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
+                                                 Wop);
+    else
+      solve_ks_kernel<OUT, 2><<<g, 256, 0, st>>>(Q, S, C, b0, coff, sjs, spad, mp, rhs, Wp, U,
+                                                 Wop);
     return;
   }
 #define BS_SOLVE_WIDE(NTC)                                                                 \

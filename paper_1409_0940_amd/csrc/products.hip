@@ -1312,6 +1312,119 @@ static void ztr_bf16_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t 
   else launch_ztr_bf16_dma<8>(Z, ldz, rows, s, Rt, ldr, mp, split_rows, part, st);
 }
 
+
+// ---------------------------------------------------------------------------
+// Gram tile of one block of a BF16 Z on BF16 MFMA: the lower 64 x 64 tile
+// (ta, tb) of I + Z_b^T Z_b.  Products of BF16 values are exact in FP32, so
+// this is the same arithmetic as widening Z to FP32 (FP32 accumulation), at
+// the rate of the 16x16x32 BF16 instruction.  A step is 32 rows: lane
+// (f = lane % 16, g = lane / 16) loads rows 8 g .. 8 g + 7 of features
+// 4 f .. 4 f + 3 of both feature tiles (8-byte loads, 128 contiguous bytes of
+// a row per 16 lanes) and transposes them in registers with byte permutes
+// into four 8-row fragments per tile, one for each feature 4 f + q.  The k of
+// an instruction is then the 32 rows of the step and instruction (qa, qb)
+// accumulates G[4 m + qa][4 n + qb], m, n < 16.  The 4 waves take interleaved
+// steps; their partial sums are added in wave order through LDS.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+gram_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
+                 int64_t sj, double* __restrict__ slot, int64_t S) {
+  __shared__ float red[64 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int64_t t = blockIdx.x;
+  int64_t ta = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
+  while (ta * (ta + 1) / 2 > t) --ta;
+  const int64_t tb = t - ta * (ta + 1) / 2;
+  const int64_t fa = 64 * ta + 4 * fr, fb = 64 * tb + 4 * fr;  // block-local features
+  // features at or past s_j read as zero: mask of the 4 packed halves
+  auto keep = [&](int64_t f0) -> uint2 {
+    uint2 k;
+    k.x = (f0 < sj ? 0x0000ffffu : 0u) | (f0 + 1 < sj ? 0xffff0000u : 0u);
+    k.y = (f0 + 2 < sj ? 0x0000ffffu : 0u) | (f0 + 3 < sj ? 0xffff0000u : 0u);
+    return k;
+  };
+  const uint2 ka = keep(fa), kb = keep(fb);
+  const bool la = fa < sj, lb = fb < sj;
+  const uint16_t* za_base = Z + coff + fa;
+  const uint16_t* zb_base = Z + coff + fb;
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t r0 = 32 * wave; r0 < rows; r0 += 128) {
+    uint2 za[8], zb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t r = r0 + 8 * fg + i;
+      uint2 a = {0u, 0u}, b = {0u, 0u};
+      if (r < rows) {
+        if (la) a = *reinterpret_cast<const uint2*>(za_base + r * ldz);
+        if (lb) b = *reinterpret_cast<const uint2*>(zb_base + r * ldz);
+      }
+      za[i] = uint2{a.x & ka.x, a.y & ka.y};
+      zb[i] = uint2{b.x & kb.x, b.y & kb.y};
+    }
+    u32x4 a[4], b[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      a[0][h] = __builtin_amdgcn_perm(za[2 * h + 1].x, za[2 * h].x, 0x05040100u);
+      a[1][h] = __builtin_amdgcn_perm(za[2 * h + 1].x, za[2 * h].x, 0x07060302u);
+      a[2][h] = __builtin_amdgcn_perm(za[2 * h + 1].y, za[2 * h].y, 0x05040100u);
+      a[3][h] = __builtin_amdgcn_perm(za[2 * h + 1].y, za[2 * h].y, 0x07060302u);
+      b[0][h] = __builtin_amdgcn_perm(zb[2 * h + 1].x, zb[2 * h].x, 0x05040100u);
+      b[1][h] = __builtin_amdgcn_perm(zb[2 * h + 1].x, zb[2 * h].x, 0x07060302u);
+      b[2][h] = __builtin_amdgcn_perm(zb[2 * h + 1].y, zb[2 * h].y, 0x05040100u);
+      b[3][h] = __builtin_amdgcn_perm(zb[2 * h + 1].y, zb[2 * h].y, 0x07060302u);
+    }
+#pragma unroll
+    for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb) acc[qa][qb] = mfma_bf16x8(a[qa], b[qb], acc[qa][qb]);
+  }
+  // element (m = acc_row(fg, r), n = fr) of instruction (qa, qb) is
+  // G[64 ta + 4 m + qa][64 tb + 4 n + qb]; local index (4 m + qa, 4 n + qb)
+  for (int w = 1; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            red[(4 * acc_row<float>(fg, r) + qa) * 64 + 4 * fr + qb] = acc[qa][qb][r];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[qa][qb][r] += red[(4 * acc_row<float>(fg, r) + qa) * 64 + 4 * fr + qb];
+    }
+    __syncthreads();
+  }
+  if (wave == 0) {
+#pragma unroll
+    for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = 64 * ta + 4 * acc_row<float>(fg, r) + qa;
+          const int64_t gj = 64 * tb + 4 * fr + qb;
+          if (gi < sj && gj < sj)
+            slot[gi * S + gj] = (double)acc[qa][qb][r] + (gi == gj ? 1.0 : 0.0);
+        }
+  }
+}
+
 }  // namespace
 
 hipError_t ztr_partial(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t s,
@@ -1496,6 +1609,9 @@ hipError_t gram(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t coff
   dim3 g((unsigned)(T * (T + 1) / 2));
   if (prec == BS_PREC_F64)
     gram_kernel<double><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, coff, sj, slot, S);
+  else if (prec == BS_PREC_BF16 && ldz % 4 == 0 && coff % 4 == 0 &&
+           reinterpret_cast<uintptr_t>(Z) % 8 == 0)
+    gram_bf16_kernel<<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, coff, sj, slot, S);
   else if (prec == BS_PREC_BF16)
     gram_kernel<uint16_t><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, coff, sj, slot, S);
   else

@@ -64,13 +64,14 @@ class Scheduler:
     """FIFO admission by footprint with a fixed number of execution slots."""
 
     def __init__(self, executor, budget_bytes, max_active=8, check_every=10, max_iters=200,
-                 rtol=2e-6, clock=time.perf_counter, idle_sleep=2e-4):
+                 rtol=2e-6, clock=time.perf_counter, idle_sleep=2e-4, ctol=5e-3):
         self.ex = executor
         self.budget = budget_bytes
         self.max_active = max_active
         self.check_every = check_every
         self.max_iters = max_iters
         self.rtol = rtol
+        self.ctol = ctol
         self.clock = clock
         self.idle_sleep = idle_sleep
         self.used = 0
@@ -79,8 +80,15 @@ class Scheduler:
         self.trace = []          # (t, event, rid, used)
 
     def _converged(self, slot, obj):
+        """Objective change between checks below rtol and, where the executor
+        reports it, the consensus residual ||W' - W-bar|| / ||W'|| below ctol:
+        the local model's objective settles well before the returned
+        consensus model W-bar has caught up with it."""
         prev = slot.prev_obj
-        return prev is not None and abs(obj - prev) <= self.rtol * max(abs(obj), 1e-300)
+        if prev is None or abs(obj - prev) > self.rtol * max(abs(obj), 1e-300):
+            return False
+        cons = getattr(self.ex, "consensus", None)
+        return cons is None or cons(slot.handle) <= self.ctol
 
     def run(self, jobs, time_scale=1.0):
         """Serve `jobs` (arrival times scaled by `time_scale`); returns results by rid."""
@@ -158,10 +166,21 @@ def latency_summary(results, wall_s):
         k = max(0, min(len(lat) - 1, int(math.ceil(p / 100.0 * len(lat))) - 1))
         return lat[k]
 
+    def pct_of(vals, p):
+        vals = sorted(vals)
+        if not vals:
+            return math.nan
+        return vals[max(0, min(len(vals) - 1, int(math.ceil(p / 100.0 * len(vals))) - 1))]
+
+    wait = [r.admitted_s - r.arrival_s for r in ok]
+    service = [r.finished_s - r.admitted_s for r in ok]
     iters = sum(r.iters for r in ok)
     return {"requests": len(results), "served": len(ok),
             "rejected": len(results) - len(ok),
             "p50_ms": 1e3 * pct(50), "p99_ms": 1e3 * pct(99), "max_ms": 1e3 * (lat[-1] if lat else math.nan),
+            # latency = queue wait (arrival to admission) + service (admission to result)
+            "wait_p50_ms": 1e3 * pct_of(wait, 50), "wait_p99_ms": 1e3 * pct_of(wait, 99),
+            "service_p50_ms": 1e3 * pct_of(service, 50), "service_p99_ms": 1e3 * pct_of(service, 99),
             "wall_s": wall_s, "solves_per_s": len(ok) / wall_s if wall_s > 0 else math.nan,
             "iters_per_s": iters / wall_s if wall_s > 0 else math.nan, "total_iters": iters}
 
@@ -186,16 +205,25 @@ class GpuExecutor:
     (BSADMM_Z_KEEP): Z is generated once at setup and iterations only stream
     it through the two products; its bytes are part of the admission
     footprint.  ``z_mode="store"`` regenerates Z every iteration instead.
+
+    The default precision is refined BF16 (BSADMM_BF16R): BF16 products, and
+    every fifth iteration the products of the kept feature defect (BF16X3
+    features minus BF16 ones) refresh their correction.  Plain BF16 converges
+    to the optimum of its perturbed features, which for some requests of the
+    stream is more than 1e-4 above the true one (a one-vs-all hinge request
+    with sigma = 2 at d = 784: 3.2e-4); the refined fixed point is within
+    1e-6 there.
     """
 
-    def __init__(self, precision="bf16x3", max_streams=8, device="cuda:0", setup_workers=2,
-                 z_mode="keep", rho_adapt=None):
+    def __init__(self, precision="bf16r", max_streams=16, device="cuda:0", setup_workers=4,
+                 z_mode="keep", rho_adapt=None, graph=True):
         import torch
         from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
         self.precision = precision
         self.z_mode = z_mode
         self.rho_adapt = rho_adapt        # (every, mu, tau): residual balancing per solve
+        self.graph = graph                # iteration chunks replayed as HIP graphs
         self.device = torch.device(device)
         self.free_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_streams)]
         self.pool = ThreadPoolExecutor(max_workers=setup_workers)
@@ -221,7 +249,7 @@ class GpuExecutor:
             dev = [torch.from_numpy(a).to(self.device) for a in (X, Y, W, b)]
             mon = torch.zeros(4, dtype=torch.float64, device=self.device)
         S = Solver(*dev, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision, stream=stream,
-                   z_mode=self.z_mode, rho_adapt=self.rho_adapt)
+                   z_mode=self.z_mode, rho_adapt=self.rho_adapt, graph=self.graph)
         return S, dev, mon
 
     def start(self, job):
@@ -268,6 +296,11 @@ class GpuExecutor:
         r = h["job"].spec
         return v[0] / r.n + r.lam * v[1]
 
+    def consensus(self, h):
+        """||W' - W-bar|| / ||W'|| from the same monitor read (R = 1)."""
+        v = h["host"].tolist()
+        return math.sqrt(v[2] / v[1]) if v[1] > 0 else math.inf
+
     def finish(self, h):
         coef = h["S"].coef().cpu().numpy()
         h["S"].close()
@@ -299,7 +332,7 @@ def _request_inputs(r):
     return wl.make_inputs(wl.request_workload(r))
 
 
-def serve_stream(count=256, rate_per_s=20.0, precision="bf16x3", budget_gb=160.0, max_active=8,
+def serve_stream(count=256, rate_per_s=20.0, precision="bf16r", budget_gb=160.0, max_active=16,
                  max_iters=300, check_every=10, rtol=2e-6, workers=8, n_range=(2000, 200000),
                  z_mode="keep", rho_adapt=None, jobs=None):
     """Run the request stream of the serving workload end to end; returns (summary, results)."""
@@ -315,6 +348,7 @@ def serve_stream(count=256, rate_per_s=20.0, precision="bf16x3", budget_gb=160.0
     wall = time.perf_counter() - t
     summ = latency_summary(res, wall)
     summ.update({"precision": precision, "z_mode": z_mode, "max_active": max_active,
+                 "ctol": sch.ctol,
                  "rho_adapt": list(rho_adapt) if rho_adapt else None,
                  "budget_gb": budget_gb,
                  "peak_active": sch.peak_active, "peak_used_gb": sch.peak_used / (1 << 30),
@@ -332,8 +366,8 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=20.0)
-    ap.add_argument("--precision", default="bf16x3")
-    ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--precision", default="bf16r")
+    ap.add_argument("--max-active", type=int, default=16)
     ap.add_argument("--z-mode", default="keep", choices=["keep", "store"])
     ap.add_argument("--rho-adapt", default="10,5,2",
                     help="every,mu,tau of residual balancing; 'off' keeps rho = 1")

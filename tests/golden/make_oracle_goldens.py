@@ -15,10 +15,12 @@ else, and stores what the GPU tests and the benchmark compare against:
 
 Usage: python tests/golden/make_oracle_goldens.py [name ...]
 Names: ridge (n = 4096, 100 iterations), digits (n = 200000, 25 iterations),
-speech (n = 100000, 25 iterations), digits2m_r2 (the 2M-row workload's first
-two row blocks, n = 250000 on a 2 x 8 grid with the same d, s, s_j, m; 5
-iterations).  Each takes from seconds (ridge) to about an hour (digits2m_r2)
-on 8 cores.
+digits_long (the same, 100 iterations), speech (n = 100000, 25 iterations),
+digits2m_r2 (the 2M-row workload's first two row blocks, n = 250000 on a
+2 x 8 grid with the same d, s, s_j, m; 5 iterations), serving_hinge (the
+optimal objective of three hinge / one-vs-all hinge requests of the serving
+stream, from 4000-iteration runs with penalty balancing; a JSON file).  Each
+takes from seconds (ridge) to about an hour (digits2m_r2) on 8 cores.
 """
 
 from __future__ import annotations
@@ -47,6 +49,8 @@ def spec(name):
         return wl.ridge_sine_4096(), 4096, 1, 100, True
     if name == "digits":
         return wl.digits_200k(), 200000, 4, 25, True
+    if name == "digits_long":
+        return wl.digits_200k(), 200000, 4, 100, True
     if name == "speech":
         return wl.speech_100k(), 100000, 4, 25, True
     if name == "digits2m_r2":
@@ -56,7 +60,38 @@ def spec(name):
 
 def golden_path(name):
     w, n, R, iters, _ = spec(name)
-    return os.path.join(HERE, f"oracle_{name}_it{iters}.npz")
+    stem = name.split("_long")[0]
+    return os.path.join(HERE, f"oracle_{stem}_it{iters}.npz")
+
+
+def serving_hinge_requests(reqs):
+    """The hinge requests of the serving stream the GPU test serves: the
+    first two binary ones and the first one-vs-all one with n <= 6000 and
+    s <= 2048."""
+    small = [r for r in reqs if r.loss == "hinge" and r.n <= 6000 and r.s <= 2048]
+    return [r for r in small if r.m == 1][:2] + [r for r in small if r.m > 1][:1]
+
+
+def make_serving_hinge(iters=4000, tail=500):
+    out = []
+    for r in serving_hinge_requests(wl.serving_stream(256)):
+        X, Y, W, b = wl.make_inputs(wl.request_workload(r))
+        loss = "hinge" if r.m == 1 else "mc_hinge"
+        C = max(1, -(-r.s // 4096))
+        p = o.Problem(X, Y, W, b, 1, C, r.lam, 1.0, loss)
+        Z = o.rff(X, W, b)
+        st, cache = o.admm(p, iters - tail, adapt=(10, 5.0, 2.0))
+        f1 = o.objective(loss, Z, Y, st["Wbar"], r.lam)
+        st, _ = o.admm(p, tail, state=st, cache=cache, adapt=(10, 5.0, 2.0))
+        f2 = o.objective(loss, Z, Y, st["Wbar"], r.lam)
+        out.append({"rid": r.rid, "loss": loss, "n": r.n, "d": r.d, "s": r.s, "m": r.m,
+                    "lambda": r.lam, "F": f2, "F_change_last_iters": abs(f2 - f1) / abs(f2),
+                    "iters": iters})
+        print(f"serving_hinge: request {r.rid} {loss} F = {f2:.17g}", flush=True)
+    path = os.path.join(HERE, "oracle_serving_hinge_optima.json")
+    with open(path, "w") as fh:
+        json.dump({"requests": out, "rate_per_s": 20.0, "stream_seed": 4, "count": 256}, fh,
+                  indent=1)
 
 
 def make(name):
@@ -93,5 +128,8 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or ["ridge", "digits", "speech", "digits2m_r2"]:
-        make(nm)
+    for nm in sys.argv[1:] or ["ridge", "digits", "speech", "digits2m_r2", "serving_hinge"]:
+        if nm == "serving_hinge":
+            make_serving_hinge()
+        else:
+            make(nm)

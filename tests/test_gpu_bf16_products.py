@@ -89,3 +89,41 @@ def test_bf16_products_speech_row_block():
     X, Y, W, b = wl.make_inputs(w, n)
     rows = np.random.default_rng(1).choice(n, size=64, replace=False)
     _check(X, Y, W, b, 1, w.C, w.loss, w.sigma, w.lam, rows_sample=rows)
+
+
+GRAM_CASES = [
+    # name, kind, n, d, s, m, R, C: ragged s_j (176 / 177: a partial 64-tile),
+    # s_j = 64 k, and rows that are not a multiple of the 128-row step
+    ("ragged_2x3", "digits", 5003, 64, 530, 10, 2, 3),
+    ("aligned_3x2", "digits", 4099, 784, 1024, 5, 3, 2),
+    ("one_tile_1x4", "speech_pm1", 777, 440, 256, 3, 1, 4),
+]
+
+
+@pytest.mark.parametrize("case", GRAM_CASES, ids=[c[0] for c in GRAM_CASES])
+def test_bf16_gram_gives_the_projection_of_the_bf16_features(case):
+    """The cached factor of a BF16 handle comes from the Gram of its BF16 Z
+    (BF16 MFMA, exact products, FP32 accumulation) and the FP64 inverse, so
+    after an iteration U = rhs - W' must equal Z_ij^T Z_ij W'_ij with the
+    device's own BF16 Z multiplied in FP64: to the FP32 accumulation of the
+    Gram (relative 1e-5 of |Z|^T |Z| |W'|)."""
+    from paper_1409_0940_amd import Solver
+    _, kind, n, d, s, m, R, C = case
+    X, Y, W, b = inputs(kind, n, d, s, m, 23, 10.0 if d != 440 else 8.0)
+    print(f"[bf16 gram] {case[0]}", flush=True)
+    S = Solver(to_dev(X), to_dev(Y), to_dev(W), to_dev(b), R, C, 1e-4, 1.0, 10.0,
+               "squared" if kind == "digits" else "mc_hinge", "bf16")
+    S.iterate(2)
+    Z = _bf16_z(X, W, b)
+    Wp = S.state("Wp").cpu().numpy()
+    U = S.state("U").cpu().numpy()
+    S.close()
+    rows, cols = o.partition(n, R), o.partition(s, C)
+    for i, (r0, r1) in enumerate(rows):
+        for j, (c0, c1) in enumerate(cols):
+            Zb = Z[r0:r1, c0:c1]
+            w = Wp[i, c0:c1]
+            want = Zb.T @ (Zb @ w)
+            mag = np.abs(Zb).T @ (np.abs(Zb) @ np.abs(w))
+            err = np.abs(U[i, c0:c1] - want) / np.maximum(mag, 1e-30)
+            assert err.max() <= 1e-5, (i, j, err.max())

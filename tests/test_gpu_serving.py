@@ -1,5 +1,7 @@
-"""GPU tests of the serving loop: results are the same alone and in the mix,
-and served ridge solves reach the closed-form optimum's objective to 1e-4."""
+"""GPU tests of the serving loop (refined BF16 solves with Z kept in HBM,
+iteration chunks replayed as HIP graphs): results are the same alone and in the mix,
+and served solves reach the optimum's objective to 1e-4 — the closed form for
+ridge requests, a long FP64 oracle run for hinge and one-vs-all hinge ones."""
 
 import numpy as np
 import pytest
@@ -10,25 +12,25 @@ from oracle import bsadmm_oracle as o
 pytestmark = pytest.mark.gpu
 
 
-def _jobs():
+def _jobs(pred, count):
     from paper_1409_0940_amd.serving import Job
-    reqs = [r for r in wl.serving_stream(256) if r.n <= 12000 and r.s <= 2048][:6]
-    jobs = []
-    for r in reqs:
-        inp = wl.make_inputs(wl.request_workload(r))
-        jobs.append(Job(r.rid, 0.0, r, inp))
-    return jobs
+    reqs = [r for r in wl.serving_stream(256) if pred(r)][:count]
+    return [Job(r.rid, 0.0, r, wl.make_inputs(wl.request_workload(r))) for r in reqs]
+
+
+def _small(r):
+    return r.n <= 12000 and r.s <= 2048
 
 
 def test_same_result_alone_and_in_the_mix():
     from paper_1409_0940_amd.serving import GpuExecutor, Scheduler
-    jobs = _jobs()
+    jobs = _jobs(_small, 6) + _jobs(lambda r: 20000 <= r.n <= 60000 and r.s == 8192, 2)
     assert len({(j.spec.d, j.spec.loss) for j in jobs}) >= 3
-    ex = GpuExecutor("bf16x3", max_streams=4)
-    mix = Scheduler(ex, 64 << 30, max_active=4, max_iters=300).run(jobs, time_scale=0.0)
-    assert max(len([1 for r in mix.values()]), 0) == len(jobs)
+    ex = GpuExecutor(max_streams=8)
+    mix = Scheduler(ex, 64 << 30, max_active=8, max_iters=300).run(jobs, time_scale=0.0)
+    assert len(mix) == len(jobs)
     for j in jobs:
-        ex1 = GpuExecutor("bf16x3", max_streams=1)
+        ex1 = GpuExecutor(max_streams=1)
         alone = Scheduler(ex1, 64 << 30, max_active=1, max_iters=300).run([j], time_scale=0.0)
         a, m = alone[j.rid], mix[j.rid]
         assert a.status == m.status == "ok"
@@ -36,12 +38,18 @@ def test_same_result_alone_and_in_the_mix():
         assert np.array_equal(a.coef, m.coef), j.rid
 
 
-@pytest.mark.parametrize("rho_adapt", [None, (10, 5.0, 2.0)], ids=["fixed_rho", "adaptive_rho"])
-def test_served_ridge_solves_reach_the_optimum(rho_adapt):
+# At the fixed penalty rho = 1 some larger requests converge too slowly for the
+# stopping rule (objective change below 2e-6 between checks) to land within
+# 1e-4 of the optimum in 300 iterations; the served configuration balances
+# the penalty, and is checked on the larger requests.
+@pytest.mark.parametrize("rho_adapt,big", [(None, False), ((10, 5.0, 2.0), True)],
+                         ids=["fixed_rho_small", "adaptive_rho"])
+def test_served_ridge_solves_reach_the_optimum(rho_adapt, big):
     from paper_1409_0940_amd.serving import GpuExecutor, Scheduler
-    jobs = [j for j in _jobs() if j.spec.loss == "squared"]
+    lim = (40000, 8192) if big else (12000, 2048)
+    jobs = _jobs(lambda r: r.loss == "squared" and r.n <= lim[0] and r.s <= lim[1], 5)
     assert jobs
-    res = Scheduler(GpuExecutor("bf16x3", 4, rho_adapt=rho_adapt), 64 << 30, max_active=4,
+    res = Scheduler(GpuExecutor(rho_adapt=rho_adapt), 64 << 30, max_active=4,
                     max_iters=300).run(jobs, time_scale=0.0)
     for j in jobs:
         X, Y, W, b = j.inputs
@@ -49,3 +57,28 @@ def test_served_ridge_solves_reach_the_optimum(rho_adapt):
         fstar = o.objective("squared", Z, Y, o.ridge_closed_form(Z, Y, j.spec.lam), j.spec.lam)
         f = o.objective("squared", Z, Y, res[j.rid].coef, j.spec.lam)
         assert (f - fstar) / fstar <= 1e-4, (j.rid, f, fstar)
+
+
+def test_served_hinge_solves_reach_the_optimum():
+    """Binary hinge (d = 16) and one-vs-all hinge (d = 784, m = 10) requests
+    against the optimal objective of long oracle runs (written by
+    tests/golden/make_oracle_goldens.py serving_hinge)."""
+    import json
+    import os
+    from paper_1409_0940_amd.serving import GpuExecutor, Job, Scheduler, _loss
+    from tests.golden.make_oracle_goldens import serving_hinge_requests
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "oracle_serving_hinge_optima.json")) as fh:
+        optima = {r["rid"]: r for r in json.load(fh)["requests"]}
+    reqs = serving_hinge_requests(wl.serving_stream(256))
+    assert {r.rid for r in reqs} == set(optima)
+    jobs = [Job(r.rid, 0.0, r, wl.make_inputs(wl.request_workload(r))) for r in reqs]
+    res = Scheduler(GpuExecutor(rho_adapt=(10, 5.0, 2.0)), 64 << 30, max_active=3,
+                    max_iters=300).run(jobs, time_scale=0.0)
+    for j in jobs:
+        loss = _loss(j)
+        assert optima[j.rid]["loss"] == loss and optima[j.rid]["F_change_last_iters"] <= 1e-8
+        X, Y, W, b = j.inputs
+        f = o.objective(loss, o.rff(X, W, b), Y, res[j.rid].coef, j.spec.lam)
+        fstar = optima[j.rid]["F"]
+        assert (f - fstar) / fstar <= 1e-4, (j.rid, loss, f, fstar)

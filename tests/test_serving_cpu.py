@@ -126,3 +126,27 @@ def test_latency_summary_percentiles():
     assert s["solves_per_s"] == pytest.approx(50.0)
     assert s["iters_per_s"] == pytest.approx(500.0)
     assert math.isclose(s["max_ms"], 1000.0)
+
+
+def test_stopping_waits_for_the_consensus_residual():
+    """With an executor that reports the consensus residual, a solve whose
+    objective has settled keeps iterating until ||W' - W-bar|| / ||W'|| is
+    below ctol."""
+    clk = Clock()
+
+    class Consensus(FakeExecutor):
+        def objective(self, h):
+            return 1.0                      # settled from the first check on
+
+        def consensus(self, h):
+            return 0.5 ** (h["iters"] / 10.0)
+
+    ex = Consensus(clk)
+    sch = Scheduler(ex, budget_bytes=10, max_active=1, check_every=10, max_iters=1000,
+                    rtol=1e-6, clock=clk, idle_sleep=0.0, ctol=1e-3)
+    res = sch.run(_jobs([1]))
+    # 0.5^(k/10) <= 1e-3 first at k = 100
+    assert res[0].iters == 100
+    plain = Scheduler(FakeExecutor(Clock()), budget_bytes=10, max_active=1, check_every=10,
+                      max_iters=1000, rtol=1e-6, idle_sleep=0.0)
+    assert "consensus" not in dir(plain.ex)
