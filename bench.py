@@ -55,8 +55,11 @@ REGEN_KERNEL = {"fp32": "regen_kernel<FP32>", "fp64": "regen_kernel<FP64>",
                 "bf16r": "regen_bf16_wide_kernel"}
 Z_BYTES = {"fp32": 4, "fp64": 8, "bf16": 2, "bf16x3": 4, "bf16r": 2}
 
-TRAFFIC_PROFILE = {("digits_n200000_d784_s10240_m10", "fp32"):
-                   "profiles/regen_fp32_digits_n200000_s10240_traffic.md"}
+TRAFFIC_PROFILE = {
+    ("digits_n200000_d784_s10240_m10", "fp32"): "profiles/regen_fp32_digits_n200000_s10240_traffic.md",
+    ("digits_n200000_d784_s10240_m10", "bf16"): "profiles/regen_bf16_digits_n200000_s10240_traffic.md",
+    ("digits_n200000_d784_s10240_m10", "bf16r"): "profiles/regen_bf16_digits_n200000_s10240_traffic.md",
+}
 KERNEL_SOURCES = ["paper_1409_0940_amd/csrc/feature.hip", "paper_1409_0940_amd/csrc/common.h"]
 
 # residual balancing of the serving solves: check every 10 iterations, mu = 5, tau = 2
@@ -462,6 +465,10 @@ def main():
     ap.add_argument("--big-variants", default="bf16,bf16r:r5,bf16x3")
     ap.add_argument("--big-steps", type=int, default=10,
                     help="timed iterations of the 2M-row workload")
+    ap.add_argument("--profile", default="",
+                    help="WORKLOAD:PRECISION[:rK|:keep] -- only setup, warm-up and the timed steps "
+                         "of that one run (for kernel profiles); workloads: digits, ridge, speech, "
+                         "digits2m")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 4 device copies of 1 GiB (HBM counter calibration) and exit")
     ap.add_argument("--serving", type=int, default=256,
@@ -482,6 +489,22 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
                           "copies": 4}))
+        return
+
+    if args.profile:
+        import workloads as wl
+        name, prec, *opt = args.profile.split(":")
+        w = {"digits": wl.digits_200k, "ridge": wl.ridge_sine_4096, "speech": wl.speech_100k,
+             "digits2m": wl.digits_2m}[name]()
+        kw = {}
+        if opt and opt[0] == "keep":
+            kw["z_mode"] = "keep"
+        elif opt and opt[0].startswith("r"):
+            kw["refine_every"] = int(opt[0][1:])
+        X, Y, Wr, b = wl.make_inputs(w)
+        S, rec = run_precision(w, resident((X, Y, Wr, b)), prec, args.steps, args.warmup, **kw)
+        S.close()
+        print(json.dumps(rounded({"profile": args.profile, "workload": w.name, **rec})), flush=True)
         return
 
     t_start = time.perf_counter()
