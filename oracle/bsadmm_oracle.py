@@ -53,6 +53,7 @@ __all__ = [
     "objective", "ridge_closed_form", "ridge_push_through",
     "graph_projection", "Problem", "weights", "admm", "admm_reference",
     "paper_memory_floats", "predict", "set_rho", "residuals", "balance_factor",
+    "dual_point", "dual_objective",
 ]
 
 
@@ -245,6 +246,48 @@ def objective(kind, Z, Y, Wmodel, lam):
     """F(W) = (1/n) sum_r V(y_r, W^T z_r) + lam ||W||_F^2 (linearised problem)."""
     n = Z.shape[0]
     return loss_sum(kind, Y, Z @ Wmodel) / n + lam * float((Wmodel * Wmodel).sum())
+
+
+# ---------------------------------------------------------------------------
+# Lower bound on the optimum through the Fenchel dual of F (not in the paper;
+# used to certify an objective error).  With o = Z W and V_r*(u) the convex
+# conjugate of o -> V(y_r, o),
+#   F(W) = (1/n) sum_r V(y_r, z_r^T W) + lam ||W||^2
+#        >= (1/n) sum_r -V_r*(-alpha_r) - ||Z^T alpha||^2 / (4 lam n^2) = D(alpha)
+# for every alpha (n x m): minimising the Lagrangian over W gives
+# W = Z^T alpha / (2 lam n).  Conjugates: squared loss ||y - o||^2 has
+# V*(u) = u.y + ||u||^2 / 4; the (one-vs-all) hinge sum_k max(0, 1 - y_k o_k)
+# has V*(u) = u.y when every u_k y_k lies in [-1, 0], +inf otherwise.
+# ---------------------------------------------------------------------------
+
+def dual_point(kind, Y, V):
+    """Nearest point of the conjugate's domain: V itself for the squared loss,
+    y * clip(y * V, 0, 1) for the hinge losses."""
+    V = np.asarray(V, dtype=np.float64)
+    if kind == "squared":
+        return V.copy()
+    if kind in ("hinge", "mc_hinge"):
+        Y = np.asarray(Y, dtype=np.float64)
+        return Y * np.clip(Y * V, 0.0, 1.0)
+    raise ValueError(kind)
+
+
+def dual_objective(kind, Z, Y, alpha, lam):
+    """D(alpha) of the dual above (-inf outside the hinge's dual domain)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    alpha = np.asarray(alpha, dtype=np.float64)
+    n = Z.shape[0]
+    if kind == "squared":
+        conj = float((alpha * Y).sum() - 0.25 * (alpha * alpha).sum())
+    elif kind in ("hinge", "mc_hinge"):
+        t = alpha * Y
+        if (t < -1e-12).any() or (t > 1.0 + 1e-12).any():
+            return -math.inf
+        conj = float(t.sum())
+    else:
+        raise ValueError(kind)
+    g = Z.T @ alpha
+    return conj / n - float((g * g).sum()) / (4.0 * lam * n * n)
 
 
 # ---------------------------------------------------------------------------
