@@ -414,6 +414,36 @@ BSADMM_API int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* 
 BSADMM_API int bsadmm_monitor(bsadmm_handle* h, double* out);
 
 /* ----------------------------------------------------------------------
+ * bsadmm_dual_bound -- a lower bound on min F (eq. problem_linear), for
+ * certifying the objective error of a run; not in the paper.  With V_r* the
+ * convex conjugate of o -> V(y_r, o), weak Fenchel duality gives for every
+ * alpha (n x m)
+ *   F(W) >= D(alpha) = (1/n) sum_r -V_r*(-alpha_r) - ||Z^T alpha||^2 / (4 lambda n^2),
+ * with -V*(-a) = a y - a^2/4 (squared loss) and a y on the domain
+ * 0 <= a y <= 1 (hinge, one-vs-all hinge).  alpha is the penalty times the
+ * row operand of the state left by the last iteration,
+ * rho (Delta-bar/(C+1) + nu), moved into that domain (y clip(y a, 0, 1));
+ * at the ADMM fixed point it is the dual solution and D = min F.
+ * Enqueued on the handle's stream without synchronising: one transpose
+ * product over Z (two for BF16R, whose bound uses the BF16 features plus
+ * their defect; feature regeneration first unless Z is kept), into the
+ * caller-owned device array out[0..2] (doubles):
+ *   out[0] = D(alpha),  out[1] = the conjugate part,  out[2] = the
+ *   ||Z^T alpha||^2 / (4 lambda n^2) part.
+ * alpha enters the product as the precision's operand of R (FP64, FP32, or
+ * BF16 head and residual planes) and the conjugate part is summed over that
+ * rounded alpha, so out[0] is the dual objective of a point of the domain.
+ * It overwrites the R operand and right-hand-side buffers and the Z
+ * workspace, all rewritten by the next iteration, so the iteration is not
+ * changed.  With R = 1, F(W') from bsadmm_monitor minus out[0] bounds the
+ * objective error of the local model W' (state BSADMM_ST_WP).  BF16R
+ * allocates an R x s x m FP64 buffer at the first call (stream-ordered).
+ * Errors: EINVAL (null argument; a loss other than squared, hinge or
+ * one-vs-all hinge), ESTATE, ENOMEM, EDEVICE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_dual_bound(bsadmm_handle* h, double* out);
+
+/* ----------------------------------------------------------------------
  * bsadmm_set_rho -- change the ADMM penalty to rho (> 0, finite) for the
  * following iterations.  The loss-prox weight becomes 1/rho and the
  * regulariser weight n lambda / rho; with rescale_duals != 0 the scaled

@@ -30,7 +30,8 @@ PHASES = ["regen", "ztr", "solve", "zw", "row", "col", "refine"]
 
 EXPORTED = ["rff_map", "rff_map_noalloc", "bsadmm_validate", "bsadmm_footprint", "bsadmm_setup", "bsadmm_iterate",
             "bsadmm_predict", "bsadmm_get_coef", "bsadmm_state_size", "bsadmm_export_state",
-            "bsadmm_import_state", "bsadmm_objective", "bsadmm_monitor", "bsadmm_set_rho",
+            "bsadmm_import_state", "bsadmm_objective", "bsadmm_monitor", "bsadmm_dual_bound",
+            "bsadmm_set_rho",
             "bsadmm_destroy", "bsadmm_last_error"]
 
 
@@ -90,6 +91,7 @@ def lib():
         L.bsadmm_import_state.argtypes = [vp, i32, vp]
         L.bsadmm_objective.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.bsadmm_monitor.argtypes = [vp, vp]
+        L.bsadmm_dual_bound.argtypes = [vp, vp]
         L.bsadmm_set_rho.argtypes = [vp, ctypes.c_double, i32]
         L.bsadmm_destroy.argtypes = [vp]
         L.bsadmm_last_error.argtypes = []
@@ -279,6 +281,13 @@ def bsadmm_objective(h, Wmodel=None):
 def bsadmm_monitor(h, out):
     """Enqueue the convergence reductions into out (4 float64 on the device)."""
     _check("bsadmm_monitor", lib().bsadmm_monitor(h, _ptr(out)))
+    return out
+
+
+def bsadmm_dual_bound(h, out):
+    """Enqueue the Fenchel lower bound on min F into out (3 float64 on the
+    device: D, its conjugate part, its quadratic part)."""
+    _check("bsadmm_dual_bound", lib().bsadmm_dual_bound(h, _ptr(out)))
     return out
 
 

@@ -233,6 +233,7 @@ struct bsadmm_handle {
        *Wop = nullptr, *part = nullptr;
   void *Zd = nullptr, *Zf = nullptr;  // refined BF16: feature defect, FP32-faithful features
   double *cA = nullptr, *cP = nullptr;  // refined BF16: stored product defects
+  double* dualA = nullptr;  // refined BF16 dual bound: defect part of Z^T alpha (lazy)
   double *Q = nullptr, *O = nullptr, *Obar = nullptr, *nu = nullptr, *Dbar = nullptr,
          *P = nullptr, *Wbar = nullptr, *mu = nullptr, *Wc = nullptr, *Wp = nullptr,
          *mup = nullptr, *U = nullptr, *rhs = nullptr;
@@ -423,6 +424,57 @@ int objective_of(bsadmm_handle* h, const double* Wmodel, double* F) {
   return BSADMM_OK;
 }
 
+// Transpose products Z_ij^T R_i of the row blocks [i0, i1) of a group into
+// the split partials; z is the group's feature workspace (the features of
+// the handle's precision, or the defect of refined BF16) and R the operand
+// buffer as the row step (or the dual bound) wrote it.
+hipError_t ztr_rows(bsadmm_handle* h, int i0, int i1, const void* z, hipStream_t s) {
+  const Plan& L = h->L;
+  const int64_t r0 = L.rstart[i0];
+  for (int i = i0; i < i1; ++i) {
+    const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
+    const char* Ri = bs::bf16_planes(L.prec, L.mp)
+                         ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
+                         : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
+    hipError_t e = bs::ztr_partial(
+        L.prec, (const char*)z + (size_t)(ri - r0) * L.spad * L.zb, L.spad, ni, L.spad, Ri,
+        (int64_t)L.R * L.nbpad, L.mp, L.split_rows,
+        (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.vb, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Enqueue the dual bound on the handle's stream: alpha from the current
+// state into the R operand buffer (free between iterations), Z^T alpha over
+// every group into rhs (also free between iterations; refined BF16 adds the
+// defect product, so the bound is that of the FP32-faithful features), and
+// the final sums into out[0..2].
+int enqueue_dual_bound(bsadmm_handle* h, int loss, double* out) {
+  const Plan& L = h->L;
+  const hipStream_t st = h->st;
+  const double cfac = 1.0 / (double)(L.C + 1);
+  HCHK(bs::dual_rows(L.prec, loss, h->wts, cfac, L.n, L.R, L.m, L.mp, L.nbpad, h->p.Y, h->nu,
+                     h->Dbar, h->Rop, h->mon_part, kMonBlocks, st));
+  for (const auto& g : L.groups) {
+    const int i0 = g.first, i1 = g.second;
+    if (!L.keep) HCHK(regen_group(h, i0, i1, st));
+    if (L.refine) {
+      if (!L.keep) HCHK(defect_group(h, i0, i1, st, h->Zf));
+      HCHK(ztr_rows(h, i0, i1, h->Zd, st));
+      HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
+                          L.mp, nullptr, nullptr, nullptr, nullptr, h->dualA, st));
+    }
+    HCHK(ztr_rows(h, i0, i1, h->Z, st));
+    HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
+                        L.mp, nullptr, nullptr, nullptr, L.refine ? h->dualA : nullptr, h->rhs,
+                        st));
+  }
+  HCHK(bs::dual_final(h->rhs, L.R, L.spad * L.mp, L.n, h->p.lambda, h->mon_part, kMonBlocks, out,
+                      st));
+  return BSADMM_OK;
+}
+
 // Whether iteration number `k` (1-based over the handle's life) ends with a
 // residual-balancing check.
 inline bool checked_iteration(const bsadmm_handle* h, int64_t k) {
@@ -465,29 +517,13 @@ int enqueue_iteration(bsadmm_handle* h, hipStream_t s, bool check, bool refine, 
   end(BSADMM_PH_COL);
   for (const auto& g : L.groups) {
     const int i0 = g.first, i1 = g.second;
-    const int64_t r0 = L.rstart[i0];
     if (!L.keep) {  // a kept Z was generated at setup
       begin();
       HCHK(regen_group(h, i0, i1, st));
       launches += L.C;
       end(BSADMM_PH_REGEN);
     }
-    // transpose products Z_ij^T R_i of the row blocks of the group into the
-    // split partials (feature block z: the BF16 features or their defect)
-    auto ztr_group = [&](const void* z) -> hipError_t {
-      for (int i = i0; i < i1; ++i) {
-        const int64_t ri = L.rstart[i], ni = L.rstart[i + 1] - ri;
-        const char* Ri = bs::bf16_planes(L.prec, L.mp)
-                             ? (const char*)h->Rop + (size_t)i * L.nbpad * 2
-                             : (const char*)h->Rop + (size_t)ri * L.mp * L.vb;
-        hipError_t e = bs::ztr_partial(
-            L.prec, (const char*)z + (size_t)(ri - r0) * L.spad * L.zb, L.spad, ni, L.spad, Ri,
-            (int64_t)L.R * L.nbpad, L.mp, L.split_rows,
-            (char*)h->part + (size_t)i * L.nsplit_max * L.spad * L.mp * L.vb, s);
-        if (e != hipSuccess) return e;
-      }
-      return hipSuccess;
-    };
+    auto ztr_group = [&](const void* z) { return ztr_rows(h, i0, i1, z, s); };
     if (refine) {
       // Refinement of the projection's products: FP32-faithful features of
       // the group, their defect against the BF16 features, and the defects
@@ -1122,6 +1158,23 @@ int bsadmm_monitor(bsadmm_handle* h, double* out) {
     return hip_fail(e, "monitor");
   }
   return BSADMM_OK;
+}
+
+int bsadmm_dual_bound(bsadmm_handle* h, double* out) {
+  g_err.clear();
+  if (!h || !out) return fail(BSADMM_EINVAL, "NULL argument");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  const int loss = kernel_loss(h->p.loss);
+  if (h->p.loss != BSADMM_SQUARED && h->p.loss != BSADMM_HINGE && h->p.loss != BSADMM_MC_HINGE)
+    return fail(BSADMM_EINVAL, "dual bound: squared, hinge and one-vs-all hinge losses only");
+  const Plan& L = h->L;
+  if (L.refine && !h->dualA) {
+    if (h->alloc((void**)&h->dualA, (size_t)L.R * L.spad * L.mp * 8) != hipSuccess)
+      return fail(BSADMM_ENOMEM, "device allocation failed in dual bound");
+  }
+  const int rc = enqueue_dual_bound(h, loss, out);
+  if (rc != BSADMM_OK) h->poisoned = true;
+  return rc;
 }
 
 int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F) {

@@ -490,6 +490,111 @@ __global__ void final_reduce_kernel(const double* __restrict__ part, int nb, dou
   if (threadIdx.x == 0) out[q] = sc * t;
 }
 
+// ---------------------------------------------------------------------------
+// Lower bound on the optimum of F through its Fenchel dual (not in the
+// paper): for any alpha (n x m) in the domain of the conjugate losses,
+//   D(alpha) = (1/n) sum_r -V*(-alpha_r) - ||Z^T alpha||^2 / (4 lambda n^2)
+// is at most min F.  -V*(-a) is a y - a^2 / 4 for the squared loss and a y
+// for the hinge losses, whose domain is a y in [0, 1].  The dual point is
+// the penalty times the row operand, rho (Delta-bar / (C+1) + nu), moved
+// into that domain (hinge: y clip(y a, 0, 1)); at the ADMM fixed point it is
+// the dual solution.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dual_value(int loss, double a, double y) {
+  if (loss == 0) return a;
+  double t = y * a;
+  t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+  return y * t;
+}
+
+// alpha into the FP64 / FP32 operand layout of R (n x mp); part[block] =
+// sum of the conjugate terms of the rounded alpha (the operand the product
+// sees, still in the domain: rounding keeps 0 <= y a <= 1).
+template <typename OP>
+__global__ void dual_rows_kernel(int loss, const double* __restrict__ wts, double cfac, int64_t n,
+                                 int64_t m, int64_t mp, const float* __restrict__ Y,
+                                 const double* __restrict__ nu, const double* __restrict__ Dbar,
+                                 OP* __restrict__ Rop, double* __restrict__ part) {
+  __shared__ double red[256];
+  const double rho = wts[BS_W_RHO];
+  double conj = 0.0;
+  GRID_STRIDE(e, n * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    const double y = (double)Y[e];
+    const OP q = cvt_from_double<OP>(dual_value(loss, rho * (Dbar[o] * cfac + nu[o]), y));
+    Rop[o] = q;
+    const double a = to_double(q);
+    conj += loss == 0 ? a * y - 0.25 * a * a : a * y;
+  }
+  const double t = block_sum(conj, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// The same into the BF16 head and residual planes (layout of row_pre_bf16).
+__global__ void dual_rows_bf16_kernel(int loss, const double* __restrict__ wts, double cfac,
+                                      int64_t n, int R, int64_t m, int64_t mp, int64_t nbpad,
+                                      const float* __restrict__ Y, const double* __restrict__ nu,
+                                      const double* __restrict__ Dbar, uint16_t* __restrict__ Rt,
+                                      double* __restrict__ part) {
+  __shared__ double red[256];
+  const double rho = wts[BS_W_RHO];
+  const int64_t ldr = (int64_t)R * nbpad;
+  double conj = 0.0;
+  GRID_STRIDE(e, n * m) {
+    const int64_t r = e / m, c = e - r * m;
+    const int64_t o = r * mp + c;
+    const double y = (double)Y[e];
+    const double v = dual_value(loss, rho * (Dbar[o] * cfac + nu[o]), y);
+    int64_t i = r * R / n;
+    while (i + 1 < R && (i + 1) * n / R <= r) ++i;
+    while (i > 0 && i * n / R > r) --i;
+    uint16_t hi, lo;
+    split_bf16(v, hi, lo);
+    const int64_t t = c * ldr + i * nbpad + (r - i * n / R);
+    Rt[t] = hi;
+    Rt[t + mp * ldr] = lo;
+    const double a = (double)bf16_to_f32(hi) + (double)bf16_to_f32(lo);
+    conj += loss == 0 ? a * y - 0.25 * a * a : a * y;
+  }
+  const double t = block_sum(conj, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// part[block] = sum over this block's share of the feature x column entries
+// e of (sum_i A[i][e])^2: Z^T alpha = sum over row blocks of Z_ij^T alpha_i.
+__global__ void colsum_sumsq_partial_kernel(const double* __restrict__ A, int R, int64_t per,
+                                            double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  GRID_STRIDE(e, per) {
+    double v = 0.0;
+    for (int i = 0; i < R; ++i) v += A[(int64_t)i * per + e];
+    acc += v * v;
+  }
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// out = {D, conjugate part / n, quadratic part}, partials as in dual_bound
+__global__ void dual_final_kernel(const double* __restrict__ part, int nb, double n,
+                                  double lambda, double* __restrict__ out) {
+  __shared__ double red[2][256];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) {
+    a += part[k];
+    b += part[nb + k];
+  }
+  const double conj = block_sum(a, red[0]);
+  const double sq = block_sum(b, red[1]);
+  if (threadIdx.x == 0) {
+    const double c = conj / n, q = sq / (4.0 * lambda * n * n);
+    out[0] = c - q;
+    out[1] = c;
+    out[2] = q;
+  }
+}
+
 }  // namespace
 
 hipError_t monitor(int loss, const double* P, const float* Y, const double* Wp,
@@ -517,6 +622,28 @@ hipError_t residuals(const ResidualArgs& a, int R, int64_t n, int64_t spad, int6
                                              part + 6 * nb);
   diffsq_partial_kernel<<<nb, 256, 0, st>>>(a.Dbar, a.Dbar_prev, 1, n, m, mp, part + 7 * nb);
   final_reduce_kernel<<<8, 256, 0, st>>>(part, nb, 1.0, 1.0, 1.0, 1.0, out);
+  return hipGetLastError();
+}
+
+hipError_t dual_rows(int prec, int loss, const double* wts, double cfac, int64_t n, int R,
+                     int64_t m, int64_t mp, int64_t nbpad, const float* Y, const double* nu,
+                     const double* Dbar, void* Rop, double* part, int nb, hipStream_t st) {
+  if (bf16_planes(prec, mp))
+    dual_rows_bf16_kernel<<<nb, 256, 0, st>>>(loss, wts, cfac, n, R, m, mp, nbpad, Y, nu, Dbar,
+                                              (uint16_t*)Rop, part);
+  else if (prec == BS_PREC_F64)
+    dual_rows_kernel<double><<<nb, 256, 0, st>>>(loss, wts, cfac, n, m, mp, Y, nu, Dbar,
+                                                 (double*)Rop, part);
+  else
+    dual_rows_kernel<float><<<nb, 256, 0, st>>>(loss, wts, cfac, n, m, mp, Y, nu, Dbar,
+                                                (float*)Rop, part);
+  return hipGetLastError();
+}
+
+hipError_t dual_final(const double* A, int R, int64_t per, int64_t n, double lambda, double* part,
+                      int nb, double* out, hipStream_t st) {
+  colsum_sumsq_partial_kernel<<<nb, 256, 0, st>>>(A, R, per, part + nb);
+  dual_final_kernel<<<1, 256, 0, st>>>(part, nb, (double)n, lambda, out);
   return hipGetLastError();
 }
 

@@ -167,6 +167,16 @@ hipError_t sumsq_partial(const double* a, int64_t count, double* part, int nbloc
 // Convergence monitor (no synchronisation): out[0] = sum V(y, P),
 // out[1] = sum_i ||Wp_i||^2 / R, out[2] = sum_i ||Wp_i - Wbar||^2,
 // out[3] = ||Dbar||^2, via nb partial sums per quantity in `part` (4 nb).
+// Fenchel dual bound (not in the paper): alpha = rho (Delta-bar/(C+1) + nu)
+// moved into the conjugate's domain (loss 0 squared, 1 hinge), written into
+// the R operand layout, with the conjugate terms' partial sums in part[0, nb).
+hipError_t dual_rows(int prec, int loss, const double* wts, double cfac, int64_t n, int R,
+                     int64_t m, int64_t mp, int64_t nbpad, const float* Y, const double* nu,
+                     const double* Dbar, void* Rop, double* part, int nb, hipStream_t st);
+// out = {D, conj / n, ||Z^T alpha||^2 / (4 lambda n^2)} from part[0, nb) and
+// A = Z_ij^T alpha_i (R blocks of `per` values, summed over i).
+hipError_t dual_final(const double* A, int R, int64_t per, int64_t n, double lambda, double* part,
+                      int nb, double* out, hipStream_t st);
 hipError_t monitor(int loss, const double* P, const float* Y, const double* Wp,
                    const double* Wbar, const double* Dbar, int R, int64_t n, int64_t spad,
                    int64_t m, int64_t mp, double* part, int nb, double* out, hipStream_t st);

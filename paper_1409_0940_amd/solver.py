@@ -78,6 +78,11 @@ class Solver:
         """Enqueue [sum V(y, Z W'), mean ||W'_i||^2, sum ||W'_i - W-bar||^2, ||Delta-bar||^2]."""
         return abi.bsadmm_monitor(self.h, out)
 
+    def dual_bound_async(self, out):
+        """Enqueue [D, conjugate part, quadratic part] of the Fenchel lower
+        bound D <= min F at the current state (squared and hinge losses)."""
+        return abi.bsadmm_dual_bound(self.h, out)
+
     def predict(self, Xt):
         return abi.bsadmm_predict(self.h, Xt, self.m, stream=self.stream)
 
