@@ -62,8 +62,6 @@ TRAFFIC_PROFILE = {
 }
 KERNEL_SOURCES = ["paper_1409_0940_amd/csrc/feature.hip", "paper_1409_0940_amd/csrc/common.h"]
 
-# residual balancing of the serving solves: check every 10 iterations, mu = 5, tau = 2
-SERVING_ADAPT = (10, 5.0, 2.0)
 
 
 def log(msg):
@@ -549,8 +547,8 @@ def main():
     }
     if args.serving:
         from paper_1409_0940_amd.serving import serve_stream
-        log(f"serving stream: {args.serving} requests at 20/s, penalty adaptation {SERVING_ADAPT}")
-        summ, _, _ = serve_stream(args.serving, rho_adapt=SERVING_ADAPT)
+        log(f"serving stream: {args.serving} requests at 20/s, certified stopping")
+        summ, _, _ = serve_stream(args.serving)
         out["serving"] = summ
         log(f"serving: p50 {summ['p50_ms']:.1f} ms, p99 {summ['p99_ms']:.1f} ms, "
             f"{summ['solves_per_s']:.2f} solves/s")

@@ -1,7 +1,9 @@
 """GPU tests of the serving loop (refined BF16 solves with Z kept in HBM,
-iteration chunks replayed as HIP graphs): results are the same alone and in the mix,
-and served solves reach the optimum's objective to 1e-4 — the closed form for
-ridge requests, a long FP64 oracle run for hinge and one-vs-all hinge ones."""
+iteration chunks replayed as HIP graphs, stopping certified by the duality
+gap of the library's dual bound): results are the same alone and in the mix,
+and served solves reach the optimum's objective to 1e-4 -- the closed form
+for ridge requests, a long FP64 oracle run for hinge and one-vs-all hinge
+ones."""
 
 import numpy as np
 import pytest
@@ -38,24 +40,22 @@ def test_same_result_alone_and_in_the_mix():
         assert np.array_equal(a.coef, m.coef), j.rid
 
 
-# At the fixed penalty rho = 1 some larger requests converge too slowly for the
-# stopping rule (objective change below 2e-6 between checks) to land within
-# 1e-4 of the optimum in 300 iterations; the served configuration balances
-# the penalty, and is checked on the larger requests.
-@pytest.mark.parametrize("rho_adapt,big", [(None, False), ((10, 5.0, 2.0), True)],
-                         ids=["fixed_rho_small", "adaptive_rho"])
-def test_served_ridge_solves_reach_the_optimum(rho_adapt, big):
+@pytest.mark.parametrize("big", [False, True], ids=["small", "large"])
+def test_served_ridge_solves_reach_the_optimum(big):
+    """Certified stops (status ok) are within 1e-4 of the closed form's
+    objective, and within the gap the executor certified."""
     from paper_1409_0940_amd.serving import GpuExecutor, Scheduler
     lim = (40000, 8192) if big else (12000, 2048)
-    jobs = _jobs(lambda r: r.loss == "squared" and r.n <= lim[0] and r.s <= lim[1], 5)
+    jobs = _jobs(lambda r: r.loss == "squared" and r.n <= lim[0] and r.s <= lim[1]
+                 and (r.n >= 12000 or not big), 5)
     assert jobs
-    res = Scheduler(GpuExecutor(rho_adapt=rho_adapt), 64 << 30, max_active=4,
-                    max_iters=300).run(jobs, time_scale=0.0)
+    res = Scheduler(GpuExecutor(), 64 << 30, max_active=4, max_iters=300).run(jobs, time_scale=0.0)
     for j in jobs:
         X, Y, W, b = j.inputs
         Z = o.rff(X, W, b)
         fstar = o.objective("squared", Z, Y, o.ridge_closed_form(Z, Y, j.spec.lam), j.spec.lam)
         f = o.objective("squared", Z, Y, res[j.rid].coef, j.spec.lam)
+        assert res[j.rid].status == "ok", (j.rid, res[j.rid].iters)
         assert (f - fstar) / fstar <= 1e-4, (j.rid, f, fstar)
 
 
@@ -73,12 +73,14 @@ def test_served_hinge_solves_reach_the_optimum():
     reqs = serving_hinge_requests(wl.serving_stream(256))
     assert {r.rid for r in reqs} == set(optima)
     jobs = [Job(r.rid, 0.0, r, wl.make_inputs(wl.request_workload(r))) for r in reqs]
-    res = Scheduler(GpuExecutor(rho_adapt=(10, 5.0, 2.0)), 64 << 30, max_active=3,
-                    max_iters=300).run(jobs, time_scale=0.0)
+    # the binary hinge request 15 certifies after about 450 iterations
+    res = Scheduler(GpuExecutor(), 64 << 30, max_active=3, max_iters=600).run(jobs,
+                                                                               time_scale=0.0)
     for j in jobs:
         loss = _loss(j)
         assert optima[j.rid]["loss"] == loss and optima[j.rid]["F_change_last_iters"] <= 1e-8
         X, Y, W, b = j.inputs
         f = o.objective(loss, o.rff(X, W, b), Y, res[j.rid].coef, j.spec.lam)
         fstar = optima[j.rid]["F"]
+        assert res[j.rid].status == "ok", (j.rid, res[j.rid].iters)
         assert (f - fstar) / fstar <= 1e-4, (j.rid, loss, f, fstar)

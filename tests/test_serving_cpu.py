@@ -158,3 +158,38 @@ def test_stopping_waits_for_the_consensus_residual():
     plain = Scheduler(FakeExecutor(Clock()), budget_bytes=10, max_active=1, check_every=10,
                       max_iters=1000, rtol=1e-6, idle_sleep=0.0)
     assert "consensus" not in dir(plain.ex)
+
+
+def test_certified_stopping_on_the_duality_gap():
+    """With an executor that reports a duality gap (F - D) / D, a solve stops
+    at the first check where the gap is at most gtol, whatever its objective
+    change, and a gap that never closes runs to the cap."""
+    clk = Clock()
+
+    class Gap(FakeExecutor):
+        def objective(self, h):
+            return 1.0                      # the change rule alone would stop at once
+
+        def gap(self, h):
+            return 0.5 ** (h["iters"] / 10.0)
+
+    sch = Scheduler(Gap(clk), budget_bytes=10, max_active=1, check_every=10, max_iters=1000,
+                    rtol=1e-2, clock=clk, idle_sleep=0.0, gtol=1e-4)
+    res = sch.run(_jobs([1]))
+    # 0.5^(k/10) <= 1e-4 first at k = 140
+    assert res[0].iters == 140 and res[0].status == "ok"
+
+    class Open(Gap):
+        def gap(self, h):
+            return math.inf                 # D <= 0: nothing certified
+
+    capped = Scheduler(Open(Clock()), 10, 1, 10, 50, 1e-2, idle_sleep=0.0).run(_jobs([1]))[0]
+    assert capped.iters == 50 and capped.status == "max_iters"
+
+
+def test_request_rho_rule():
+    from types import SimpleNamespace as NS
+    from paper_1409_0940_amd.serving import request_rho
+    assert request_rho(NS(loss="hinge", m=1, n=10000, lam=1e-4)) == pytest.approx(1.0)
+    assert request_rho(NS(loss="hinge", m=10, n=10000, lam=1e-4)) == pytest.approx(2.0)
+    assert request_rho(NS(loss="squared", m=1, n=40000, lam=1e-2)) == pytest.approx(40.0)
