@@ -446,7 +446,8 @@ zw_f32_lds_kernel(const float* __restrict__ Zg, int64_t ldz, int64_t n, int R, i
 // ---------------------------------------------------------------------------
 // Gram tile of one block: slot[a][b] tile = I + Z_b^T Z_b restricted to the
 // 64 x 64 tile (ta, tb), ta >= tb.  The 4 waves take interleaved groups of 4
-// rows and their partial sums are added in wave order through LDS.
+// rows and their partial sums are added in wave order through LDS.  Tiles in
+// the XCD-aware super-tile order of gram_bf16_kernel (below).
 // ---------------------------------------------------------------------------
 template <typename ZT>
 __global__ void __launch_bounds__(256)
@@ -457,12 +458,15 @@ gram_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
   __shared__ acc_t red[64 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
-  // tile index -> (ta, tb), ta >= tb
-  const int64_t t = blockIdx.x;
-  int64_t ta = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
-  while (ta * (ta + 1) / 2 > t) --ta;
-  const int64_t tb = t - ta * (ta + 1) / 2;
+  // slot -> super-tile (sa, sb), sa >= sb, and tile (ta, tb) inside it
+  const int64_t L = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int64_t q = L / 64, u = L % 64;
+  int64_t sa = (int64_t)((__builtin_sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+  while ((sa + 1) * (sa + 2) / 2 <= q) ++sa;
+  while (sa * (sa + 1) / 2 > q) --sa;
+  const int64_t sb = q - sa * (sa + 1) / 2;
+  const int64_t ta = 8 * sa + u / 8, tb = 8 * sb + u % 8;
+  if (tb > ta || 64 * ta >= sj) return;  // whole workgroup, before any barrier
   const int64_t fa = 64 * ta + 4 * fr, fb = 64 * tb + 4 * fr;  // block-local features
 
   accv acc[4][4];
@@ -1330,6 +1334,12 @@ static void ztr_bf16_dispatch(const void* Z, int64_t ldz, int64_t rows, int64_t 
 // an instruction is then the 32 rows of the step and instruction (qa, qb)
 // accumulates G[4 m + qa][4 n + qb], m, n < 16.  The 4 waves take interleaved
 // steps; their partial sums are added in wave order through LDS.
+// Tile order: the grid has 64 slots per super-tile of 8 x 8 tiles of the
+// lower triangle (slots above the diagonal or past the edge exit at once),
+// and each XCD takes a contiguous range of slots, so the workgroups resident
+// on an XCD read the 16 feature strips of about one super-tile and its L2
+// serves their re-reads (tiles in plain triangle order spread the strips
+// over all XCDs and re-read Z from beyond L2 about 30 times).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 gram_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
@@ -1337,11 +1347,14 @@ gram_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int6
   __shared__ float red[64 * 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int fr = lane & 15, fg = lane >> 4;
-  const int64_t t = blockIdx.x;
-  int64_t ta = (int64_t)((__builtin_sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while ((ta + 1) * (ta + 2) / 2 <= t) ++ta;
-  while (ta * (ta + 1) / 2 > t) --ta;
-  const int64_t tb = t - ta * (ta + 1) / 2;
+  const int64_t L = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int64_t q = L / 64, u = L % 64;
+  int64_t sa = (int64_t)((__builtin_sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+  while ((sa + 1) * (sa + 2) / 2 <= q) ++sa;
+  while (sa * (sa + 1) / 2 > q) --sa;
+  const int64_t sb = q - sa * (sa + 1) / 2;
+  const int64_t ta = 8 * sa + u / 8, tb = 8 * sb + u % 8;
+  if (tb > ta || 64 * ta >= sj) return;  // whole workgroup, before any barrier
   const int64_t fa = 64 * ta + 4 * fr, fb = 64 * tb + 4 * fr;  // block-local features
   // features at or past s_j read as zero: mask of the 4 packed halves
   auto keep = [&](int64_t f0) -> uint2 {
@@ -1361,8 +1374,9 @@ gram_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int6
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t r0 = 32 * wave; r0 < rows; r0 += 128) {
-    uint2 za[8], zb[8];
+  // a step is 32 rows of this wave (rows r0 + 8 fg + 0..7 per lane); the
+  // next step's rows are loaded while this step's products run
+  auto load_step = [&](int64_t r0, uint2* za, uint2* zb) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int64_t r = r0 + 8 * fg + i;
@@ -1374,6 +1388,12 @@ gram_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int6
       za[i] = uint2{a.x & ka.x, a.y & ka.y};
       zb[i] = uint2{b.x & kb.x, b.y & kb.y};
     }
+  };
+  uint2 za[8], zb[8];
+  load_step(32 * wave, za, zb);
+  for (int64_t r0 = 32 * wave; r0 < rows; r0 += 128) {
+    uint2 na[8], nb[8];
+    load_step(r0 + 128, na, nb);   // rows past the end load as zero
     u32x4 a[4], b[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
@@ -1390,6 +1410,11 @@ gram_bf16_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int6
     for (int qa = 0; qa < 4; ++qa)
 #pragma unroll
       for (int qb = 0; qb < 4; ++qb) acc[qa][qb] = mfma_bf16x8(a[qa], b[qb], acc[qa][qb]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      za[i] = na[i];
+      zb[i] = nb[i];
+    }
   }
   // element (m = acc_row(fg, r), n = fr) of instruction (qa, qb) is
   // G[64 ta + 4 m + qa][64 tb + 4 n + qb]; local index (4 m + qa, 4 n + qb)
@@ -1610,8 +1635,9 @@ hipError_t zw(int prec, const void* Z, int64_t ldz, int64_t n, int R, int i0, in
 
 hipError_t gram(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t coff, int64_t sj,
                 double* slot, int64_t S, hipStream_t st) {
-  const int64_t T = (sj + 63) / 64;
-  dim3 g((unsigned)(T * (T + 1) / 2));
+  // 64 workgroup slots per super-tile of 8 x 8 tiles of the lower triangle
+  const int64_t T = (sj + 63) / 64, ST = (T + 7) / 8;
+  const dim3 g((unsigned)(ST * (ST + 1) / 2 * 64));
   if (prec == BS_PREC_F64)
     gram_kernel<double><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, coff, sj, slot, S);
   else if (prec == BS_PREC_BF16 && ldz % 4 == 0 && coff % 4 == 0 &&
