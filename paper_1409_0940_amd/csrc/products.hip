@@ -983,6 +983,126 @@ ztr_bf16x3_dma_kernel(const float* __restrict__ Z, int64_t ldz, int64_t rows, in
 }
 
 // ---------------------------------------------------------------------------
+// BF16 Gram for large blocks: 128 x 128 output tiles (features fa0, fb0 of
+// the lower triangle), one 64 x 64 quadrant per wave, every wave over all
+// rows.  Each step of 32 rows stages the rows' 128 + 128 features (16 KB)
+// in LDS once for the 4 waves, double-buffered (next step loaded from
+// global while this step's products run), so a row segment moves from L2 once
+// per 128 x 128 tile instead of once per wave and 64 x 64 tile.  Staged rows
+// have a pitch of 272 bytes: the two 16-lane halves of a fragment read (rows
+// 8 apart) fall in disjoint banks, and a 16-lane staging store writes one
+// row's 256 contiguous bytes.  Fragments are read and transposed exactly as in
+// gram_bf16_kernel.  Tiles in super-tiles of 4 x 4 tiles, XCD-aware.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+gram_bf16_wide_kernel(const uint16_t* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
+                      int64_t sj, double* __restrict__ slot, int64_t S) {
+  constexpr int PITCH = 272, MAT = 32 * PITCH, BUF = 2 * MAT;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int wa = wave >> 1, wb = wave & 1;
+  const int64_t L = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const int64_t q = L / 16, u = L % 16;
+  int64_t sa = (int64_t)((__builtin_sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+  while ((sa + 1) * (sa + 2) / 2 <= q) ++sa;
+  while (sa * (sa + 1) / 2 > q) --sa;
+  const int64_t sb = q - sa * (sa + 1) / 2;
+  const int64_t ta = 4 * sa + u / 4, tb = 4 * sb + u % 4;
+  if (tb > ta || 128 * ta >= sj) return;  // whole workgroup, before any barrier
+  const int64_t fa0 = 128 * ta, fb0 = 128 * tb;
+
+  // staging: segment v = tid + 256 k (k < 4) is matrix v / 512 (A, B), row
+  // (v % 512) / 16 of the step, 16-byte segment v % 16 (8 features)
+  int64_t gofs[4];
+  int lofs[4];
+  uint4 keepm[4];
+  bool live[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int v = tid + 256 * k, mat = v / 512, row = (v % 512) / 16, seg = v % 16;
+    const int64_t f = (mat ? fb0 : fa0) + 8 * seg;
+    live[k] = f < sj;
+    gofs[k] = (int64_t)row * ldz + coff + (live[k] ? f : 0);
+    lofs[k] = mat * MAT + row * PITCH + 16 * seg;
+    unsigned m[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+      m[h] = (f + 2 * h < sj ? 0x0000ffffu : 0u) | (f + 2 * h + 1 < sj ? 0xffff0000u : 0u);
+    keepm[k] = uint4{m[0], m[1], m[2], m[3]};
+  }
+  auto fetch = [&](int64_t r0, uint4* stg) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int row = ((tid + 256 * k) % 512) / 16;
+      uint4 v = uint4{0u, 0u, 0u, 0u};
+      if (live[k] && r0 + row < rows)
+        v = *reinterpret_cast<const uint4*>(Z + r0 * ldz + gofs[k]);
+      stg[k] = uint4{v.x & keepm[k].x, v.y & keepm[k].y, v.z & keepm[k].z, v.w & keepm[k].w};
+    }
+  };
+  auto stage = [&](int buf, const uint4* stg) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) *reinterpret_cast<uint4*>(&lds[buf * BUF + lofs[k]]) = stg[k];
+  };
+
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  uint4 stg[4];
+  fetch(0, stg);
+  stage(0, stg);
+  __syncthreads();
+  const int aofs = (8 * fg) * PITCH + 128 * wa + 8 * fr;
+  const int bofs = MAT + (8 * fg) * PITCH + 128 * wb + 8 * fr;
+  for (int64_t r0 = 0; r0 < rows; r0 += 32) {
+    const int buf = (int)((r0 >> 5) & 1);
+    const bool more = r0 + 32 < rows;
+    if (more) fetch(r0 + 32, stg);
+    uint2 za[8], zb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      za[i] = *reinterpret_cast<const uint2*>(&lds[buf * BUF + aofs + i * PITCH]);
+      zb[i] = *reinterpret_cast<const uint2*>(&lds[buf * BUF + bofs + i * PITCH]);
+    }
+    u32x4 a[4], b[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      a[0][h] = __builtin_amdgcn_perm(za[2 * h + 1].x, za[2 * h].x, 0x05040100u);
+      a[1][h] = __builtin_amdgcn_perm(za[2 * h + 1].x, za[2 * h].x, 0x07060302u);
+      a[2][h] = __builtin_amdgcn_perm(za[2 * h + 1].y, za[2 * h].y, 0x05040100u);
+      a[3][h] = __builtin_amdgcn_perm(za[2 * h + 1].y, za[2 * h].y, 0x07060302u);
+      b[0][h] = __builtin_amdgcn_perm(zb[2 * h + 1].x, zb[2 * h].x, 0x05040100u);
+      b[1][h] = __builtin_amdgcn_perm(zb[2 * h + 1].x, zb[2 * h].x, 0x07060302u);
+      b[2][h] = __builtin_amdgcn_perm(zb[2 * h + 1].y, zb[2 * h].y, 0x05040100u);
+      b[3][h] = __builtin_amdgcn_perm(zb[2 * h + 1].y, zb[2 * h].y, 0x07060302u);
+    }
+#pragma unroll
+    for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb) acc[qa][qb] = mfma_bf16x8(a[qa], b[qb], acc[qa][qb]);
+    if (more) stage(buf ^ 1, stg);
+    __syncthreads();
+  }
+  // element (m = acc_row(fg, r), n = fr) of instruction (qa, qb) is
+  // G[fa0 + 64 wa + 4 m + qa][fb0 + 64 wb + 4 n + qb]
+#pragma unroll
+  for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = fa0 + 64 * wa + 4 * acc_row<float>(fg, r) + qa;
+        const int64_t gj = fb0 + 64 * wb + 4 * fr + qb;
+        if (gi < sj && gj < sj)
+          slot[gi * S + gj] = (double)acc[qa][qb][r] + (gi == gj ? 1.0 : 0.0);
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Forward products from a BF16 Z for many output columns: the W' planes of a
 // 32-feature stage (2 x NC columns x 64 B) are loaded once per workgroup into
 // LDS (row pitch 80 B: the 16 columns a fragment read touches fall in
@@ -1640,8 +1760,16 @@ hipError_t gram(int prec, const void* Z, int64_t ldz, int64_t rows, int64_t coff
   const dim3 g((unsigned)(ST * (ST + 1) / 2 * 64));
   if (prec == BS_PREC_F64)
     gram_kernel<double><<<g, 256, 0, st>>>((const double*)Z, ldz, rows, coff, sj, slot, S);
-  else if (prec == BS_PREC_BF16 && ldz % 4 == 0 && coff % 4 == 0 &&
-           reinterpret_cast<uintptr_t>(Z) % 8 == 0)
+  else if (prec == BS_PREC_BF16 && T >= 64 && ldz % 8 == 0 && coff % 8 == 0 &&
+           reinterpret_cast<uintptr_t>(Z) % 16 == 0) {
+    // large blocks (s_j > 4032): 128 x 128 tiles, 16 slots per super-tile
+    // of 4 x 4 tiles; smaller ones keep 64 x 64 tiles with the rows split
+    // over the waves, which fills the chip with more workgroups
+    const int64_t T2 = (sj + 127) / 128, ST2 = (T2 + 3) / 4;
+    gram_bf16_wide_kernel<<<dim3((unsigned)(ST2 * (ST2 + 1) / 2 * 16)), 256, 0, st>>>(
+        (const uint16_t*)Z, ldz, rows, coff, sj, slot, S);
+  } else if (prec == BS_PREC_BF16 && ldz % 4 == 0 && coff % 4 == 0 &&
+             reinterpret_cast<uintptr_t>(Z) % 8 == 0)
     gram_bf16_kernel<<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, coff, sj, slot, S);
   else if (prec == BS_PREC_BF16)
     gram_kernel<uint16_t><<<g, 256, 0, st>>>((const uint16_t*)Z, ldz, rows, coff, sj, slot, S);

@@ -97,6 +97,10 @@ GRAM_CASES = [
     ("ragged_2x3", "digits", 5003, 64, 530, 10, 2, 3),
     ("aligned_3x2", "digits", 4099, 784, 1024, 5, 3, 2),
     ("one_tile_1x4", "speech_pm1", 777, 440, 256, 3, 1, 4),
+    # s_j > 4032: the 128 x 128 tile kernel, ragged (4133 = 32 * 128 + 37,
+    # 3001 rows: a partial 32-row step) and aligned (4096)
+    ("wide_ragged_1x2", "digits", 3001, 64, 8266, 4, 1, 2),
+    ("wide_aligned_2x1", "speech_pm1", 1500, 440, 4096, 3, 2, 1),
 ]
 
 
