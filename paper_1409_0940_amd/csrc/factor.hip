@@ -5,7 +5,8 @@
 // W'_ij = Q_ij rhs_ij becomes one batched FP64 product with no sequential
 // triangular sweeps, and its cost (2 s_j^2 m flops, s_j^2 doubles streamed)
 // is the same as two triangular solves.  Setup, per matrix A = I + G:
-//   1. blocked right-looking Cholesky A = L L^T (64 x 64 tiles),
+//   1. blocked Cholesky A = L L^T (64 x 64 tiles; trailing updates applied
+//      per panel of 4 tile columns),
 //   2. X = L^{-1} by recursive doubling over tile blocks
 //      (X_CA = -X_CC L_CA X_AA for sibling blocks A, C),
 //   3. Q = X^T X, written as a full symmetric matrix.
@@ -35,6 +36,26 @@ __device__ __forceinline__ void load_tile(tile_t& dst, const double* __restrict_
       dst[c][r] = v;
     else
       dst[r][c] = v;
+  }
+}
+
+// The same load split in two, so that the global loads of the next tile
+// product can be issued before the current one's MFMAs: thread t holds
+// elements (t / 64 + 4 i, t % 64), i < 16, in registers.
+__device__ __forceinline__ void fetch_tile(double (&r)[16], const double* __restrict__ src,
+                                           int64_t ld) {
+  const int row = threadIdx.x >> 6, c = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) r[i] = src[(int64_t)(row + 4 * i) * ld + c];
+}
+__device__ __forceinline__ void put_tile(tile_t& dst, const double (&r)[16], bool transpose) {
+  const int row = threadIdx.x >> 6, c = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (transpose)
+      dst[c][row + 4 * i] = r[i];
+    else
+      dst[row + 4 * i][c] = r[i];
   }
 }
 
@@ -155,9 +176,37 @@ trsm_kernel(double* __restrict__ slots, int64_t S, int kb, const double* __restr
   for_acc(acc, [&](int r, int c, double v) { T[r * S + c] = v; });
 }
 
-// Trailing update: A[ib][jb] -= L[ib][kb] L[jb][kb]^T for kb < jb <= ib.
+// Trailing updates in panels of PW tile columns (left-looking inside the
+// panel, right-looking across panels): after column kb of the panel
+// [K, K + PW) is factored, only the panel's later columns take its update
+// (syrk_panel_kernel); the columns past the panel take the updates of all
+// PW columns at once (syrk_multi_kernel), so each of their tiles is read
+// and written once per panel instead of once per column.
+constexpr int PW = 4;
+
+// A[ib][jb] -= L[ib][kb] L[jb][kb]^T for kb < jb < jend, jb <= ib < nblk;
+// grid (rows below kb, panel columns after kb, matrices).
 __global__ void __launch_bounds__(256)
-syrk_kernel(double* __restrict__ slots, int64_t S, int kb) {
+syrk_panel_kernel(double* __restrict__ slots, int64_t S, int kb, int jend) {
+  __shared__ tile_t At;
+  __shared__ tile_t Bt;
+  const int64_t ib = kb + 1 + blockIdx.x, jb = kb + 1 + blockIdx.y;
+  if (ib < jb || jb >= jend) return;  // whole workgroup
+  double* base = slots + (int64_t)blockIdx.z * S * S;
+  load_tile(At, base + ib * NB * S + (int64_t)kb * NB, S, false);
+  load_tile(Bt, base + jb * NB * S + (int64_t)kb * NB, S, false);
+  __syncthreads();
+  v4d acc[2][2];
+  zero_acc(acc);
+  tile_mma_nt(acc, At, Bt);
+  double* T = base + ib * NB * S + jb * NB;
+  for_acc(acc, [&](int r, int c, double v) { T[r * S + c] -= v; });
+}
+
+// A[ib][jb] -= sum_{k = K}^{K + nk - 1} L[ib][k] L[jb][k]^T for
+// K + nk <= jb <= ib; grid (triangle of the trailing tiles, matrices).
+__global__ void __launch_bounds__(256)
+syrk_multi_kernel(double* __restrict__ slots, int64_t S, int K, int nk) {
   __shared__ tile_t At;
   __shared__ tile_t Bt;
   const int64_t t = blockIdx.x;
@@ -165,14 +214,24 @@ syrk_kernel(double* __restrict__ slots, int64_t S, int kb) {
   while ((a + 1) * (a + 2) / 2 <= t) ++a;
   while (a * (a + 1) / 2 > t) --a;
   const int64_t b = t - a * (a + 1) / 2;
-  const int64_t ib = kb + 1 + a, jb = kb + 1 + b;
+  const int64_t ib = K + nk + a, jb = K + nk + b;
   double* base = slots + (int64_t)blockIdx.y * S * S;
-  load_tile(At, base + ib * NB * S + (int64_t)kb * NB, S, false);
-  load_tile(Bt, base + jb * NB * S + (int64_t)kb * NB, S, false);
-  __syncthreads();
   v4d acc[2][2];
   zero_acc(acc);
-  tile_mma_nt(acc, At, Bt);
+  double ra[16], rb[16];
+  fetch_tile(ra, base + ib * NB * S + (int64_t)K * NB, S);
+  fetch_tile(rb, base + jb * NB * S + (int64_t)K * NB, S);
+  for (int k = K; k < K + nk; ++k) {
+    put_tile(At, ra, false);
+    put_tile(Bt, rb, false);
+    __syncthreads();
+    if (k + 1 < K + nk) {
+      fetch_tile(ra, base + ib * NB * S + (int64_t)(k + 1) * NB, S);
+      fetch_tile(rb, base + jb * NB * S + (int64_t)(k + 1) * NB, S);
+    }
+    tile_mma_nt(acc, At, Bt);
+    __syncthreads();
+  }
   double* T = base + ib * NB * S + jb * NB;
   for_acc(acc, [&](int r, int c, double v) { T[r * S + c] -= v; });
 }
@@ -220,10 +279,17 @@ trinv_y_kernel(const double* __restrict__ slots, int64_t S, int b, double* __res
   double* Xb = work + (int64_t)blockIdx.y * S * S;
   v4d acc[2][2];
   zero_acc(acc);
+  double ra[16], rb[16];
+  fetch_tile(ra, Lb + (C0 + c) * NB * S + (A0 + a) * NB, S);
+  fetch_tile(rb, Xb + (A0 + a) * NB * S + (A0 + a) * NB, S);
   for (int j = a; j < b; ++j) {
-    load_tile(At, Lb + (C0 + c) * NB * S + (A0 + j) * NB, S, false);
-    load_tile(Bt, Xb + (A0 + j) * NB * S + (A0 + a) * NB, S, true);
+    put_tile(At, ra, false);
+    put_tile(Bt, rb, true);
     __syncthreads();
+    if (j + 1 < b) {
+      fetch_tile(ra, Lb + (C0 + c) * NB * S + (A0 + j + 1) * NB, S);
+      fetch_tile(rb, Xb + (A0 + j + 1) * NB * S + (A0 + a) * NB, S);
+    }
     tile_mma_nt(acc, At, Bt);
     __syncthreads();
   }
@@ -242,10 +308,17 @@ trinv_x_kernel(int64_t S, int b, double* __restrict__ work) {
   double* Xb = work + (int64_t)blockIdx.y * S * S;
   v4d acc[2][2];
   zero_acc(acc);
+  double ra[16], rb[16];
+  fetch_tile(ra, Xb + (C0 + c) * NB * S + C0 * NB, S);
+  fetch_tile(rb, Xb + (A0 + a) * NB * S + C0 * NB, S);
   for (int j = 0; j <= c; ++j) {
-    load_tile(At, Xb + (C0 + c) * NB * S + (C0 + j) * NB, S, false);
-    load_tile(Bt, Xb + (A0 + a) * NB * S + (C0 + j) * NB, S, true);
+    put_tile(At, ra, false);
+    put_tile(Bt, rb, true);
     __syncthreads();
+    if (j + 1 <= c) {
+      fetch_tile(ra, Xb + (C0 + c) * NB * S + (C0 + j + 1) * NB, S);
+      fetch_tile(rb, Xb + (A0 + a) * NB * S + (C0 + j + 1) * NB, S);
+    }
     tile_mma_nt(acc, At, Bt);
     __syncthreads();
   }
@@ -268,10 +341,17 @@ xtx_kernel(const double* __restrict__ work, int64_t S, double* __restrict__ slot
   double* Qb = slots + (int64_t)blockIdx.y * S * S;
   v4d acc[2][2];
   zero_acc(acc);
+  double ra[16], rb[16];
+  fetch_tile(ra, Xb + a * NB * S + a * NB, S);
+  fetch_tile(rb, Xb + a * NB * S + b * NB, S);
   for (int64_t c = a; c < nblk; ++c) {
-    load_tile(At, Xb + c * NB * S + a * NB, S, true);
-    load_tile(Bt, Xb + c * NB * S + b * NB, S, true);
+    put_tile(At, ra, true);
+    put_tile(Bt, rb, true);
     __syncthreads();
+    if (c + 1 < nblk) {
+      fetch_tile(ra, Xb + (c + 1) * NB * S + a * NB, S);
+      fetch_tile(rb, Xb + (c + 1) * NB * S + b * NB, S);
+    }
     tile_mma_nt(acc, At, Bt);
     __syncthreads();
   }
@@ -559,13 +639,20 @@ hipError_t identity_pad(double* slots, int batch, int64_t S, const int64_t* sj_h
 hipError_t spd_inverse(double* slots, int batch, int64_t S, double* work, double* dinv, int* flag,
                        hipStream_t st) {
   const int nblk = (int)(S / NB);
-  for (int kb = 0; kb < nblk; ++kb) {
-    potrf_diag_kernel<<<batch, 256, 0, st>>>(slots, S, kb, dinv, flag);
-    const int T = nblk - kb - 1;
-    if (T > 0) {
-      trsm_kernel<<<dim3(T, batch), 256, 0, st>>>(slots, S, kb, dinv);
-      syrk_kernel<<<dim3(T * (T + 1) / 2, batch), 256, 0, st>>>(slots, S, kb);
+  for (int K = 0; K < nblk; K += PW) {
+    const int jend = std::min(nblk, K + PW);
+    for (int kb = K; kb < jend; ++kb) {
+      potrf_diag_kernel<<<batch, 256, 0, st>>>(slots, S, kb, dinv, flag);
+      const int T = nblk - kb - 1;
+      if (T > 0) {
+        trsm_kernel<<<dim3(T, batch), 256, 0, st>>>(slots, S, kb, dinv);
+        if (jend - kb - 1 > 0)
+          syrk_panel_kernel<<<dim3(T, jend - kb - 1, batch), 256, 0, st>>>(slots, S, kb, jend);
+      }
     }
+    const int T2 = nblk - jend;
+    if (T2 > 0)
+      syrk_multi_kernel<<<dim3(T2 * (T2 + 1) / 2, batch), 256, 0, st>>>(slots, S, K, jend - K);
   }
   trinv_diag_kernel<<<dim3(nblk, batch), 256, 0, st>>>(dinv, S, work);
   for (int b = 1; b < nblk; b *= 2) {
