@@ -6,9 +6,10 @@ step), so both the FP64 oracle and the HIP path can consume its output without
 sharing any computation.
 
 Canonical inputs are float32 arrays.  Bulk matrices are drawn in fixed-size
-row chunks, each from its own ``SeedSequence.spawn`` child stream, so any row
-range can be regenerated alone and the result does not depend on how many
-rows are requested at once.
+row chunks (65536 rows), each from its own ``SeedSequence.spawn`` child
+stream, so the full chunks of a draw do not depend on how many rows are
+requested; a partial last chunk draws fewer numbers and differs from the
+leading rows of that chunk in a larger draw.
 
 Workloads (the paper's experimental section describes MNIST, 784 pixel
 features and 10 classes, and TIMIT, 440 features and 147 phoneme classes;
@@ -166,8 +167,9 @@ def digits_2m() -> Workload:
 def make_inputs(w: Workload, n: int | None = None):
     """Draw (X, Y, W, b) float32 for a workload; ``n`` overrides the row count.
 
-    Rows are chunk-seeded, so a smaller ``n`` returns exactly the leading rows
-    of the full-size draw.
+    Rows are chunk-seeded: with ``n`` a multiple of 65536 a smaller ``n``
+    returns exactly the leading rows of the full-size draw (a partial last
+    chunk differs).
     """
     n = w.n if n is None else n
     if w.d in (16, 64) and w.extra.get("gen", "sine") == "sine":
