@@ -46,6 +46,8 @@ class Result:
     objective: float
     coef: object = None          # host numpy array (s x m)
     status: str = "ok"
+    gap: float = math.nan        # certified relative objective error bound at the stop
+                                 # (inf: not certified; nan: the executor reports none)
 
     @property
     def latency_s(self):
@@ -145,13 +147,15 @@ class Scheduler:
                 slot.checks.append(obj)
                 conv = self._converged(slot, obj)
                 if conv or slot.iters >= self.max_iters:
+                    gapf = getattr(self.ex, "gap", None)
+                    gap = gapf(slot.handle) if gapf is not None else math.nan
                     coef = self.ex.finish(slot.handle)
                     active.remove(slot)
                     self.used -= slot.job.footprint
                     tf = now()
                     results[slot.job.rid] = Result(slot.job.rid, slot.job.arrival_s * time_scale,
                                                    slot.admitted_s, tf, slot.iters, obj, coef,
-                                                   "ok" if conv else "max_iters")
+                                                   "ok" if conv else "max_iters", gap)
                     self.trace.append((tf, "finish", slot.job.rid, self.used))
                 else:
                     slot.prev_obj = obj
@@ -187,9 +191,17 @@ def latency_summary(results, wall_s):
     wait = [r.admitted_s - r.arrival_s for r in ok]
     service = [r.finished_s - r.admitted_s for r in ok]
     iters = sum(r.iters for r in ok)
+    gaps_ok = [r.gap for r in ok if r.status == "ok" and math.isfinite(r.gap)]
+    gaps_cap = sorted(r.gap for r in ok if r.status == "max_iters" and math.isfinite(r.gap))
     return {"requests": len(results), "served": len(ok),
             "rejected": len(results) - len(ok),
             "stopped_at_iteration_cap": sum(1 for r in ok if r.status == "max_iters"),
+            # certified bound on the relative objective error of each served model
+            "certified_gap_max": max(gaps_ok) if gaps_ok else math.nan,
+            "capped_gap_median": gaps_cap[len(gaps_cap) // 2] if gaps_cap else math.nan,
+            "capped_gap_max": gaps_cap[-1] if gaps_cap else math.nan,
+            "capped_without_bound": sum(1 for r in ok if r.status == "max_iters"
+                                        and not math.isfinite(r.gap)),
             "p50_ms": 1e3 * pct(50), "p99_ms": 1e3 * pct(99), "max_ms": 1e3 * (lat[-1] if lat else math.nan),
             # latency = queue wait (arrival to admission) + service (admission to result)
             "wait_p50_ms": 1e3 * pct_of(wait, 50), "wait_p99_ms": 1e3 * pct_of(wait, 99),

@@ -193,3 +193,15 @@ def test_request_rho_rule():
     assert request_rho(NS(loss="hinge", m=1, n=10000, lam=1e-4)) == pytest.approx(1.0)
     assert request_rho(NS(loss="hinge", m=10, n=10000, lam=1e-4)) == pytest.approx(2.0)
     assert request_rho(NS(loss="squared", m=1, n=40000, lam=1e-2)) == pytest.approx(40.0)
+
+
+def test_summary_reports_certified_gaps():
+    from paper_1409_0940_amd.serving import Result
+    res = {0: Result(0, 0.0, 0.0, 1.0, 50, 1.0, None, "ok", 8e-5),
+           1: Result(1, 0.0, 0.0, 1.0, 20, 1.0, None, "ok", 3e-5),
+           2: Result(2, 0.0, 0.0, 2.0, 300, 1.0, None, "max_iters", 4e-3),
+           3: Result(3, 0.0, 0.0, 2.0, 300, 1.0, None, "max_iters", math.inf)}
+    s = latency_summary(res, 2.0)
+    assert s["certified_gap_max"] == pytest.approx(8e-5)
+    assert s["capped_gap_max"] == pytest.approx(4e-3)
+    assert s["capped_without_bound"] == 1 and s["stopped_at_iteration_cap"] == 2
