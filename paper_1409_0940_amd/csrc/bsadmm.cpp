@@ -81,12 +81,12 @@ struct Plan {
          b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0, b_prev = 0;
   // refined BF16: feature defects (BF16) and FP32-faithful features of a
   // row-block group, and the stored defects of the two products
-  size_t b_wsd = 0, b_wsf = 0, b_ca = 0, b_cp = 0;
+  size_t b_wsd = 0, b_ca = 0, b_cp = 0;
   // operand elements between the W' copies of consecutive row blocks
   int64_t wop_stride() const { return bs::bf16_planes(prec, mp) ? 2 * mp * spad : spad * mp; }
   size_t total() const {
     return b_xp + b_wt + b_bias + b_q + b_ws + 5 * b_row + b_rop + 3 * b_col + 4 * b_colR + b_wop +
-           b_part + b_small + b_fac_tmp + b_prev + b_wsd + b_wsf + b_ca + b_cp;
+           b_part + b_small + b_fac_tmp + b_prev + b_wsd + b_ca + b_cp;
   }
 };
 
@@ -159,7 +159,8 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.S = rup(smax, 64);
   // Row-block groups for the Z workspace (one group of all rows when Z is kept).
   L.keep = p->z_mode == BSADMM_Z_KEEP;
-  const size_t row_bytes = (size_t)L.spad * (L.refine ? 8 : L.zb);
+  // refined BF16 keeps the BF16 features and their defect (2 + 2 bytes)
+  const size_t row_bytes = (size_t)L.spad * (L.refine ? 4 : L.zb);
   if (L.keep && p->workspace_bytes && p->workspace_bytes < (size_t)L.n * row_bytes)
     return fail(BSADMM_ENOMEM, "BSADMM_Z_KEEP needs " + std::to_string((size_t)L.n * row_bytes) +
                                    " B of workspace, workspace_bytes is smaller");
@@ -196,10 +197,9 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   L.b_q = (size_t)L.R * L.C * slot;
   L.b_ws = (size_t)L.ws_rows * L.spad * L.zb;
   if (L.refine) {
+    // the defect of the workspace's (or the kept) BF16 features; the
+    // FP32-faithful features it comes from are never stored
     L.b_wsd = (size_t)L.ws_rows * L.spad * 2;
-    // a kept Z keeps its defect too; the FP32-faithful features are then
-    // needed at setup only (a temporary there)
-    L.b_wsf = L.keep ? 0 : (size_t)L.ws_rows * L.spad * 4;
     L.b_ca = (size_t)L.R * L.spad * L.mp * 8;
     L.b_cp = (size_t)L.n * L.mp * 8;
   }
@@ -231,7 +231,7 @@ struct bsadmm_handle {
   std::vector<void*> allocs;
   void *Xp = nullptr, *Wt = nullptr, *bias = nullptr, *Z = nullptr, *Rop = nullptr,
        *Wop = nullptr, *part = nullptr;
-  void *Zd = nullptr, *Zf = nullptr;  // refined BF16: feature defect, FP32-faithful features
+  void* Zd = nullptr;  // refined BF16: feature defect bf16(Zf - Z) of the workspace rows
   double *cA = nullptr, *cP = nullptr;  // refined BF16: stored product defects
   double* dualA = nullptr;  // refined BF16 dual bound: defect part of Z^T alpha (lazy)
   double *Q = nullptr, *O = nullptr, *Obar = nullptr, *nu = nullptr, *Dbar = nullptr,
@@ -298,16 +298,22 @@ hipError_t regen_group(bsadmm_handle* h, int i0, int i1, hipStream_t s) {
   return regen_group(h, i0, i1, s, h->L.prec, h->Z, h->L.zb);
 }
 
-// Refined BF16: FP32-faithful features of the group into `zf`, and the
-// defect bf16(Zf - Z) of the group's BF16 features into Zd.
-hipError_t defect_group(bsadmm_handle* h, int i0, int i1, hipStream_t s, void* zf) {
+// Refined BF16: the FP32-faithful (BF16X3) features of the group, formed in
+// the regeneration kernel and not stored, and their defect bf16(Zf - Z)
+// against the group's BF16 features into Zd.
+hipError_t defect_group(bsadmm_handle* h, int i0, int i1, hipStream_t s) {
   const Plan& L = h->L;
-  hipError_t e = regen_group(h, i0, i1, s, BS_PREC_BF16X3, zf, 4);
-  const int64_t rows = L.rstart[i1] - L.rstart[i0];
-  if (e == hipSuccess)
-    e = bs::feature_defect((const float*)zf, (const uint16_t*)h->Z, (uint16_t*)h->Zd,
-                           rows * L.spad, s);
-  return e;
+  const int64_t r0 = L.rstart[i0], rows = L.rstart[i1] - r0;
+  const int64_t xps = L.n * L.Kp;
+  for (int j = 0; j < L.C; ++j) {
+    hipError_t e = bs::regen_defect(
+        (const char*)h->Xp + (size_t)r0 * L.Kp * L.op, xps, rows,
+        (const char*)h->Wt + (size_t)L.cstart[j] * L.Kp * L.op, L.s * L.Kp, L.sj[j],
+        (const char*)h->bias + (size_t)L.cstart[j] * 4, L.Kp, h->scale,
+        (const uint16_t*)h->Z + L.coff[j], (uint16_t*)h->Zd + L.coff[j], L.spad, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 struct PhaseTimer {
@@ -394,7 +400,7 @@ int objective_of(bsadmm_handle* h, const double* Wmodel, double* F) {
   for (size_t g = 0; g < L.groups.size() && e == hipSuccess; ++g) {
     const int i0 = L.groups[g].first, i1 = L.groups[g].second;
     if (!L.keep) e = regen_group(h, i0, i1, st);
-    if (e == hipSuccess && L.refine && !L.keep) e = defect_group(h, i0, i1, st, h->Zf);
+    if (e == hipSuccess && L.refine && !L.keep) e = defect_group(h, i0, i1, st);
     if (e == hipSuccess)
       e = bs::zw(L.prec, h->Z, L.spad, L.n, L.R, i0, i1, L.spad, wop, 0, L.mp, h->P, st);
     if (e == hipSuccess && L.refine)
@@ -460,7 +466,7 @@ int enqueue_dual_bound(bsadmm_handle* h, int loss, double* out) {
     const int i0 = g.first, i1 = g.second;
     if (!L.keep) HCHK(regen_group(h, i0, i1, st));
     if (L.refine) {
-      if (!L.keep) HCHK(defect_group(h, i0, i1, st, h->Zf));
+      if (!L.keep) HCHK(defect_group(h, i0, i1, st));
       HCHK(ztr_rows(h, i0, i1, h->Zd, st));
       HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
                           L.mp, nullptr, nullptr, nullptr, nullptr, h->dualA, st));
@@ -530,7 +536,7 @@ int enqueue_iteration(bsadmm_handle* h, hipStream_t s, bool check, bool refine, 
       // of both products, kept for the BF16 iterations until the next
       // refinement: cA_i = dZ_ij^T R_i, cP_i = sum_j dZ_ij W'_ij.
       begin();
-      if (!L.keep) HCHK(defect_group(h, i0, i1, st, h->Zf));
+      if (!L.keep) HCHK(defect_group(h, i0, i1, st));
       HCHK(ztr_group(h->Zd));
       HCHK(bs::reduce_rhs(L.prec, h->part, L.nsplit_max, L.n, L.R, i0, i1, L.split_rows, L.spad,
                           L.mp, nullptr, nullptr, nullptr, nullptr, h->cA, s));
@@ -743,7 +749,6 @@ int do_setup(bsadmm_handle* h) {
   ALLOC(h->part, L.b_part);
   if (L.refine) {
     ALLOC(h->Zd, L.b_wsd);
-    ALLOC(h->Zf, L.b_wsf);
     ALLOC(h->cA, L.b_ca);
     ALLOC(h->cP, L.b_cp);
   }
@@ -779,7 +784,6 @@ int do_setup(bsadmm_handle* h) {
   HCHK(hipMemsetAsync(h->Z, 0, L.b_ws, st));
   if (L.refine) {  // pad columns of the workspaces stay zero
     HCHK(hipMemsetAsync(h->Zd, 0, L.b_wsd, st));
-    if (L.b_wsf) HCHK(hipMemsetAsync(h->Zf, 0, L.b_wsf, st));
     HCHK(hipMemsetAsync(h->cA, 0, L.b_ca, st));
     HCHK(hipMemsetAsync(h->cP, 0, L.b_cp, st));
   }
@@ -819,24 +823,13 @@ int do_setup(bsadmm_handle* h) {
   const size_t slot = (size_t)L.S * L.S;
   // Refined BF16 builds the cache from its BF16 features, as plain BF16 does
   // (the refinement corrects the products through that same factor); a kept
-  // Z also keeps its defect, formed here with a temporary for the BF16X3
-  // features.
-  void* zf = h->Zf;
-  if (L.refine && L.keep) {
-    hipError_t e = hipMallocAsync(&zf, (size_t)L.ws_rows * L.spad * 4, st);
-    if (e != hipSuccess) return fail(BSADMM_ENOMEM, "device allocation failed for setup features");
-    e = hipMemsetAsync(zf, 0, (size_t)L.ws_rows * L.spad * 4, st);
-    if (e != hipSuccess) {
-      (void)hipFreeAsync(zf, st);
-      return hip_fail(e, "hipMemsetAsync");
-    }
-  }
+  // Z also keeps its defect, formed here.
   int grc = BSADMM_OK;
   for (const auto& g : L.groups) {
     const int i0 = g.first, i1 = g.second;
     const int64_t r0 = L.rstart[i0];
     hipError_t e = regen_group(h, i0, i1, st);
-    if (e == hipSuccess && L.refine && L.keep) e = defect_group(h, i0, i1, st, zf);
+    if (e == hipSuccess && L.refine && L.keep) e = defect_group(h, i0, i1, st);
     for (int i = i0; i < i1 && e == hipSuccess; ++i)
       for (int j = 0; j < L.C && e == hipSuccess; ++j)
         e = bs::gram(L.prec, (const char*)h->Z + (size_t)(L.rstart[i] - r0) * L.spad * L.zb,
@@ -847,7 +840,6 @@ int do_setup(bsadmm_handle* h) {
       break;
     }
   }
-  if (L.refine && L.keep) (void)hipFreeAsync(zf, st);
   if (grc) return grc;
   std::vector<int64_t> sjb((size_t)L.R * L.C);
   for (int i = 0; i < L.R; ++i)

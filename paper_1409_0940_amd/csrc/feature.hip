@@ -117,7 +117,8 @@ __global__ void __launch_bounds__(NTHREADS, regen_wgs<P>())
 regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t rows,
              const typename Prec<P>::op_t* __restrict__ Wt, int64_t wps, int64_t cols,
              const typename Prec<P>::acc_t* __restrict__ bias, int64_t Kp,
-             typename Prec<P>::acc_t scale, ZT* __restrict__ Z, int64_t ldz) {
+             typename Prec<P>::acc_t scale, ZT* __restrict__ Z, int64_t ldz,
+             const uint16_t* __restrict__ Zt, uint16_t* __restrict__ Zd) {
   using op_t = typename Prec<P>::op_t;
   using acc_t = typename Prec<P>::acc_t;
   using accv = typename Prec<P>::accv;
@@ -282,12 +283,15 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
   // non-temporal stores; straight from the MFMA layout a store instruction
   // writes 64 bytes into each of 4 rows.  The LDS is free once every wave
   // has passed the barrier below (the last chunk's products may follow the
-  // loop's last barrier).
+  // loop's last barrier).  With Zd (FP32-faithful features of refined BF16)
+  // the float values are not stored: the defect bf16(z - Zt) against the
+  // BF16 features Zt of the same elements goes to Zd instead.
   if constexpr (sizeof(ZT) == 4) {
     constexpr int ZP = BN + 4;                     // floats per staged row (528 B)
     static_assert(BM / 2 * ZP * 4 <= (int)sizeof(lds), "half a Z tile fits in the staging LDS");
     if (row0 + BM <= rows && col0 + BN <= cols && ldz % 4 == 0 &&
-        reinterpret_cast<uintptr_t>(Z) % 16 == 0) {
+        reinterpret_cast<uintptr_t>(Z) % 16 == 0 && reinterpret_cast<uintptr_t>(Zt) % 8 == 0 &&
+        reinterpret_cast<uintptr_t>(Zd) % 8 == 0) {
       float* zt = reinterpret_cast<float*>(&lds[0][0][0][0]);
       __syncthreads();
 #pragma unroll
@@ -312,8 +316,18 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
         for (int ps = 0; ps < BM / 2 / RPP; ++ps) {
           const int r = ps * RPP + tid / 32, sg = tid % 32;
           const v4f w = *reinterpret_cast<const v4f*>(zt + r * ZP + sg * 4);
-          __builtin_nontemporal_store(
-              w, reinterpret_cast<v4f*>(Z + (row0 + h * (BM / 2) + r) * ldz + col0 + sg * 4));
+          const int64_t off = (row0 + h * (BM / 2) + r) * ldz + col0 + sg * 4;
+          if (Zd) {
+            const uint2 t = *reinterpret_cast<const uint2*>(Zt + off);
+            uint2 o;
+            o.x = (uint32_t)f32_to_bf16(w[0] - bf16_to_f32((uint16_t)(t.x & 0xffffu))) |
+                  ((uint32_t)f32_to_bf16(w[1] - bf16_to_f32((uint16_t)(t.x >> 16))) << 16);
+            o.y = (uint32_t)f32_to_bf16(w[2] - bf16_to_f32((uint16_t)(t.y & 0xffffu))) |
+                  ((uint32_t)f32_to_bf16(w[3] - bf16_to_f32((uint16_t)(t.y >> 16))) << 16);
+            *reinterpret_cast<uint2*>(Zd + off) = o;
+          } else {
+            __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(Z + off));
+          }
         }
         __syncthreads();
       }
@@ -339,10 +353,16 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
             z = scale * rff_cos_bf16out(th);
           else
             z = scale * rff_cosf(th);
-          if constexpr (sizeof(ZT) == 2)
+          if constexpr (sizeof(ZT) == 2) {
             Z[row * ldz + col] = f32_to_bf16((float)z);
-          else
+          } else if constexpr (sizeof(ZT) == 4) {
+            if (Zd)
+              Zd[row * ldz + col] = f32_to_bf16((float)z - bf16_to_f32(Zt[row * ldz + col]));
+            else
+              Z[row * ldz + col] = (ZT)z;
+          } else {
             Z[row * ldz + col] = (ZT)z;
+          }
         }
       }
     }
@@ -694,33 +714,16 @@ hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st
   return hipGetLastError();
 }
 
-namespace {
-// dZ = bf16(Zf - Zt) elementwise, four elements a thread (count % 4 == 0).
-__global__ void defect_kernel(const float* __restrict__ Zf, const uint16_t* __restrict__ Zt,
-                              uint16_t* __restrict__ dZ, int64_t count4) {
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < count4;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    const float4 f = reinterpret_cast<const float4*>(Zf)[q];
-    const uint2 t = reinterpret_cast<const uint2*>(Zt)[q];
-    const float d0 = f.x - bf16_to_f32((uint16_t)(t.x & 0xffffu));
-    const float d1 = f.y - bf16_to_f32((uint16_t)(t.x >> 16));
-    const float d2 = f.z - bf16_to_f32((uint16_t)(t.y & 0xffffu));
-    const float d3 = f.w - bf16_to_f32((uint16_t)(t.y >> 16));
-    uint2 o;
-    o.x = (uint32_t)f32_to_bf16(d0) | ((uint32_t)f32_to_bf16(d1) << 16);
-    o.y = (uint32_t)f32_to_bf16(d2) | ((uint32_t)f32_to_bf16(d3) << 16);
-    reinterpret_cast<uint2*>(dZ)[q] = o;
-  }
-}
-}  // namespace
-
-hipError_t feature_defect(const float* Zf, const uint16_t* Zt, uint16_t* dZ, int64_t count,
-                          hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  if (count % 4 != 0 || reinterpret_cast<uintptr_t>(Zf) % 16 != 0 ||
-      reinterpret_cast<uintptr_t>(Zt) % 8 != 0 || reinterpret_cast<uintptr_t>(dZ) % 8 != 0)
-    return hipErrorInvalidValue;
-  defect_kernel<<<grid_1d(count / 4, 256), 256, 0, st>>>(Zf, Zt, dZ, count / 4);
+hipError_t regen_defect(const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
+                        int64_t cols, const void* bias, int64_t Kp, double scale,
+                        const uint16_t* Zt, uint16_t* Zd, int64_t ldz, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  if (!Zt || !Zd) return hipErrorInvalidValue;
+  int64_t tiles = ((rows + BM - 1) / BM) * ((cols + BN - 1) / BN);
+  if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+  regen_kernel<BS_PREC_BF16X3, float><<<dim3((unsigned)tiles), NTHREADS, 0, st>>>(
+      (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,
+      (float)scale, nullptr, ldz, Zt, Zd);
   return hipGetLastError();
 }
 
@@ -735,12 +738,12 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
     case BS_PREC_F64:
       regen_kernel<BS_PREC_F64, double><<<g, NTHREADS, 0, st>>>(
           (const double*)Xp, xps, rows, (const double*)Wt, wps, cols, (const double*)bias, Kp,
-          scale, (double*)Z, ldz);
+          scale, (double*)Z, ldz, nullptr, nullptr);
       break;
     case BS_PREC_F32:
       regen_kernel<BS_PREC_F32, float><<<g, NTHREADS, 0, st>>>(
           (const float*)Xp, xps, rows, (const float*)Wt, wps, cols, (const float*)bias, Kp,
-          (float)scale, (float*)Z, ldz);
+          (float)scale, (float*)Z, ldz, nullptr, nullptr);
       break;
     case BS_PREC_BF16: {
       // wide tiles: the 16-byte row stores of Z need ldz and the base 16-byte
@@ -757,14 +760,14 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
       } else {
         regen_kernel<BS_PREC_BF16, uint16_t><<<g, NTHREADS, 0, st>>>(
             (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias,
-            Kp, (float)scale, (uint16_t*)Z, ldz);
+            Kp, (float)scale, (uint16_t*)Z, ldz, nullptr, nullptr);
       }
       break;
     }
     default:
       regen_kernel<BS_PREC_BF16X3, float><<<g, NTHREADS, 0, st>>>(
           (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,
-          (float)scale, (float*)Z, ldz);
+          (float)scale, (float*)Z, ldz, nullptr, nullptr);
   }
   return hipGetLastError();
 }

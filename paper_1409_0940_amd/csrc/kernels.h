@@ -44,11 +44,12 @@ hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st
 hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
                  int64_t cols, const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
                  hipStream_t st);
-
-// Feature defect of refined BF16: dZ = bf16(Zf - Zt) for count elements
-// (count % 4 == 0; Zf 16-byte, Zt and dZ 8-byte aligned).
-hipError_t feature_defect(const float* Zf, const uint16_t* Zt, uint16_t* dZ, int64_t count,
-                          hipStream_t st);
+// Refined BF16: BF16X3 (FP32-faithful) features of the same block, not
+// stored; their defect bf16(z - Zt) against the BF16 features Zt goes to Zd
+// (both BF16, row stride ldz).
+hipError_t regen_defect(const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
+                        int64_t cols, const void* bias, int64_t Kp, double scale,
+                        const uint16_t* Zt, uint16_t* Zd, int64_t ldz, hipStream_t st);
 
 // The padded feature index: feature block j occupies [coff_j, coff_j + s_j)
 // with coff_j a multiple of 64; spad is the padded total; pad entries are 0.
