@@ -112,7 +112,15 @@ template <int P> constexpr int krow_bytes() {
 // Workgroups per CU the register budget is sized for.
 template <int P> constexpr int regen_wgs() { return P == BS_PREC_F32 ? 4 : 2; }
 
-template <int P, typename ZT>
+// Defect bf16(z - t) of an FP32-faithful feature z against its BF16 value t.
+// z must be the rounded float (as stored): no contraction of the product that
+// formed z with this difference, so both epilogue paths give the same bits.
+__device__ __forceinline__ uint16_t feature_defect_bf16(float z, uint16_t t) {
+#pragma clang fp contract(off)
+  return f32_to_bf16(z - bf16_to_f32(t));
+}
+
+template <int P, typename ZT, bool DEFECT = false>
 __global__ void __launch_bounds__(NTHREADS, regen_wgs<P>())
 regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t rows,
              const typename Prec<P>::op_t* __restrict__ Wt, int64_t wps, int64_t cols,
@@ -283,15 +291,15 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
   // non-temporal stores; straight from the MFMA layout a store instruction
   // writes 64 bytes into each of 4 rows.  The LDS is free once every wave
   // has passed the barrier below (the last chunk's products may follow the
-  // loop's last barrier).  With Zd (FP32-faithful features of refined BF16)
-  // the float values are not stored: the defect bf16(z - Zt) against the
+  // loop's last barrier).  DEFECT (FP32-faithful features of refined BF16):
+  // the float values are not stored; the defect bf16(z - Zt) against the
   // BF16 features Zt of the same elements goes to Zd instead.
   if constexpr (sizeof(ZT) == 4) {
     constexpr int ZP = BN + 4;                     // floats per staged row (528 B)
     static_assert(BM / 2 * ZP * 4 <= (int)sizeof(lds), "half a Z tile fits in the staging LDS");
     if (row0 + BM <= rows && col0 + BN <= cols && ldz % 4 == 0 &&
-        reinterpret_cast<uintptr_t>(Z) % 16 == 0 && reinterpret_cast<uintptr_t>(Zt) % 8 == 0 &&
-        reinterpret_cast<uintptr_t>(Zd) % 8 == 0) {
+        reinterpret_cast<uintptr_t>(DEFECT ? (const void*)Zd : (const void*)Z) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(Zt) % 8 == 0) {
       float* zt = reinterpret_cast<float*>(&lds[0][0][0][0]);
       __syncthreads();
 #pragma unroll
@@ -317,13 +325,13 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
           const int r = ps * RPP + tid / 32, sg = tid % 32;
           const v4f w = *reinterpret_cast<const v4f*>(zt + r * ZP + sg * 4);
           const int64_t off = (row0 + h * (BM / 2) + r) * ldz + col0 + sg * 4;
-          if (Zd) {
+          if constexpr (DEFECT) {
             const uint2 t = *reinterpret_cast<const uint2*>(Zt + off);
             uint2 o;
-            o.x = (uint32_t)f32_to_bf16(w[0] - bf16_to_f32((uint16_t)(t.x & 0xffffu))) |
-                  ((uint32_t)f32_to_bf16(w[1] - bf16_to_f32((uint16_t)(t.x >> 16))) << 16);
-            o.y = (uint32_t)f32_to_bf16(w[2] - bf16_to_f32((uint16_t)(t.y & 0xffffu))) |
-                  ((uint32_t)f32_to_bf16(w[3] - bf16_to_f32((uint16_t)(t.y >> 16))) << 16);
+            o.x = (uint32_t)feature_defect_bf16(w[0], (uint16_t)(t.x & 0xffffu)) |
+                  ((uint32_t)feature_defect_bf16(w[1], (uint16_t)(t.x >> 16)) << 16);
+            o.y = (uint32_t)feature_defect_bf16(w[2], (uint16_t)(t.y & 0xffffu)) |
+                  ((uint32_t)feature_defect_bf16(w[3], (uint16_t)(t.y >> 16)) << 16);
             *reinterpret_cast<uint2*>(Zd + off) = o;
           } else {
             __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(Z + off));
@@ -355,11 +363,8 @@ regen_kernel(const typename Prec<P>::op_t* __restrict__ Xp, int64_t xps, int64_t
             z = scale * rff_cosf(th);
           if constexpr (sizeof(ZT) == 2) {
             Z[row * ldz + col] = f32_to_bf16((float)z);
-          } else if constexpr (sizeof(ZT) == 4) {
-            if (Zd)
-              Zd[row * ldz + col] = f32_to_bf16((float)z - bf16_to_f32(Zt[row * ldz + col]));
-            else
-              Z[row * ldz + col] = (ZT)z;
+          } else if constexpr (DEFECT) {
+            Zd[row * ldz + col] = feature_defect_bf16((float)z, Zt[row * ldz + col]);
           } else {
             Z[row * ldz + col] = (ZT)z;
           }
@@ -721,7 +726,7 @@ hipError_t regen_defect(const void* Xp, int64_t xps, int64_t rows, const void* W
   if (!Zt || !Zd) return hipErrorInvalidValue;
   int64_t tiles = ((rows + BM - 1) / BM) * ((cols + BN - 1) / BN);
   if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-  regen_kernel<BS_PREC_BF16X3, float><<<dim3((unsigned)tiles), NTHREADS, 0, st>>>(
+  regen_kernel<BS_PREC_BF16X3, float, true><<<dim3((unsigned)tiles), NTHREADS, 0, st>>>(
       (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,
       (float)scale, nullptr, ldz, Zt, Zd);
   return hipGetLastError();
