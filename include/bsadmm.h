@@ -138,7 +138,10 @@ enum { BSADMM_L2 = 0 };
  *        every iteration (no regeneration).  Needs n x spad elements of
  *        workspace (spad = sum_j s_j rounded up to 64 per block); setup fails
  *        with ENOMEM if workspace_bytes is set and smaller.  Results equal
- *        STORE bit for bit.                                                 */
+ *        STORE bit for bit.
+ * A workspace element is the stored feature: 8 bytes (FP64), 4 (FP32,
+ * BF16X3), 2 (BF16), 4 for BF16R (the BF16 feature and its defect; the
+ * FP32-faithful features it comes from are never stored).                 */
 enum { BSADMM_Z_AUTO = 0, BSADMM_Z_STORE = 1, BSADMM_Z_KEEP = 2 };
 
 /* -------------------------------------------------------------- problem */
