@@ -179,7 +179,8 @@ typedef struct bsadmm_problem {
   const float* X;   /* device, n x d, caller-owned, must outlive the handle */
   const float* Y;   /* device, n x m, caller-owned, must outlive the handle */
   const float* W;   /* device, d x s feature directions (N(0, 1/sigma^2)),
-                       caller-owned; copied at setup                        */
+                       caller-owned; copied at setup.  NULL together with b:
+                       drawn by the library from `seed` (below)             */
   const float* b;   /* device, s feature offsets (U[0, 2 pi)); copied       */
   void* stream;     /* hipStream_t for every call on the handle             */
   size_t hbm_budget_bytes;  /* 0 = no limit; else setup fails with ENOMEM
@@ -207,6 +208,19 @@ typedef struct bsadmm_problem {
   int32_t refine_every;     /* BF16R: iterations between refinements, >= 0;
                                0 selects 5.  Must be 0 for other precisions */
   int32_t reserved2;        /* 0                                            */
+  /* Feature-map draw when W and b are both NULL (the random draw of the
+   * section on randomized kernel maps, which the paper generates from a
+   * seed rather than storing): with Philox4x32-10 (Salmon, Moraes, Dror and
+   * Shaw, SC 2011) under key (seed mod 2^32, seed / 2^32), the counter
+   * (t mod 2^32, t / 2^32, 0, 0) gives the pair W[2t], W[2t + 1] of the
+   * row-major d x s array: its words (w0, w1, w2, w3) as two uniforms
+   * u = (floor((w_hi 2^32 + w_lo) / 2^11) + 1/2) 2^-53 in (0, 1), u1 from
+   * (w0, w1) and u2 from (w2, w3), then Box-Muller,
+   * sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) / sigma; the counter
+   * (j mod 2^32, j / 2^32, 1, 0) gives b[j] = 2 pi u1 (0 if that rounds to
+   * 2 pi in FP32).  Evaluated in FP64, stored in FP32; bsadmm_get_features
+   * copies the draw out.                                                  */
+  uint64_t seed;
 } bsadmm_problem;
 
 /* Phases timed with HIP events on the handle's stream (bsadmm_stats). */
@@ -388,6 +402,17 @@ enum {
 BSADMM_API int bsadmm_state_size(const bsadmm_handle* h, int32_t which, int64_t* count);
 BSADMM_API int bsadmm_export_state(const bsadmm_handle* h, int32_t which, double* dst);
 BSADMM_API int bsadmm_import_state(bsadmm_handle* h, int32_t which, const double* src);
+
+/* ----------------------------------------------------------------------
+ * bsadmm_get_features -- copy the feature-map draw of a handle set up with
+ * W = b = NULL (the problem's seed) into the caller's device arrays
+ * W (d x s, row-major FP32) and b (s FP32), enqueued on the handle's stream
+ * (no synchronisation).  Passing them back as W and b to another setup
+ * gives the same run.
+ * Errors: EINVAL (null argument; the handle was given W and b), ESTATE,
+ * EDEVICE.
+ * -------------------------------------------------------------------- */
+BSADMM_API int bsadmm_get_features(const bsadmm_handle* h, float* W, float* b);
 
 /* ----------------------------------------------------------------------
  * bsadmm_objective -- F(W) = (1/n) sum_r V(y_r, W^T z(x_r)) + lambda ||W||_F^2

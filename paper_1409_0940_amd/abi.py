@@ -31,6 +31,7 @@ PHASES = ["regen", "ztr", "solve", "zw", "row", "col", "refine"]
 EXPORTED = ["rff_map", "rff_map_noalloc", "bsadmm_validate", "bsadmm_footprint", "bsadmm_setup", "bsadmm_iterate",
             "bsadmm_predict", "bsadmm_get_coef", "bsadmm_state_size", "bsadmm_export_state",
             "bsadmm_import_state", "bsadmm_objective", "bsadmm_monitor", "bsadmm_dual_bound",
+            "bsadmm_get_features",
             "bsadmm_set_rho",
             "bsadmm_destroy", "bsadmm_last_error"]
 
@@ -47,6 +48,7 @@ class BsadmmProblem(ctypes.Structure):
         ("rho_adapt_every", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("rho_adapt_mu", ctypes.c_double), ("rho_adapt_tau", ctypes.c_double),
         ("refine_every", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -92,6 +94,7 @@ def lib():
         L.bsadmm_objective.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.bsadmm_monitor.argtypes = [vp, vp]
         L.bsadmm_dual_bound.argtypes = [vp, vp]
+        L.bsadmm_get_features.argtypes = [vp, vp, vp]
         L.bsadmm_set_rho.argtypes = [vp, ctypes.c_double, i32]
         L.bsadmm_destroy.argtypes = [vp]
         L.bsadmm_last_error.argtypes = []
@@ -172,18 +175,26 @@ def rff_map_noalloc(X, W, b, precision, out, stream=None):
 
 def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
                  stream=None, hbm_budget_bytes=0, workspace_bytes=0, check=True, z_mode="auto",
-                 rho_adapt=None, graph=False, refine_every=0):
+                 rho_adapt=None, graph=False, refine_every=0, s=None, seed=0):
     """bsadmm_problem for device tensors; rho_adapt = (every, mu, tau) or None;
     graph=True sets BSADMM_F_GRAPH (iterations replayed as HIP graphs);
-    refine_every: refinement period of precision "bf16r" (0: the default)."""
+    refine_every: refinement period of precision "bf16r" (0: the default).
+    W = b = None: the library draws the feature map from `seed` (s features)."""
     n, d = X.shape
     m = Y.shape[1]
-    s = W.shape[1]
+    if (W is None) != (b is None):
+        raise ValueError("W and b must both be given or both be None")
+    if W is None:
+        if s is None:
+            raise ValueError("s is needed when W and b are drawn from the seed")
+    else:
+        s = W.shape[1]
     if check:
         _need_cuda_f32("X", X, (n, d))
         _need_cuda_f32("Y", Y, (n, m))
-        _need_cuda_f32("W", W, (d, s))
-        _need_cuda_f32("b", b, (s,))
+        if W is not None:
+            _need_cuda_f32("W", W, (d, s))
+            _need_cuda_f32("b", b, (s,))
     p = BsadmmProblem()
     p.n, p.d, p.m, p.s = n, d, m, s
     p.R, p.C = R, C
@@ -192,7 +203,9 @@ def make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="f
     p.precision = PRECISION[precision] if isinstance(precision, str) else precision
     p.z_mode = Z_MODE[z_mode] if isinstance(z_mode, str) else z_mode
     p.lam, p.rho, p.sigma = lam, rho, sigma
-    p.X, p.Y, p.W, p.b = (_addr(t) for t in (X, Y, W, b))
+    p.X, p.Y = _addr(X), _addr(Y)
+    p.W, p.b = (None, None) if W is None else (_addr(W), _addr(b))
+    p.seed = seed
     p.stream = _stream(stream).value if check else None
     p.hbm_budget_bytes = hbm_budget_bytes
     p.workspace_bytes = workspace_bytes
@@ -289,6 +302,12 @@ def bsadmm_dual_bound(h, out):
     device: D, its conjugate part, its quadratic part)."""
     _check("bsadmm_dual_bound", lib().bsadmm_dual_bound(h, _ptr(out)))
     return out
+
+
+def bsadmm_get_features(h, W, b):
+    """Enqueue a copy of the seeded feature map (W d x s, b s; float32, device)."""
+    _check("bsadmm_get_features", lib().bsadmm_get_features(h, _ptr(W), _ptr(b)))
+    return W, b
 
 
 def bsadmm_set_rho(h, rho, rescale_duals=True):

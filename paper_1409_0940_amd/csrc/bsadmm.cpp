@@ -81,12 +81,12 @@ struct Plan {
          b_colR = 0, b_wop = 0, b_part = 0, b_small = 0, b_fac_tmp = 0, b_prev = 0;
   // refined BF16: feature defects (BF16) and FP32-faithful features of a
   // row-block group, and the stored defects of the two products
-  size_t b_wsd = 0, b_ca = 0, b_cp = 0;
+  size_t b_wsd = 0, b_ca = 0, b_cp = 0, b_feat = 0;
   // operand elements between the W' copies of consecutive row blocks
   int64_t wop_stride() const { return bs::bf16_planes(prec, mp) ? 2 * mp * spad : spad * mp; }
   size_t total() const {
     return b_xp + b_wt + b_bias + b_q + b_ws + 5 * b_row + b_rop + 3 * b_col + 4 * b_colR + b_wop +
-           b_part + b_small + b_fac_tmp + b_prev + b_wsd + b_ca + b_cp;
+           b_part + b_small + b_fac_tmp + b_prev + b_wsd + b_ca + b_cp + b_feat;
   }
 };
 
@@ -118,7 +118,9 @@ int validate(const bsadmm_problem* p) {
     return fail(BSADMM_EINVAL, "rho_adapt_mu must be 0 or finite and > 1");
   if (p->rho_adapt_tau != 0.0 && !(p->rho_adapt_tau > 1.0 && std::isfinite(p->rho_adapt_tau)))
     return fail(BSADMM_EINVAL, "rho_adapt_tau must be 0 or finite and > 1");
-  if (!p->X || !p->Y || !p->W || !p->b) return fail(BSADMM_EINVAL, "X, Y, W, b must be non-NULL");
+  if (!p->X || !p->Y) return fail(BSADMM_EINVAL, "X and Y must be non-NULL");
+  if (!p->W != !p->b)
+    return fail(BSADMM_EINVAL, "W and b must both be given, or both NULL (drawn from seed)");
   const void* ptrs[4] = {p->X, p->Y, p->W, p->b};
   for (const void* q : ptrs)
     if (reinterpret_cast<uintptr_t>(q) % 16 != 0)
@@ -191,6 +193,8 @@ int make_plan(const bsadmm_problem* p, Plan& L) {
   const size_t slot = (size_t)L.S * L.S * 8;
   const size_t fac_cap = (size_t)4 << 30;
   L.fac_batch = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.R * L.C, fac_cap / slot));
+  // a feature map drawn from the seed is kept for bsadmm_get_features
+  L.b_feat = p->W ? 0 : ((size_t)L.d * L.s + (size_t)L.s) * 4 + 256;
   L.b_xp = (size_t)L.n * L.Kp * L.op * L.planes;
   L.b_wt = (size_t)L.s * L.Kp * L.op * L.planes;
   L.b_bias = (size_t)L.s * (L.prec == BSADMM_FP64 ? 8 : 4);
@@ -234,6 +238,7 @@ struct bsadmm_handle {
   void* Zd = nullptr;  // refined BF16: feature defect bf16(Zf - Z) of the workspace rows
   double *cA = nullptr, *cP = nullptr;  // refined BF16: stored product defects
   double* dualA = nullptr;  // refined BF16 dual bound: defect part of Z^T alpha (lazy)
+  float *W_own = nullptr, *b_own = nullptr;  // feature map drawn from the seed (W = b = NULL)
   double *Q = nullptr, *O = nullptr, *Obar = nullptr, *nu = nullptr, *Dbar = nullptr,
          *P = nullptr, *Wbar = nullptr, *mu = nullptr, *Wc = nullptr, *Wp = nullptr,
          *mup = nullptr, *U = nullptr, *rhs = nullptr;
@@ -787,6 +792,17 @@ int do_setup(bsadmm_handle* h) {
     HCHK(hipMemsetAsync(h->cA, 0, L.b_ca, st));
     HCHK(hipMemsetAsync(h->cP, 0, L.b_cp, st));
   }
+  // the feature map from the seed when W = b = NULL (the random draw of the
+  // section on randomized kernel maps), kept for bsadmm_get_features
+  if (!p.W) {
+    void* feat = nullptr;
+    ALLOC(feat, L.b_feat);
+    h->W_own = (float*)feat;
+    h->b_own = h->W_own + ((L.d * L.s + 63) / 64) * 64;
+    HCHK(bs::draw_features(p.seed, L.d, L.s, p.sigma, h->W_own, h->b_own, st));
+    h->p.W = h->W_own;
+    h->p.b = h->b_own;
+  }
   // operands and input checks (refined BF16: BF16 head and residual planes,
   // the head being the BF16 operand)
   const int pprec = L.refine ? BS_PREC_BF16X3 : L.prec;
@@ -1167,6 +1183,19 @@ int bsadmm_dual_bound(bsadmm_handle* h, double* out) {
   const int rc = enqueue_dual_bound(h, loss, out);
   if (rc != BSADMM_OK) h->poisoned = true;
   return rc;
+}
+
+int bsadmm_get_features(const bsadmm_handle* h, float* W, float* b) {
+  g_err.clear();
+  if (!h || !W || !b) return fail(BSADMM_EINVAL, "NULL argument");
+  if (h->poisoned) return fail(BSADMM_ESTATE, "handle poisoned by an earlier device error");
+  if (!h->W_own) return fail(BSADMM_EINVAL, "W and b were given at setup, not drawn from the seed");
+  const Plan& L = h->L;
+  hipError_t e = hipMemcpyAsync(W, h->W_own, (size_t)L.d * L.s * 4, hipMemcpyDeviceToDevice, h->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b, h->b_own, (size_t)L.s * 4, hipMemcpyDeviceToDevice, h->st);
+  if (e != hipSuccess) return hip_fail(e, "get_features");
+  return BSADMM_OK;
 }
 
 int bsadmm_objective(bsadmm_handle* h, const double* Wmodel, double* F) {

@@ -44,6 +44,10 @@ hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st
 hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
                  int64_t cols, const void* bias, int64_t Kp, double scale, void* Z, int64_t ldz,
                  hipStream_t st);
+// Feature-map draw from a seed (Philox4x32-10 and Box-Muller, as documented
+// with bsadmm_problem.seed): W (d x s, N(0, 1/sigma^2)) and b (s, U[0, 2 pi)).
+hipError_t draw_features(uint64_t seed, int64_t d, int64_t s, double sigma, float* W, float* b,
+                         hipStream_t st);
 // Refined BF16: BF16X3 (FP32-faithful) features of the same block, not
 // stored; their defect bf16(z - Zt) against the BF16 features Zt goes to Zd
 // (both BF16, row stride ldz).

@@ -13,18 +13,20 @@ class Solver:
 
     def __init__(self, X, Y, W, b, R, C, lam, rho, sigma, loss="squared", precision="fp32",
                  stream=None, hbm_budget_bytes=0, workspace_bytes=0, z_mode="auto",
-                 rho_adapt=None, graph=False, refine_every=0):
+                 rho_adapt=None, graph=False, refine_every=0, s=None, seed=0):
+        """W = b = None draws the feature map in the library from `seed`
+        (s features); get_features() returns it."""
         self._keep = (X, Y, W, b)
         self.n, self.d = X.shape
         self.m = Y.shape[1]
-        self.s = W.shape[1]
+        self.s = W.shape[1] if W is not None else int(s)
         self.R, self.C = R, C
         self.device = X.device
         self.stream = stream
         self.problem = abi.make_problem(X, Y, W, b, R, C, lam, rho, sigma, loss, precision,
                                         stream, hbm_budget_bytes, workspace_bytes, z_mode=z_mode,
                                         rho_adapt=rho_adapt, graph=graph,
-                                        refine_every=refine_every)
+                                        refine_every=refine_every, s=s, seed=seed)
         self.precision = precision
         self.h = abi.bsadmm_setup(self.problem)
 
@@ -77,6 +79,14 @@ class Solver:
     def monitor_async(self, out):
         """Enqueue [sum V(y, Z W'), mean ||W'_i||^2, sum ||W'_i - W-bar||^2, ||Delta-bar||^2]."""
         return abi.bsadmm_monitor(self.h, out)
+
+    def get_features(self):
+        """(W, b) of a feature map drawn from the seed, as float32 device tensors."""
+        W = torch.empty((self.d, self.s), dtype=torch.float32, device=self.device)
+        b = torch.empty((self.s,), dtype=torch.float32, device=self.device)
+        abi.bsadmm_get_features(self.h, W, b)
+        torch.cuda.synchronize(self.device)
+        return W, b
 
     def dual_bound_async(self, out):
         """Enqueue [D, conjugate part, quadratic part] of the Fenchel lower

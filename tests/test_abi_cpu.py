@@ -212,3 +212,16 @@ def test_noalloc_rejects_oversize_before_any_device_call():
     assert rc == 1
     assert "MiB scratch" in L.bsadmm_last_error().decode()
     assert L.rff_map_noalloc(None, 0, 4, None, None, 4, 1, None, None) == 0   # n = 0: no work
+
+
+def test_seeded_feature_map_validation_and_footprint():
+    """W and b both NULL: valid (drawn from the seed), the footprint grows by
+    the kept draw (d x s + s floats); only one of them NULL is refused."""
+    given = _problem()
+    drawn = _problem(ptrs=(0x10000, 0x20000, 0, 0))
+    assert abi.bsadmm_validate(drawn) == 0
+    extra = abi.bsadmm_footprint(drawn) - abi.bsadmm_footprint(given)
+    assert (16 * 512 + 512) * 4 <= extra <= (16 * 512 + 512) * 4 + 256
+    for ptrs in ((0x10000, 0x20000, 0, 0x40000), (0x10000, 0x20000, 0x30000, 0)):
+        assert abi.bsadmm_validate(_problem(ptrs=ptrs)) == 1
+        assert "both NULL" in pkg.lib().bsadmm_last_error().decode()
