@@ -252,7 +252,8 @@ class GpuExecutor:
     """
 
     def __init__(self, precision="bf16r", max_streams=16, device="cuda:0", setup_workers=4,
-                 z_mode="keep", rho_adapt=None, graph=True, rho=None, certify=True):
+                 z_mode="keep", rho_adapt=None, graph=True, rho=None, certify=True,
+                 refine_every=0):
         import torch
         from concurrent.futures import ThreadPoolExecutor
         self.torch = torch
@@ -264,6 +265,7 @@ class GpuExecutor:
                                           # or None for request_rho
         self.certify = certify            # stop on the dual bound's gap and return W'
         self.dual_after = 1e-3            # objective change that triggers the dual bound
+        self.refine_every = refine_every  # BF16R refinement period (0: the library's default)
         if not certify:
             self.gap = None               # the scheduler then uses its objective-change rule
         self.device = torch.device(device)
@@ -292,8 +294,9 @@ class GpuExecutor:
             mon = torch.zeros(7, dtype=torch.float64, device=self.device)
         rho = (request_rho(r) if self.rho is None
                else self.rho(r) if callable(self.rho) else float(self.rho))
+        kw = {"refine_every": self.refine_every} if self.precision == "bf16r" else {}
         S = Solver(*dev, 1, C, r.lam, rho, r.sigma, _loss(job), self.precision, stream=stream,
-                   z_mode=self.z_mode, rho_adapt=self.rho_adapt, graph=self.graph)
+                   z_mode=self.z_mode, rho_adapt=self.rho_adapt, graph=self.graph, **kw)
         return S, dev, mon
 
     def start(self, job):
@@ -406,14 +409,16 @@ def _request_inputs(r):
 
 def serve_stream(count=256, rate_per_s=20.0, precision="bf16r", budget_gb=160.0, max_active=16,
                  max_iters=300, check_every=10, rtol=2e-6, workers=8, n_range=(2000, 200000),
-                 z_mode="keep", rho_adapt=None, jobs=None, certify=True, gtol=1e-4):
+                 z_mode="keep", rho_adapt=None, jobs=None, certify=True, gtol=1e-4,
+                 refine_every=0):
     """Run the request stream of the serving workload end to end; returns (summary, results)."""
     import workloads as wl
     t = time.perf_counter()
     if jobs is None:   # a caller comparing settings passes the same jobs again
         jobs = make_jobs(wl.serving_stream(count, rate_per_s, n_range=n_range), workers)
     gen_s = time.perf_counter() - t
-    ex = GpuExecutor(precision, max_active, z_mode=z_mode, rho_adapt=rho_adapt, certify=certify)
+    ex = GpuExecutor(precision, max_active, z_mode=z_mode, rho_adapt=rho_adapt, certify=certify,
+                     refine_every=refine_every)
     sch = Scheduler(ex, int(budget_gb * (1 << 30)), max_active, check_every, max_iters, rtol,
                     gtol=gtol)
     t = time.perf_counter()
