@@ -27,7 +27,8 @@ CFLAGS = [
     "-Wno-unused-command-line-argument",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
-SOURCES = ["feature.hip", "products.hip", "factor.hip", "elementwise.hip", "bsadmm.cpp"]
+SOURCES = ["feature.hip", "draw.hip", "products.hip", "factor.hip", "elementwise.hip",
+           "bsadmm.cpp"]
 
 
 def _compile(src: str) -> tuple[str, int, str]:
