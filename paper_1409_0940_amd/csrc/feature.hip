@@ -398,9 +398,10 @@ static_assert(WBM * WZPITCH <= 2 * (WBM + WBN) * WPITCH, "a Z tile fits in the s
 // Raw buffer descriptor over [p, p + bytes): loads past the end return zero.
 // p and bytes are wave-uniform; rebuilding them from readfirstlane halves
 // keeps the descriptor in scalar registers even where their arithmetic was
-// done in vector registers.  wide_load builds it at every call: a descriptor
-// kept live across the k-loop was given vector registers, which wraps each
-// load in a readfirstlane loop (about 90 instructions and 8 branches a chunk).
+// done in vector registers.  A descriptor in vector registers wraps each load
+// in a readfirstlane loop.  The byte counts below take min() of two int64
+// values: HIP's math headers evaluate min() of an int64 and an int in double
+// precision, in vector registers.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t wide_rsrc(const void* p, int64_t bytes) {
   const uint64_t a = reinterpret_cast<uint64_t>(p);
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
@@ -525,16 +526,16 @@ regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
   origin(t, row0, col0);
   const int64_t nchunks = Kp / BK;
   u32x4 sa[WNS], sb[WNS];
-  wide_load(Xp + row0 * Kp, min<int64_t>(rows - row0, WBM) * rowb, Wt + col0 * Kp,
-            min<int64_t>(cols - col0, WBN) * rowb, voff, rowb, 0, sa, sb);
+  wide_load(Xp + row0 * Kp, min(rows - row0, (int64_t)WBM) * rowb, Wt + col0 * Kp,
+            min(cols - col0, (int64_t)WBN) * rowb, voff, rowb, 0, sa, sb);
   wide_store(lds[0], lofs, sa, sb);
   __syncthreads();
 
   for (;;) {
     const void* pa = Xp + row0 * Kp;
-    const int64_t na = min<int64_t>(rows - row0, WBM) * rowb;
+    const int64_t na = min(rows - row0, (int64_t)WBM) * rowb;
     const void* pb = Wt + col0 * Kp;
-    const int64_t nbb = min<int64_t>(cols - col0, WBN) * rowb;
+    const int64_t nbb = min(cols - col0, (int64_t)WBN) * rowb;
     const int tnext = t + wpx;
     const bool has_next = tnext < tend;
     int64_t nrow0 = 0, ncol0 = 0;
@@ -552,8 +553,8 @@ regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
       if (more)
         wide_load(pa, na, pb, nbb, voff, rowb, (int)(c + 1) * WKROW, sa, sb);
       else if (has_next)
-        wide_load(Xp + nrow0 * Kp, min<int64_t>(rows - nrow0, WBM) * rowb, Wt + ncol0 * Kp,
-                  min<int64_t>(cols - ncol0, WBN) * rowb, voff, rowb, 0, sa, sb);
+        wide_load(Xp + nrow0 * Kp, min(rows - nrow0, (int64_t)WBM) * rowb, Wt + ncol0 * Kp,
+                  min(cols - ncol0, (int64_t)WBN) * rowb, voff, rowb, 0, sa, sb);
       wide_mfma(lds[buf], wm, wn, fr, fg, acc);
       if (more) wide_store(lds[buf ^ 1], lofs, sa, sb);
       __syncthreads();
