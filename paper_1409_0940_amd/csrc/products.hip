@@ -477,25 +477,50 @@ gram_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
-  for (int64_t rb = 4 * wave; rb < rows; rb += 16) {
+  // Row steps of 4 rows (lane group fg takes row rb + fg); the loads of the
+  // next GS steps are in flight while the current GS steps' products run.
+  // Rows past the end and features past sj load as zero (the clamped address
+  // is read and discarded).
+  constexpr int GS = 4;
+  const bool fa_ok[4] = {fa < sj, fa + 1 < sj, fa + 2 < sj, fa + 3 < sj};
+  const bool fb_ok[4] = {fb < sj, fb + 1 < sj, fb + 2 < sj, fb + 3 < sj};
+  auto load_step = [&](int64_t rb, acc_t (&a)[4], acc_t (&b)[4]) {
     const int64_t r = rb + fg;
-    acc_t a[4], b[4];
-    if (r < rows) {
-      load_z4<ZT>(Z + r * ldz + coff + fa, a);
-      load_z4<ZT>(Z + r * ldz + coff + fb, b);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[q] = b[q] = 0;
-    }
+    const int64_t rc = r < rows ? r : rows - 1;
+    load_z4<ZT>(Z + rc * ldz + coff + fa, a);
+    load_z4<ZT>(Z + rc * ldz + coff + fb, b);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (fa + q >= sj) a[q] = 0;
-      if (fb + q >= sj) b[q] = 0;
+      if (r >= rows || !fa_ok[q]) a[q] = 0;
+      if (r >= rows || !fb_ok[q]) b[q] = 0;
+    }
+  };
+  acc_t a[GS][4], b[GS][4];
+  int64_t rb = 4 * wave;
+#pragma unroll
+  for (int g = 0; g < GS; ++g) load_step(rb + 16 * g, a[g], b[g]);
+  for (; rb < rows; rb += 16 * GS) {
+    acc_t na[GS][4], nb[GS][4];
+    const bool more = rb + 16 * GS < rows;
+    if (more) {
+#pragma unroll
+      for (int g = 0; g < GS; ++g) load_step(rb + 16 * (GS + g), na[g], nb[g]);
     }
 #pragma unroll
-    for (int qa = 0; qa < 4; ++qa)
+    for (int g = 0; g < GS; ++g)
 #pragma unroll
-      for (int qb = 0; qb < 4; ++qb) acc[qa][qb] = mfma4(a[qa], b[qb], acc[qa][qb]);
+      for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) acc[qa][qb] = mfma4(a[g][qa], b[g][qb], acc[qa][qb]);
+    if (more) {
+#pragma unroll
+      for (int g = 0; g < GS; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a[g][q] = na[g][q];
+          b[g][q] = nb[g][q];
+        }
+    }
   }
   // element (m = acc_row(fg, r), n = fr) of instruction (qa, qb) is
   // G[64 ta + 4 m + qa][64 tb + 4 n + qb]; local index (4 m + qa, 4 n + qb)
