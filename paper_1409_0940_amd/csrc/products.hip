@@ -478,10 +478,12 @@ gram_kernel(const ZT* __restrict__ Z, int64_t ldz, int64_t rows, int64_t coff,
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
   // Row steps of 4 rows (lane group fg takes row rb + fg); the loads of the
-  // next GS steps are in flight while the current GS steps' products run.
+  // next GS steps are in flight while the current GS steps' products run
+  // (FP32 Gram setup of the speech workload: 2, 4, 8 steps 0.286, 0.269,
+  // 0.264 s).
   // Rows past the end and features past sj load as zero (the clamped address
   // is read and discarded).
-  constexpr int GS = 4;
+  constexpr int GS = sizeof(acc_t) == 8 ? 4 : 8;   // FP64: 4 (registers)
   const bool fa_ok[4] = {fa < sj, fa + 1 < sj, fa + 2 < sj, fa + 3 < sj};
   const bool fb_ok[4] = {fb < sj, fb + 1 < sj, fb + 2 < sj, fb + 3 < sj};
   auto load_step = [&](int64_t rb, acc_t (&a)[4], acc_t (&b)[4]) {
