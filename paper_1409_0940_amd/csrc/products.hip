@@ -230,8 +230,17 @@ __global__ void reduce_rhs_kernel(const A* __restrict__ part, int64_t nsplit_max
     const int64_t ni = (int64_t)(i + 1) * n / R - (int64_t)i * n / R;
     const int64_t ns = (ni + split_rows - 1) / split_rows;
     const A* pp = part + (int64_t)i * nsplit_max * per + fc;
+    // the loads of 8 splits go out together; the sum keeps split order
     double a = 0.0;
-    for (int64_t sp = 0; sp < ns; ++sp) a += (double)pp[sp * per];
+    int64_t sp = 0;
+    for (; sp + 8 <= ns; sp += 8) {
+      A v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[(sp + u) * per];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += (double)v[u];
+    }
+    for (; sp < ns; ++sp) a += (double)pp[sp * per];
     const int64_t off = (int64_t)i * per + fc;
     double v = Wbar ? Wbar[fc] - mup[off] + U[off] + a : a;
     if (corr) v += corr[off];
