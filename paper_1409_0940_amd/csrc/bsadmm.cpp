@@ -324,7 +324,7 @@ hipError_t defect_group(bsadmm_handle* h, int i0, int i1, hipStream_t s) {
 struct PhaseTimer {
   bsadmm_handle* h;
   bool on;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks{};
   size_t used = 0;
   hipEvent_t get() {
     if (used == h->evpool.size()) {
