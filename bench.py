@@ -334,7 +334,7 @@ def bench_digits(args, out_cpu):
     return rec, head, variants
 
 
-def bench_ridge(args):
+def bench_ridge(args, out_cpu):
     """FP64 ridge, 100 iterations: launch-bound; eager launches against HIP-graph replay."""
     import torch
     import workloads as wl
@@ -342,6 +342,8 @@ def bench_ridge(args):
     X, Y, Wr, b = wl.make_inputs(w)
     dev = resident((X, Y, Wr, b))
     golden = load_golden("ridge")
+    if not args.no_cpu_baseline:
+        out_cpu["ridge"] = cpu_baseline(w, X, Y, Wr, b)
     E, F_eval = fp64_evaluator(w, dev)
     recs = {}
     for graph in (False, True):
@@ -512,7 +514,7 @@ def main():
     config, head, variants = bench_digits(args, cpu)
     others = {}
     for name in [x for x in args.workloads.split(",") if x]:
-        fn = {"ridge": lambda: bench_ridge(args), "speech": lambda: bench_speech(args, cpu),
+        fn = {"ridge": lambda: bench_ridge(args, cpu), "speech": lambda: bench_speech(args, cpu),
               "digits2m": lambda: bench_digits2m(args, cpu)}[name]
         others[name] = fn()
         if name in cpu:
