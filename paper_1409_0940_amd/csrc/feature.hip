@@ -623,6 +623,193 @@ regen_bf16_wide_kernel(const uint16_t* __restrict__ Xp, int64_t rows,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wide-tile regeneration for split BF16 operands (head h and residual l
+// planes of X and W; phase = h_x h_w + h_x l_w + l_x h_w per 32-value k-step,
+// in that order, as regen_kernel).  A 512-thread workgroup computes a
+// 256 x 256 tile (8 waves of 128 rows x 64 features); each staged chunk is
+// one k-step of the four planes, 1024 rows of 64 bytes (pitch 80), double
+// buffered in all of the 160 KB of LDS, and feeds three products, so a
+// staged byte feeds three times the MFMA work of the one-plane wide kernel.
+// X is the MFMA's M operand, as in regen_kernel, so the bits are regen_kernel's.
+// The FP32 features leave through LDS in two halves of 128 rows as whole
+// 1 KB rows.  Persistent, one workgroup per CU, tiles dealt as in the wide
+// kernel.  (The refinement defect stays with regen_kernel: through this
+// kernel it measured 4.8% slower.)
+// ---------------------------------------------------------------------------
+constexpr int XBM = 256, XBN = 256, XNT = 512, XKROW = 64, XPITCH = XKROW + 16;
+constexpr int XSET = 256 * XPITCH;                // bytes of one staged plane (X or W rows)
+constexpr int XBUF = 4 * XSET;                    // one chunk: X head, X residual, W head, W residual
+constexpr int XNS = 4 * 256 * (XKROW / 16) / XNT; // staged segments per thread (8)
+constexpr int XZP = XBN + 4;                      // floats per staged Z row (1040 B)
+static_assert(2 * XBUF <= 163840, "two chunks fit the LDS");
+static_assert((XBM / 2) * XZP * 4 <= 2 * XBUF, "half a Z tile fits the LDS");
+
+__global__ void __launch_bounds__(XNT, 1)
+regen_bf16x3_wide_kernel(const uint16_t* __restrict__ Xp, int64_t xps, int64_t rows,
+                         const uint16_t* __restrict__ Wt, int64_t wps, int64_t cols,
+                         const float* __restrict__ bias, int64_t Kp, float scale,
+                         float* __restrict__ Z, int64_t ldz) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * XBUF];
+
+  const int tiles_m = (int)((rows + XBM - 1) / XBM);
+  const int tiles_n = (int)((cols + XBN - 1) / XBN);
+  const int T = tiles_m * tiles_n;
+  const int x = (int)(blockIdx.x % 8), wpx = (int)(gridDim.x / 8);
+  const int per = (T + 7) / 8, full = T - (per - 1) * 8;
+  const int tbeg = x < full ? x * per : full * per + (x - full) * (per - 1);
+  const int tend = tbeg + (x < full ? per : per - 1);
+  int t = tbeg + (int)(blockIdx.x / 8);
+  if (t >= tend) return;  // uniform over the workgroup
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;     // 2 x 4 waves
+  const int fr = lane & 15, fg = lane >> 4;
+  // staging: thread tid moves segment tid % 4 of rows tid / 4 and tid / 4 + 128
+  // of each of the four planes
+  const int rowb = (int)(Kp * 2);
+  const int voff = (tid / 4) * rowb + (tid % 4) * 16;
+  const int lofs = (tid / 4) * XPITCH + (tid % 4) * 16;
+  const int per_group = GROUP_M * tiles_n;
+  auto origin = [&](int tt, int64_t& r0, int64_t& c0) {
+    const int g = tt / per_group;
+    const int first_m = g * GROUP_M;
+    const int gsize = min(GROUP_M, tiles_m - first_m);
+    r0 = (int64_t)(first_m + (tt % per_group) % gsize) * XBM;
+    c0 = (int64_t)((tt % per_group) / gsize) * XBN;
+  };
+  auto load = [&](int64_t r0, int64_t c0, int koff, u32x4 (&sg)[XNS]) {
+    const int64_t na = min(rows - r0, (int64_t)XBM) * rowb;
+    const int64_t nb = min(cols - c0, (int64_t)XBN) * rowb;
+    const __amdgpu_buffer_rsrc_t rs[4] = {wide_rsrc(Xp + r0 * Kp, na), wide_rsrc(Xp + xps + r0 * Kp, na),
+                                          wide_rsrc(Wt + c0 * Kp, nb), wide_rsrc(Wt + wps + c0 * Kp, nb)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        sg[2 * q + h] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                      rs[q], voff, h * 128 * rowb + koff, 0));
+  };
+  auto store = [&](unsigned char* buf, const u32x4 (&sg)[XNS]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        *reinterpret_cast<u32x4*>(buf + q * XSET + lofs + h * 128 * XPITCH) = sg[2 * q + h];
+  };
+  using F = Frag<BS_PREC_BF16X3>;
+  auto frag = [&](const unsigned char* buf, int q, int row) {
+    return load_frag<BS_PREC_BF16X3>(
+        reinterpret_cast<const uint16_t*>(buf + q * XSET + row * XPITCH + 16 * fg));
+  };
+
+  int64_t row0, col0;
+  origin(t, row0, col0);
+  const int64_t nchunks = Kp / (XKROW / 2);
+  u32x4 sg[XNS];
+  load(row0, col0, 0, sg);
+  store(lds, sg);
+  __syncthreads();
+
+  for (;;) {
+    const int tnext = t + wpx;
+    const bool has_next = tnext < tend;
+    int64_t nrow0 = 0, ncol0 = 0;
+    if (has_next) origin(tnext, nrow0, ncol0);
+
+    v4f acc[8][4];   // [row tile][feature tile]
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t c = 0; c < nchunks; ++c) {
+      const unsigned char* cur = lds + (c & 1) * XBUF;
+      const bool more = c + 1 < nchunks;
+      if (more) load(row0, col0, (int)(c + 1) * XKROW, sg);
+      else if (has_next) load(nrow0, ncol0, 0, sg);
+      F wh[4], wl[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        wh[j] = frag(cur, 2, wn * 64 + j * 16 + fr);
+        wl[j] = frag(cur, 3, wn * 64 + j * 16 + fr);
+      }
+#pragma unroll
+      for (int qr = 0; qr < 4; ++qr) {   // row tiles 2 qr, 2 qr + 1
+        F xh[2], xl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          xh[i] = frag(cur, 0, wm * 128 + (2 * qr + i) * 16 + fr);
+          xl[i] = frag(cur, 1, wm * 128 + (2 * qr + i) * 16 + fr);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            mfma_step(acc[2 * qr + i][j], xh[i], wh[j]);
+            mfma_step(acc[2 * qr + i][j], xh[i], wl[j]);
+            mfma_step(acc[2 * qr + i][j], xl[i], wh[j]);
+          }
+      }
+      if (more) store(lds + ((c + 1) & 1) * XBUF, sg);
+      __syncthreads();
+    }
+
+    // Epilogue: lane holds rows 4 fg .. 4 fg + 3 of row tile i for feature fr
+    // of feature tile j.
+    const bool fast = row0 + XBM <= rows && col0 + XBN <= cols;
+    if (fast) {
+      float* zt = reinterpret_cast<float*>(lds);
+#pragma unroll 1
+      for (int h = 0; h < 2; ++h) {
+        if (wm == h) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int cl = wn * 64 + j * 16 + fr;
+            const float bcol = bias[col0 + cl];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                zt[(i * 16 + acc_row<float>(fg, r)) * XZP + cl] =
+                    scale * rff_cosf(acc[i][j][r] + bcol);
+          }
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int ps = 0; ps < (XBM / 2) / (XNT / 64); ++ps) {
+          const int r = ps * (XNT / 64) + tid / 64, sgi = tid % 64;
+          const v4f w = *reinterpret_cast<const v4f*>(zt + r * XZP + sgi * 4);
+          const int64_t off = (row0 + h * (XBM / 2) + r) * ldz + col0 + sgi * 4;
+          __builtin_nontemporal_store(w, reinterpret_cast<v4f*>(Z + off));
+        }
+        __syncthreads();   // the LDS: the next half, or the next tile's first chunk
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = col0 + wn * 64 + j * 16 + fr;
+        const bool cok = col < cols;
+        const float bcol = cok ? bias[col] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t row = row0 + wm * 128 + i * 16 + acc_row<float>(fg, r);
+            if (cok && row < rows) Z[row * ldz + col] = scale * rff_cosf(acc[i][j][r] + bcol);
+          }
+      }
+    }
+    if (!has_next) break;
+    // every wave passed the last barrier: no one reads LDS any more
+    store(lds, sg);
+    __syncthreads();
+    t = tnext;
+    row0 = nrow0;
+    col0 = ncol0;
+  }
+}
+
 // Compute units of the current device (queried once per device).
 int cu_count() {
   static int cached[64] = {0};
@@ -720,6 +907,27 @@ hipError_t check_finite(const float* p, int64_t count, int* flag, hipStream_t st
   return hipGetLastError();
 }
 
+namespace {
+
+// Split-operand regeneration on wide tiles where its 16-byte row stores and
+// 32-bit staging offsets allow; false where regen_kernel must run instead
+// (same bits either way).
+bool regen_bf16x3_wide(const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
+                       int64_t cols, const void* bias, int64_t Kp, double scale, float* Z,
+                       int64_t ldz, hipStream_t st) {
+  const int64_t wt = ((rows + XBM - 1) / XBM) * ((cols + XBN - 1) / XBN);
+  if (ldz % 4 != 0 || reinterpret_cast<uintptr_t>(Z) % 16 != 0 || wt > 0x7fffffff ||
+      Kp % (XKROW / 2) != 0 || Kp > ((int64_t)1 << 21))
+    return false;
+  const int64_t nwg = std::min<int64_t>(std::max(8, cu_count() / 8 * 8), (wt + 7) / 8 * 8);
+  regen_bf16x3_wide_kernel<<<dim3((unsigned)nwg), XNT, 0, st>>>(
+      (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,
+      (float)scale, Z, ldz);
+  return true;
+}
+
+}  // namespace
+
 hipError_t regen_defect(const void* Xp, int64_t xps, int64_t rows, const void* Wt, int64_t wps,
                         int64_t cols, const void* bias, int64_t Kp, double scale,
                         const uint16_t* Zt, uint16_t* Zd, int64_t ldz, hipStream_t st) {
@@ -771,6 +979,8 @@ hipError_t regen(int prec, const void* Xp, int64_t xps, int64_t rows, const void
       break;
     }
     default:
+      if (regen_bf16x3_wide(Xp, xps, rows, Wt, wps, cols, bias, Kp, scale, (float*)Z, ldz, st))
+        break;
       regen_kernel<BS_PREC_BF16X3, float><<<g, NTHREADS, 0, st>>>(
           (const uint16_t*)Xp, xps, rows, (const uint16_t*)Wt, wps, cols, (const float*)bias, Kp,
           (float)scale, (float*)Z, ldz, nullptr, nullptr);
