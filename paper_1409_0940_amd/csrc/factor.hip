@@ -139,16 +139,24 @@ potrf_diag_kernel(double* __restrict__ slots, int64_t S, int kb, double* __restr
     }
     __syncthreads();
   }
-  // Li = L^{-1}, one column per thread (forward substitution)
+  // Li = L^{-1}, one column per thread of wave 0 (forward substitution), the
+  // column in registers: the loops are unrolled over all rows, so that no
+  // product waits for a value the same lane has just written to LDS.  Terms
+  // k < c multiply a zero entry and leave the +0 sum at +0, so the sums and
+  // the bits are those of the substitution that starts at k = c.
   if (tid < NB) {
     const int c = tid;
-    for (int i = 0; i < c; ++i) Li[i][c] = 0.0;
-    Li[c][c] = 1.0 / L[c][c];
-    for (int i = c + 1; i < NB; ++i) {
+    double li[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
       double acc = 0.0;
-      for (int k = c; k < i; ++k) acc += L[i][k] * Li[k][c];
-      Li[i][c] = -acc / L[i][i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc += L[i][k] * li[k];
+      const double diag = L[i][i];
+      li[i] = i < c ? 0.0 : (i == c ? 1.0 / diag : -acc / diag);
     }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Li[i][c] = li[i];
   }
   __syncthreads();
   double* D = dinv + (int64_t)blockIdx.x * S * NB + (int64_t)kb * NB * NB;
